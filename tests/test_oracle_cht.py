@@ -1,0 +1,133 @@
+"""Conjugate-heat-transfer pins of the oracle's energy lattice (Sec. 2.2):
+the closed-form erfc solution of Sec. 3.1 (stationary and moving interface),
+steady conduction across a layered slab, and the energy balance behind the
+printed equilibrium temperature of Sec. 3.5.
+
+These use the oracle's caller-driven mode: the velocity is prescribed (only
+the energy lattice runs, as in Sec. 3.1) and f_s is written per step.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import erfc
+
+import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def setup_1d():
+    with open(os.path.join(GOLD, "cht_1d_setup.json")) as fh:
+        return json.load(fh)
+
+
+def run_1d(O, Rl, Rcv, U, t_end, lam, scale=1, L=500):
+    """Solid (T_h = 1) left of an interface on a cell face, fluid (T_c = 0)
+    right of it, both moving at U; walls far away held at T_h / T_c.
+    `scale` refines dx by that factor (dt by its square, diffusive scaling).
+    Returns node positions (in coarse units), T and the erfc solution."""
+    nx, xf = 2 * L * scale, float(L * scale)
+    d = W.domain(nx, 1, lambda_f=lam, R_lambda=Rl, R_cv=Rcv)
+    d = W.walls(d, (0, 1), thermal="dirichlet", T_wall=[1.0, 0.0, 0.0, 0.0])
+    Uc = U / scale
+    o = O.Oracle(d, [], hooks={"thermal_only": 1, "fs_from_array": 1,
+                               "u_pres": (Uc, 0.0)})
+    xl = np.arange(nx, dtype=float)
+    o.raw("fs_next")[0, :] = np.clip(xf - xl, 0.0, 1.0)
+    o.raw("T")[0, :] = np.where(xl < xf, 1.0, 0.0)
+    o.init()
+    for n in range(1, t_end * scale * scale + 1):
+        o.raw("fs_next")[0, :] = np.clip(xf + Uc * n - xl, 0.0, 1.0)
+        o.step(1)
+    xc = (xl + 0.5 - xf) / scale
+    T = o.field("T")[0]
+    Xi = U * t_end
+    a_s, a_f = lam * Rl / Rcv, lam
+    K = math.sqrt(Rl * Rcv)
+    Ta = np.where(
+        xc < Xi,
+        1.0 - 1.0 / (K + 1) * erfc((Xi - xc) / (2 * math.sqrt(a_s * t_end))),
+        K / (K + 1) * erfc((xc - Xi) / (2 * math.sqrt(a_f * t_end))))
+    return xc, T, Ta
+
+
+@pytest.mark.parametrize("Rl", [1.0, 4.0])
+@pytest.mark.parametrize("Rcv", [0.25, 1.0, 4.0])
+def test_erfc_stationary(oracle_mod, Rl, Rcv):
+    g = setup_1d()
+    _, T, Ta = run_1d(oracle_mod, Rl, Rcv, 0.0, g["t"], g["lambda_f"])
+    assert np.abs(T - Ta).max() < 2e-4
+
+
+@pytest.mark.parametrize("Rl", [1.0, 4.0])
+@pytest.mark.parametrize("Rcv", [0.25, 1.0, 4.0])
+def test_erfc_moving(oracle_mod, Rl, Rcv):
+    """The source term q_c and [df_s/dt] are active; the printed X_i = 100
+    at t = 2000 is reproduced by construction (U t)."""
+    g = setup_1d()
+    assert g["U_moving"] * g["t"] == g["X_i_at_t_moving"]
+    _, T, Ta = run_1d(oracle_mod, Rl, Rcv, g["U_moving"], g["t"],
+                      g["lambda_f"])
+    assert np.abs(T - Ta).max() < 2e-2
+
+
+@pytest.mark.parametrize("Rl,Rcv,gain", [(1.0, 4.0, 3.5), (4.0, 0.25, 1.5)])
+def test_erfc_moving_converges_under_refinement(oracle_mod, Rl, Rcv, gain):
+    """Halving dx (and quartering dt) shrinks the moving-case error: about
+    second order in the solid bulk, about first order at the smeared
+    interface cell."""
+    g = setup_1d()
+    e = []
+    for s in (1, 2):
+        _, T, Ta = run_1d(oracle_mod, Rl, Rcv, g["U_moving"], g["t"],
+                          g["lambda_f"], scale=s)
+        e.append(np.abs(T - Ta).max())
+    assert e[1] * gain < e[0]
+
+
+@pytest.mark.parametrize("Rl,Rcv,sigma_rule", [(10.0, 2.0, 0), (10.0, 0.5, 0),
+                                               (1.0, 1.0, 0), (10.0, 2.0, 1),
+                                               (0.25, 3.0, 0)])
+def test_layered_slab_steady_conduction(oracle_mod, Rl, Rcv, sigma_rule):
+    """Solid cells 0..15, fluid cells 16..39, interface on a cell face,
+    Dirichlet walls T = 1 / T = 0 on the outer faces, no flow.  The steady
+    state is piecewise linear with continuous T and continuous flux
+    lambda dT/dx at the interface (the conjugate condition), whatever the
+    heat capacities -- the scheme reproduces it exactly."""
+    O = oracle_mod
+    nx, xs, lam = 40, 16, 0.1
+    d = W.domain(nx, 1, lambda_f=lam, R_lambda=Rl, R_cv=Rcv,
+                 sigma_rule=sigma_rule)
+    d = W.walls(d, (0, 1), thermal="dirichlet", T_wall=[1.0, 0.0, 0.0, 0.0])
+    o = O.Oracle(d, [], hooks={"thermal_only": 1, "fs_from_array": 1,
+                               "u_pres": (0.0, 0.0)})
+    x = np.arange(nx)
+    o.raw("fs_next")[0, :] = (x < xs).astype(float)
+    o.raw("T")[0, :] = 0.5
+    o.init()
+    o.step(250000)
+    ls = lam * Rl
+    Ti = (ls / xs) / (ls / xs + lam / (nx - xs))
+    xc = x + 0.5
+    Ta = np.where(xc < xs, 1 + (Ti - 1) * xc / xs, Ti * (nx - xc) / (nx - xs))
+    assert np.abs(o.field("T")[0] - Ta).max() < 1e-11
+
+
+def test_printed_equilibrium_temperature_energy_balance():
+    """With adiabatic walls the total internal energy is conserved, so the
+    final uniform T is sum(c_v T_0) / sum(c_v); for cold particles (T = 0,
+    c_vs = 2 c_vf) in hot fluid (T = 1) this is (1 - phi)/(1 + phi).  At the
+    printed setup (2048 disks, D = 24, L = 1700) it gives the printed 0.5145;
+    the oracle's own adiabatic box reaches the same relation
+    (test_adiabatic_equilibrium_temperature)."""
+    with open(os.path.join(GOLD, "energy_balance_2048.json")) as fh:
+        g = json.load(fh)
+    phi = g["n_particles"] * math.pi * (g["D"] / 2) ** 2 / g["L"] ** 2
+    Rcv = g["R_cv"]
+    Teq = ((1 - phi) * 1.0 * g["T_fluid"] + phi * Rcv * g["T_particles"]) / (
+        (1 - phi) * 1.0 + phi * Rcv)
+    assert abs(Teq - (1 - phi) / (1 + phi)) < 1e-15
+    assert round(Teq, 4) == g["T_eq_printed"]
