@@ -1,0 +1,665 @@
+// vlb_api.hip -- host implementation of the C ABI declared in include/vlb.h.
+// Owns the device memory of a context, derives the kernel constants from the
+// descriptor, and sequences the kernels of each time step on the context's
+// stream.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "vlb_internal.h"
+
+using namespace vlb;
+
+struct vlb_ctx {
+  vlb_domain_desc d;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Params P;
+  int prec = 0;
+  size_t plane = 0, pop_elem = 0, h_elem = 0;
+  void* f[2] = {nullptr, nullptr};
+  void* g[2] = {nullptr, nullptr};
+  void* h = nullptr;
+  int cur = 0;
+  double* macro = nullptr;
+  int* blk_cnt = nullptr;
+  int2* blk_ent = nullptr;
+  // particles
+  int np = 0;
+  int maxb = 0;
+  double* pmem[2] = {nullptr, nullptr};
+  int* pslot[2] = {nullptr, nullptr};
+  PState ps[2];
+  int pcur = 0;
+  double* pconst = nullptr;
+  int* pfixed = nullptr;
+  PConst pc;
+  double* partial = nullptr;
+  double* thermal4 = nullptr;
+  std::vector<vlb_particle_desc> parts;
+  // status
+  int* flags = nullptr;
+  int* flags_host = nullptr;
+  int have_partials = 0;
+  int64_t step = 0;
+  bool initialized = false;
+  size_t dev_bytes = 0;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  std::string err;
+};
+
+static std::string g_create_error;
+
+static const double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+static const int kEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+static vlb_status fail(vlb_ctx* c, vlb_status s, const std::string& msg) {
+  if (c) c->err = msg; else g_create_error = msg;
+  return s;
+}
+
+static vlb_status hip_fail(vlb_ctx* c, hipError_t e, const char* where) {
+  return fail(c, VLB_EHIP,
+              std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr); \
+  } while (0)
+
+static bool dalloc(vlb_ctx* c, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    return false;
+  }
+  c->dev_bytes += bytes;
+  return true;
+}
+
+static void free_particles(vlb_ctx* c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c->pmem[k]) (void)hipFree(c->pmem[k]);
+    if (c->pslot[k]) (void)hipFree(c->pslot[k]);
+    c->pmem[k] = nullptr;
+    c->pslot[k] = nullptr;
+  }
+  if (c->pconst) (void)hipFree(c->pconst);
+  if (c->pfixed) (void)hipFree(c->pfixed);
+  if (c->partial) (void)hipFree(c->partial);
+  if (c->thermal4) (void)hipFree(c->thermal4);
+  c->pconst = nullptr;
+  c->pfixed = nullptr;
+  c->partial = nullptr;
+  c->thermal4 = nullptr;
+}
+
+static vlb_status validate(const vlb_domain_desc* d, std::string& why) {
+  if (d->nx < 1 || d->ny < 1) return why = "nx and ny must be >= 1", VLB_EINVAL;
+  if ((int64_t)d->nx * d->ny * 9 >= ((int64_t)1 << 31))
+    return why = "domain too large (9 nx ny must fit in int32)", VLB_EINVAL;
+  for (int a = 0; a < 2; ++a) {
+    int f0 = d->face_flow[2 * a], f1 = d->face_flow[2 * a + 1];
+    if ((f0 != VLB_PERIODIC && f0 != VLB_WALL) ||
+        (f1 != VLB_PERIODIC && f1 != VLB_WALL))
+      return why = "face_flow must be VLB_PERIODIC or VLB_WALL", VLB_EINVAL;
+    if ((f0 == VLB_PERIODIC) != (f1 == VLB_PERIODIC))
+      return why = "periodic faces must come in pairs", VLB_EINVAL;
+  }
+  for (int k = 0; k < 4; ++k)
+    if (d->face_thermal[k] != VLB_ADIABATIC &&
+        d->face_thermal[k] != VLB_DIRICHLET)
+      return why = "face_thermal must be VLB_ADIABATIC or VLB_DIRICHLET",
+             VLB_EINVAL;
+  if (!(d->tau_f > 0.5)) return why = "tau_f must exceed 1/2", VLB_EINVAL;
+  if (!(d->rho_f > 0) || !(d->cv_f > 0) || !(d->lambda_f > 0) ||
+      !(d->R_lambda > 0) || !(d->R_cv > 0) || !(d->init_rho > 0))
+    return why = "densities, heat capacities and conductivities must be > 0",
+           VLB_EINVAL;
+  if (d->sigma_rule != 0 && d->sigma_rule != 1)
+    return why = "sigma_rule must be 0 or 1", VLB_EINVAL;
+  if (d->kmax < 1 || d->kmax > 8) return why = "kmax must be in 1..8", VLB_EINVAL;
+  if (d->precision < VLB_FP64 || d->precision > VLB_BF16_SHIFT)
+    return why = "unknown precision", VLB_EINVAL;
+  if (d->coll_range < 0) return why = "coll_range must be >= 0", VLB_EINVAL;
+  return VLB_OK;
+}
+
+static void derive_params(vlb_ctx* c) {
+  const vlb_domain_desc& d = c->d;
+  Params& P = c->P;
+  memset(&P, 0, sizeof(P));
+  P.nx = d.nx;
+  P.ny = d.ny;
+  P.N = d.nx * d.ny;
+  P.nblocks = (P.N + kBlock - 1) / kBlock;
+  P.perx = d.face_flow[VLB_FACE_XLO] == VLB_PERIODIC;
+  P.pery = d.face_flow[VLB_FACE_YLO] == VLB_PERIODIC;
+  P.kmax = d.kmax;
+  P.sigma_rule = d.sigma_rule;
+  // flow relaxation (Sec. 3): s_e = s_eps = 1.25, s_p = 1/tau_f,
+  // (1/s_p - 1/2)(1/s_q - 1/2) = 1/12
+  P.s_e = 1.25;
+  P.s_p = 1.0 / d.tau_f;
+  P.s_q = 1.0 / (0.5 + (1.0 / 12.0) / (d.tau_f - 0.5));
+  P.cvf = d.cv_f;
+  P.cvs = d.R_cv * d.cv_f;
+  P.dcv = P.cvs - P.cvf;
+  P.lamf = d.lambda_f;
+  P.dlam = d.R_lambda * d.lambda_f - d.lambda_f;
+  P.cref = 2.0 * P.cvf * P.cvs / (P.cvf + P.cvs);
+  // eq. lambda with alpha1 = -2: lambda/rho_f = c_ref (tau_g - 1/2)/3
+  P.taug_coef = 3.0 / (d.rho_f * P.cref);
+  // fluid force (1 - f_s)[F_ext - rho_f g beta (T - T_ref)] = (1-f_s)(A0 + B0 T)
+  P.A0x = d.body_force[0] + d.rho_f * d.beta * d.T_ref * d.gravity[0];
+  P.A0y = d.body_force[1] + d.rho_f * d.beta * d.T_ref * d.gravity[1];
+  P.B0x = -d.rho_f * d.beta * d.gravity[0];
+  P.B0y = -d.rho_f * d.beta * d.gravity[1];
+  P.init_rho = d.init_rho;
+  P.init_ux = d.init_u[0];
+  P.init_uy = d.init_u[1];
+  P.init_T = d.init_T;
+  for (int w = 0; w < 4; ++w) {
+    const bool dir = d.face_thermal[w] == VLB_DIRICHLET;
+    P.gsign[w] = dir ? -1.0 : 1.0;
+    for (int q = 0; q < 9; ++q) {
+      const double eu = kEx[q] * d.u_wall[w][0] + kEy[q] * d.u_wall[w][1];
+      P.fadd[w][q] = 6.0 * kW[q] * d.init_rho * eu;
+      P.gadd[w][q] = dir ? 2.0 * kW[q] * P.cref * d.T_wall[w] : 0.0;
+    }
+    P.wall_face[w] = d.face_flow[w] == VLB_WALL;
+  }
+  const bool shifted =
+      d.precision == VLB_FP16_SHIFT || d.precision == VLB_BF16_SHIFT;
+  for (int q = 0; q < 9; ++q) {
+    P.fshift[q] = shifted ? kW[q] * d.shift_rho0 : 0.0;
+    P.gshift[q] = shifted ? kW[q] * P.cref * d.shift_T0 : 0.0;
+  }
+  P.rho_f = d.rho_f;
+  P.grav_x = d.gravity[0];
+  P.grav_y = d.gravity[1];
+  P.coll_range = d.coll_range;
+  P.coll_pp = d.coll_stiff_pp;
+  P.coll_pw = d.coll_stiff_pw;
+  P.np = 0;
+  P.maxb = 0;
+}
+
+extern "C" {
+
+vlb_status vlb_create(const vlb_domain_desc* desc, void* hip_stream,
+                      vlb_ctx** out) {
+  if (!desc || !out) return fail(nullptr, VLB_EINVAL, "null argument");
+  *out = nullptr;
+  std::string why;
+  vlb_status st = validate(desc, why);
+  if (st != VLB_OK) return fail(nullptr, st, why);
+  vlb_ctx* c = new (std::nothrow) vlb_ctx();
+  if (!c) return fail(nullptr, VLB_ENOMEM, "host allocation failed");
+  c->d = *desc;
+  c->stream = (hipStream_t)hip_stream;
+  (void)hipGetDevice(&c->device);
+  c->prec = desc->precision;
+  derive_params(c);
+  const size_t N = (size_t)c->P.N;
+  c->plane = (N + 63) / 64 * 64;  // 256/512-byte aligned planes
+  c->pop_elem = c->prec == VLB_FP64 ? 8 : (c->prec == VLB_FP32 ? 4 : 2);
+  c->h_elem = c->prec == VLB_FP64 ? 8 : 4;
+  bool ok = true;
+  for (int k = 0; k < 2; ++k) {
+    ok = ok && dalloc(c, &c->f[k], 9 * c->plane * c->pop_elem);
+    ok = ok && dalloc(c, &c->g[k], 9 * c->plane * c->pop_elem);
+  }
+  ok = ok && dalloc(c, &c->h, N * c->h_elem);
+  ok = ok && dalloc(c, (void**)&c->macro, 6 * N * sizeof(double));
+  ok = ok && dalloc(c, (void**)&c->blk_cnt, c->P.nblocks * sizeof(int));
+  ok = ok && dalloc(c, (void**)&c->blk_ent,
+                    (size_t)c->P.nblocks * kListCap * sizeof(int2));
+  ok = ok && dalloc(c, (void**)&c->flags, 4 * sizeof(int));
+  if (ok && hipHostMalloc((void**)&c->flags_host, 4 * sizeof(int),
+                          hipHostMallocDefault) != hipSuccess)
+    ok = false;
+  if (!ok) {
+    vlb_destroy(c);
+    return fail(nullptr, VLB_ENOMEM, "device allocation failed");
+  }
+  if (hipMemsetAsync(c->blk_cnt, 0, c->P.nblocks * sizeof(int), c->stream) !=
+          hipSuccess ||
+      hipMemsetAsync(c->flags, 0, 4 * sizeof(int), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    vlb_destroy(c);
+    return fail(nullptr, VLB_EHIP, "initial clear failed");
+  }
+  *out = c;
+  return VLB_OK;
+}
+
+vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
+                             const vlb_particle_desc* p) {
+  if (!c) return VLB_EINVAL;
+  if (n < 0 || (n > 0 && !p)) return fail(c, VLB_EINVAL, "bad particle array");
+  double rmax = 0.0;
+  for (int k = 0; k < n; ++k) {
+    if (!(p[k].radius > 0.0) || p[k].radius > kMaxRadius)
+      return fail(c, VLB_EINVAL, "particle radius must be in (0, 28]");
+    if (!(p[k].rho_s > 0.0))
+      return fail(c, VLB_EINVAL, "particle density must be > 0");
+    if (c->P.perx && !(c->d.nx > 2.0 * p[k].radius + 4.0))
+      return fail(c, VLB_EINVAL, "particle wider than the periodic x axis");
+    if (c->P.pery && !(c->d.ny > 2.0 * p[k].radius + 4.0))
+      return fail(c, VLB_EINVAL, "particle wider than the periodic y axis");
+    if (!(p[k].x >= 0.0 && p[k].x < c->d.nx && p[k].y >= 0.0 &&
+          p[k].y < c->d.ny))
+      return fail(c, VLB_EINVAL, "particle centre must lie in the domain");
+    rmax = fmax(rmax, p[k].radius);
+  }
+  free_particles(c);
+  c->parts.assign(p, p + n);
+  c->np = n;
+  // band rows of a particle <= 2R + 4; each row touches <= 4 blocks
+  c->maxb = 4 * (2 * (int)ceil(rmax) + 5);
+  c->P.np = n;
+  c->P.maxb = c->maxb;
+  c->initialized = false;
+  if (n == 0) return VLB_OK;
+  bool ok = true;
+  for (int k = 0; k < 2; ++k) {
+    ok = ok && dalloc(c, (void**)&c->pmem[k], 12 * (size_t)n * sizeof(double));
+    ok = ok && dalloc(c, (void**)&c->pslot[k], (size_t)n * sizeof(int));
+  }
+  ok = ok && dalloc(c, (void**)&c->pconst, 3 * (size_t)n * sizeof(double));
+  ok = ok && dalloc(c, (void**)&c->pfixed, (size_t)n * sizeof(int));
+  ok = ok && dalloc(c, (void**)&c->partial,
+                    (size_t)n * c->maxb * kRedVals * sizeof(double));
+  ok = ok && dalloc(c, (void**)&c->thermal4, 4 * (size_t)n * sizeof(double));
+  if (!ok) {
+    free_particles(c);
+    c->np = 0;
+    c->P.np = 0;
+    return fail(c, VLB_ENOMEM, "particle allocation failed");
+  }
+  for (int k = 0; k < 2; ++k) {
+    double* b = c->pmem[k];
+    PState& s = c->ps[k];
+    s.X = b; s.Y = b + n; s.th = b + 2 * n; s.Ux = b + 3 * n; s.Uy = b + 4 * n;
+    s.Om = b + 5 * n; s.Uxp = b + 6 * n; s.Uyp = b + 7 * n; s.Omp = b + 8 * n;
+    s.Fx = b + 9 * n; s.Fy = b + 10 * n; s.Tz = b + 11 * n;
+    s.nslot = c->pslot[k];
+  }
+  c->pc.R = c->pconst;
+  c->pc.rhos = c->pconst + n;
+  c->pc.Tinit = c->pconst + 2 * n;
+  c->pc.fixed = c->pfixed;
+  return VLB_OK;
+}
+
+static Lists lists(vlb_ctx* c) {
+  Lists L;
+  L.cnt = c->blk_cnt;
+  L.ent = c->blk_ent;
+  return L;
+}
+
+static vlb_status check_flags(vlb_ctx* c) {
+  HIP_TRY(c, hipMemcpyAsync(c->flags_host, c->flags, sizeof(int),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int f = c->flags_host[0];
+  if (f & kFlagUnstable)
+    return fail(c, VLB_EUNSTABLE, "a cell reached rho <= 0 or a non-finite value");
+  if (f & kFlagListFull)
+    return fail(c, VLB_EOVERLAP, "a per-block particle list overflowed");
+  if (f & kFlagOverlap)
+    return fail(c, VLB_EOVERLAP, "more than kmax particles touch one cell");
+  return VLB_OK;
+}
+
+vlb_status vlb_init(vlb_ctx* c) {
+  if (!c) return VLB_EINVAL;
+  const int n = c->np;
+  c->pcur = 0;
+  c->cur = 0;
+  c->have_partials = 0;
+  c->step = 0;
+  if (n > 0) {
+    std::vector<double> host(12 * (size_t)n, 0.0), cst(3 * (size_t)n);
+    std::vector<int> fx(n);
+    for (int k = 0; k < n; ++k) {
+      const vlb_particle_desc& p = c->parts[k];
+      host[k] = p.x;
+      host[n + k] = p.y;
+      host[2 * n + k] = p.theta;
+      host[3 * n + k] = p.ux;
+      host[4 * n + k] = p.uy;
+      host[5 * n + k] = p.omega;
+      host[6 * n + k] = p.ux;   // previous-step velocity: U^{-1} = U^0
+      host[7 * n + k] = p.uy;
+      host[8 * n + k] = p.omega;
+      cst[k] = p.radius;
+      cst[n + k] = p.rho_s;
+      cst[2 * n + k] = p.T_init;
+      fx[k] = p.fixed ? 1 : 0;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->pmem[0], host.data(), host.size() * 8,
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->pconst, cst.data(), cst.size() * 8,
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->pfixed, fx.data(), fx.size() * 4,
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->pslot[0], 0, n * sizeof(int), c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->pslot[1], 0, n * sizeof(int), c->stream));
+    // the copies read pageable host vectors: finish before they go away
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  HIP_TRY(c, hipMemsetAsync(c->blk_cnt, 0, c->P.nblocks * sizeof(int), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->flags, 0, 4 * sizeof(int), c->stream));
+  HIP_TRY(c, launch_particles(c->P, c->ps[0], c->ps[1], c->pc, lists(c),
+                              c->partial, 0, kModeBinOnly, c->flags, c->stream));
+  HIP_TRY(c, launch_init(c->prec, c->P, c->f[0], c->g[0], c->h, c->plane,
+                         c->ps[0], c->pc, lists(c), c->macro, c->flags,
+                         c->stream));
+  vlb_status st = check_flags(c);
+  c->initialized = (st == VLB_OK);
+  return st;
+}
+
+static vlb_status one_step(vlb_ctx* c, bool last) {
+  PState cur = c->ps[c->pcur], nxt = c->ps[1 - c->pcur];
+  HIP_TRY(c, launch_particles(c->P, cur, nxt, c->pc, lists(c), c->partial,
+                              c->have_partials, kModeUpdate, c->flags,
+                              c->stream));
+  const bool timed = c->timing;
+  if (timed) {
+    if (c->ev_used + 2 > c->ev.size()) {
+      for (int k = 0; k < 64; ++k) {
+        hipEvent_t e;
+        HIP_TRY(c, hipEventCreate(&e));
+        c->ev.push_back(e);
+      }
+    }
+    HIP_TRY(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+  }
+  HIP_TRY(c, launch_lattice(c->prec, last, c->P, c->f[c->cur],
+                            c->f[1 - c->cur], c->g[c->cur], c->g[1 - c->cur],
+                            c->h, c->plane, c->np ? nxt : cur, c->pc, lists(c),
+                            c->partial, c->macro, c->flags, c->stream));
+  if (timed) {
+    HIP_TRY(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+    c->ev_used += 2;
+  }
+  if (c->np > 0) {
+    c->have_partials = 1;
+    c->pcur ^= 1;
+  }
+  c->cur ^= 1;
+  c->step++;
+  return VLB_OK;
+}
+
+vlb_status vlb_step(vlb_ctx* c, int64_t nsteps) {
+  if (!c) return VLB_EINVAL;
+  if (nsteps < 0) return fail(c, VLB_EINVAL, "nsteps must be >= 0");
+  if (!c->initialized) return fail(c, VLB_ESTATE, "vlb_init has not succeeded");
+  for (int64_t k = 0; k < nsteps; ++k) {
+    vlb_status st = one_step(c, k == nsteps - 1);
+    if (st != VLB_OK) return st;
+  }
+  vlb_status st = check_flags(c);
+  if (st != VLB_OK) c->initialized = false;
+  return st;
+}
+
+vlb_status vlb_read_field(vlb_ctx* c, int32_t field, double* dst,
+                          int32_t dst_is_device) {
+  if (!c || !dst) return VLB_EINVAL;
+  if (!c->initialized) return fail(c, VLB_ESTATE, "no valid state to read");
+  const size_t N = (size_t)c->P.N;
+  const hipMemcpyKind kind =
+      dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (field >= VLB_FIELD_RHO && field <= VLB_FIELD_DFS) {
+    HIP_TRY(c, hipMemcpyAsync(dst, c->macro + (size_t)field * N,
+                              N * sizeof(double), kind, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return VLB_OK;
+  }
+  if (field == VLB_FIELD_F || field == VLB_FIELD_G) {
+    const void* pop = field == VLB_FIELD_F ? c->f[c->cur] : c->g[c->cur];
+    double* tmp = dst;
+    if (!dst_is_device) {
+      HIP_TRY(c, hipMalloc((void**)&tmp, 9 * N * sizeof(double)));
+    }
+    hipError_t e = launch_unpack(c->prec, c->P, pop, c->plane,
+                                 field == VLB_FIELD_G, tmp, c->stream);
+    if (e == hipSuccess && !dst_is_device)
+      e = hipMemcpyAsync(dst, tmp, 9 * N * sizeof(double),
+                         hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (!dst_is_device) (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(c, e, "read populations");
+    return VLB_OK;
+  }
+  return fail(c, VLB_EINVAL, "unknown field");
+}
+
+vlb_status vlb_read_particles(vlb_ctx* c, int32_t n, vlb_particle_state* dst) {
+  if (!c || (n > 0 && !dst)) return VLB_EINVAL;
+  if (n < 0 || n > c->np) return fail(c, VLB_EINVAL, "bad particle count");
+  if (!c->initialized) return fail(c, VLB_ESTATE, "no valid state to read");
+  if (n == 0) return VLB_OK;
+  const int np = c->np;
+  PState cur = c->ps[c->pcur];
+  HIP_TRY(c, launch_particles(c->P, cur, c->ps[1 - c->pcur], c->pc, lists(c),
+                              c->partial, c->have_partials, kModeReduceOnly,
+                              c->flags, c->stream));
+  HIP_TRY(c, launch_particle_sums(c->P, cur, c->pc, c->macro, c->thermal4,
+                                  c->stream));
+  std::vector<double> st(12 * (size_t)np), th(4 * (size_t)np);
+  HIP_TRY(c, hipMemcpyAsync(st.data(), c->pmem[c->pcur], st.size() * 8,
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(th.data(), c->thermal4, th.size() * 8,
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < n; ++k) {
+    vlb_particle_state& o = dst[k];
+    o.x = st[k];
+    o.y = st[np + k];
+    o.theta = st[2 * np + k];
+    o.ux = st[3 * np + k];
+    o.uy = st[4 * np + k];
+    o.omega = st[5 * np + k];
+    o.Fx = st[9 * np + k];
+    o.Fy = st[10 * np + k];
+    o.Tz = st[11 * np + k];
+    o.T_mean = th[4 * k];
+    o.T_min = th[4 * k + 1];
+    o.E_solid = th[4 * k + 2];
+    o.fs_sum = th[4 * k + 3];
+  }
+  return VLB_OK;
+}
+
+vlb_status vlb_read_ownership(vlb_ctx* c, int32_t* count, int32_t* ids,
+                              int32_t* full) {
+  if (!c || !count || !ids || !full) return VLB_EINVAL;
+  if (!c->initialized) return fail(c, VLB_ESTATE, "no valid state to read");
+  const size_t N = (size_t)c->P.N, K = (size_t)c->P.kmax;
+  int *dc = nullptr, *di = nullptr, *df = nullptr;
+  hipError_t e = hipMalloc((void**)&dc, N * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&di, N * K * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&df, N * K * sizeof(int));
+  PState cur = c->ps[c->pcur];
+  if (e == hipSuccess)
+    e = launch_particles(c->P, cur, cur, c->pc, lists(c), c->partial, 0,
+                         kModeBinOnly, c->flags, c->stream);
+  if (e == hipSuccess)
+    e = launch_ownership(c->P, cur, c->pc, lists(c), dc, di, df, c->flags,
+                         c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(count, dc, N * sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ids, di, N * K * sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(full, df, N * K * sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (dc) (void)hipFree(dc);
+  if (di) (void)hipFree(di);
+  if (df) (void)hipFree(df);
+  if (e != hipSuccess) return hip_fail(c, e, "read ownership");
+  return VLB_OK;
+}
+
+// Checkpoint layout: header, then f and g (current copies, storage form),
+// h, macro fields, particle state (12 x np doubles), slot counts (np ints),
+// partials (np x maxb x 3 doubles).
+struct SaveHeader {
+  char magic[8];
+  int32_t nx, ny, prec, np, maxb, have_partials;
+  int64_t step;
+};
+
+static size_t save_size(const vlb_ctx* c) {
+  const size_t N = (size_t)c->P.N;
+  return sizeof(SaveHeader) + 2 * 9 * c->plane * c->pop_elem + N * c->h_elem +
+         6 * N * 8 + 12 * (size_t)c->np * 8 + (size_t)c->np * 4 +
+         (size_t)c->np * c->maxb * kRedVals * 8;
+}
+
+vlb_status vlb_save(vlb_ctx* c, void* buf, size_t* inout_len) {
+  if (!c || !inout_len) return VLB_EINVAL;
+  const size_t need = save_size(c);
+  if (!buf) {
+    *inout_len = need;
+    return VLB_OK;
+  }
+  if (*inout_len < need) return fail(c, VLB_EINVAL, "checkpoint buffer too small");
+  if (!c->initialized) return fail(c, VLB_ESTATE, "no valid state to save");
+  SaveHeader hd;
+  memset(&hd, 0, sizeof(hd));
+  memcpy(hd.magic, "VLBCKPT1", 8);
+  hd.nx = c->P.nx; hd.ny = c->P.ny; hd.prec = c->prec; hd.np = c->np;
+  hd.maxb = c->maxb; hd.have_partials = c->have_partials; hd.step = c->step;
+  char* o = (char*)buf;
+  memcpy(o, &hd, sizeof(hd));
+  o += sizeof(hd);
+  const size_t N = (size_t)c->P.N, pb = 9 * c->plane * c->pop_elem;
+  const hipMemcpyKind D2H = hipMemcpyDeviceToHost;
+  HIP_TRY(c, hipMemcpyAsync(o, c->f[c->cur], pb, D2H, c->stream)); o += pb;
+  HIP_TRY(c, hipMemcpyAsync(o, c->g[c->cur], pb, D2H, c->stream)); o += pb;
+  HIP_TRY(c, hipMemcpyAsync(o, c->h, N * c->h_elem, D2H, c->stream)); o += N * c->h_elem;
+  HIP_TRY(c, hipMemcpyAsync(o, c->macro, 6 * N * 8, D2H, c->stream)); o += 6 * N * 8;
+  if (c->np > 0) {
+    const size_t n = (size_t)c->np;
+    HIP_TRY(c, hipMemcpyAsync(o, c->pmem[c->pcur], 12 * n * 8, D2H, c->stream)); o += 12 * n * 8;
+    HIP_TRY(c, hipMemcpyAsync(o, c->pslot[c->pcur], n * 4, D2H, c->stream)); o += n * 4;
+    HIP_TRY(c, hipMemcpyAsync(o, c->partial, n * c->maxb * kRedVals * 8, D2H, c->stream));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *inout_len = need;
+  return VLB_OK;
+}
+
+vlb_status vlb_load(vlb_ctx* c, const void* buf, size_t len) {
+  if (!c || !buf) return VLB_EINVAL;
+  if (len < sizeof(SaveHeader) || len < save_size(c))
+    return fail(c, VLB_EINVAL, "checkpoint too short");
+  SaveHeader hd;
+  memcpy(&hd, buf, sizeof(hd));
+  if (memcmp(hd.magic, "VLBCKPT1", 8) != 0 || hd.nx != c->P.nx ||
+      hd.ny != c->P.ny || hd.prec != c->prec || hd.np != c->np ||
+      hd.maxb != c->maxb)
+    return fail(c, VLB_EINVAL, "checkpoint does not match this context");
+  if (c->np > 0 && c->parts.empty())
+    return fail(c, VLB_ESTATE, "set the particles before loading");
+  const char* o = (const char*)buf + sizeof(hd);
+  const size_t N = (size_t)c->P.N, pb = 9 * c->plane * c->pop_elem;
+  const hipMemcpyKind H2D = hipMemcpyHostToDevice;
+  c->cur = 0;
+  c->pcur = 0;
+  HIP_TRY(c, hipMemcpyAsync(c->f[0], o, pb, H2D, c->stream)); o += pb;
+  HIP_TRY(c, hipMemcpyAsync(c->g[0], o, pb, H2D, c->stream)); o += pb;
+  HIP_TRY(c, hipMemcpyAsync(c->h, o, N * c->h_elem, H2D, c->stream)); o += N * c->h_elem;
+  HIP_TRY(c, hipMemcpyAsync(c->macro, o, 6 * N * 8, H2D, c->stream)); o += 6 * N * 8;
+  if (c->np > 0) {
+    const size_t n = (size_t)c->np;
+    std::vector<double> cst(3 * n);
+    std::vector<int> fx(n);
+    for (size_t k = 0; k < n; ++k) {
+      cst[k] = c->parts[k].radius;
+      cst[n + k] = c->parts[k].rho_s;
+      cst[2 * n + k] = c->parts[k].T_init;
+      fx[k] = c->parts[k].fixed ? 1 : 0;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->pmem[0], o, 12 * n * 8, H2D, c->stream)); o += 12 * n * 8;
+    HIP_TRY(c, hipMemcpyAsync(c->pslot[0], o, n * 4, H2D, c->stream)); o += n * 4;
+    HIP_TRY(c, hipMemcpyAsync(c->partial, o, n * c->maxb * kRedVals * 8, H2D, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->pconst, cst.data(), cst.size() * 8, H2D, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->pfixed, fx.data(), fx.size() * 4, H2D, c->stream));
+  }
+  HIP_TRY(c, hipMemsetAsync(c->blk_cnt, 0, c->P.nblocks * sizeof(int), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->flags, 0, 4 * sizeof(int), c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->have_partials = hd.have_partials;
+  c->step = hd.step;
+  c->initialized = true;
+  return VLB_OK;
+}
+
+int64_t vlb_step_count(const vlb_ctx* c) { return c ? c->step : -1; }
+
+vlb_status vlb_timing_enable(vlb_ctx* c, int32_t on) {
+  if (!c) return VLB_EINVAL;
+  c->timing = on != 0;
+  return VLB_OK;
+}
+
+vlb_status vlb_timing_read(vlb_ctx* c, double* total_ms, int64_t* count) {
+  if (!c || !total_ms || !count) return VLB_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *count = (int64_t)(c->ev_used / 2);
+  c->ev_used = 0;
+  return VLB_OK;
+}
+
+size_t vlb_device_bytes(const vlb_ctx* c) { return c ? c->dev_bytes : 0; }
+
+const char* vlb_last_error(const vlb_ctx* c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+void vlb_destroy(vlb_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  free_particles(c);
+  for (int k = 0; k < 2; ++k) {
+    if (c->f[k]) (void)hipFree(c->f[k]);
+    if (c->g[k]) (void)hipFree(c->g[k]);
+  }
+  if (c->h) (void)hipFree(c->h);
+  if (c->macro) (void)hipFree(c->macro);
+  if (c->blk_cnt) (void)hipFree(c->blk_cnt);
+  if (c->blk_ent) (void)hipFree(c->blk_ent);
+  if (c->flags) (void)hipFree(c->flags);
+  if (c->flags_host) (void)hipHostFree(c->flags_host);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"

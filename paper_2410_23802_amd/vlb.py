@@ -1,0 +1,343 @@
+"""Python binding of the C ABI in include/vlb.h (argument marshalling only).
+
+Every step of the lattice update runs in the HIP kernels of libvlb.so; this
+module only converts Python values to the C structs and back.  It raises
+``VlbLibraryMissing`` when the library has not been built -- there is no
+fallback path.
+
+Functions keep the C names (``vlb_create``, ``vlb_step``, ...).  ``Domain``
+is a small convenience wrapper over one context.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvlb.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "vlb.h")
+
+VLB_OK, VLB_EINVAL, VLB_ENOMEM, VLB_EHIP = 0, -1, -2, -3
+VLB_EUNSTABLE, VLB_EOVERLAP, VLB_ESTATE = -4, -5, -6
+STATUS_NAMES = {0: "VLB_OK", -1: "VLB_EINVAL", -2: "VLB_ENOMEM",
+                -3: "VLB_EHIP", -4: "VLB_EUNSTABLE", -5: "VLB_EOVERLAP",
+                -6: "VLB_ESTATE"}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16s": 2, "bf16s": 3}
+FIELDS = {"rho": 0, "ux": 1, "uy": 2, "T": 3, "fs": 4, "dfs": 5, "f": 6,
+          "g": 7}
+FACE_FLOW = {"periodic": 0, "wall": 1}
+FACE_THERMAL = {"adiabatic": 0, "dirichlet": 1}
+
+
+class VlbLibraryMissing(RuntimeError):
+    pass
+
+
+class VlbError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class vlb_domain_desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("face_flow", ctypes.c_int32 * 4),
+        ("u_wall", (ctypes.c_double * 2) * 4),
+        ("face_thermal", ctypes.c_int32 * 4),
+        ("T_wall", ctypes.c_double * 4),
+        ("tau_f", ctypes.c_double), ("rho_f", ctypes.c_double),
+        ("cv_f", ctypes.c_double), ("lambda_f", ctypes.c_double),
+        ("R_lambda", ctypes.c_double), ("R_cv", ctypes.c_double),
+        ("body_force", ctypes.c_double * 2), ("gravity", ctypes.c_double * 2),
+        ("beta", ctypes.c_double), ("T_ref", ctypes.c_double),
+        ("sigma_rule", ctypes.c_int32),
+        ("coll_range", ctypes.c_double), ("coll_stiff_pp", ctypes.c_double),
+        ("coll_stiff_pw", ctypes.c_double),
+        ("init_rho", ctypes.c_double), ("init_u", ctypes.c_double * 2),
+        ("init_T", ctypes.c_double),
+        ("kmax", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("shift_rho0", ctypes.c_double), ("shift_T0", ctypes.c_double),
+    ]
+
+
+class vlb_particle_desc(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("x", "y", "theta", "ux", "uy", "omega", "radius", "rho_s",
+                 "T_init")] + [("fixed", ctypes.c_int32)]
+
+
+class vlb_particle_state(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("x", "y", "theta", "ux", "uy", "omega", "Fx", "Fy", "Tz",
+                 "T_mean", "T_min", "E_solid", "fs_sum")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvlb.so (built by paper_2410_23802_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise VlbLibraryMissing(
+            f"{LIB_PATH} is not built; run paper_2410_23802_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "vlb_create": ([ctypes.POINTER(vlb_domain_desc), vp,
+                        ctypes.POINTER(vp)], ctypes.c_int),
+        "vlb_set_particles": ([vp, i32, ctypes.POINTER(vlb_particle_desc)],
+                              ctypes.c_int),
+        "vlb_init": ([vp], ctypes.c_int),
+        "vlb_step": ([vp, i64], ctypes.c_int),
+        "vlb_read_field": ([vp, i32, vp, i32], ctypes.c_int),
+        "vlb_read_particles": ([vp, i32, ctypes.POINTER(vlb_particle_state)],
+                               ctypes.c_int),
+        "vlb_read_ownership": ([vp, vp, vp, vp], ctypes.c_int),
+        "vlb_save": ([vp, vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "vlb_load": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
+        "vlb_step_count": ([vp], i64),
+        "vlb_timing_enable": ([vp, i32], ctypes.c_int),
+        "vlb_timing_read": ([vp, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(i64)], ctypes.c_int),
+        "vlb_device_bytes": ([vp], ctypes.c_size_t),
+        "vlb_last_error": ([vp], ctypes.c_char_p),
+        "vlb_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/vlb.h declares."""
+    with open(HEADER) as fh:
+        txt = fh.read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(vlb_\w+)\s*\(", txt)))
+
+
+def make_domain_desc(d: dict, precision="fp64", shift_rho0=None,
+                     shift_T0=None) -> vlb_domain_desc:
+    s = vlb_domain_desc()
+    s.nx, s.ny = int(d["nx"]), int(d["ny"])
+    for k in range(4):
+        s.face_flow[k] = FACE_FLOW[d["face_flow"][k]]
+        s.u_wall[k][0], s.u_wall[k][1] = d["u_wall"][k]
+        s.face_thermal[k] = FACE_THERMAL[d["face_thermal"][k]]
+        s.T_wall[k] = d["T_wall"][k]
+    for name in ("tau_f", "rho_f", "cv_f", "lambda_f", "R_lambda", "R_cv",
+                 "beta", "T_ref", "coll_range", "coll_stiff_pp",
+                 "coll_stiff_pw", "init_rho", "init_T"):
+        setattr(s, name, float(d[name]))
+    s.body_force[0], s.body_force[1] = d["body_force"]
+    s.gravity[0], s.gravity[1] = d["gravity"]
+    s.init_u[0], s.init_u[1] = d["init_u"]
+    s.sigma_rule = int(d["sigma_rule"])
+    s.kmax = int(d["kmax"])
+    s.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    s.shift_rho0 = float(d["init_rho"] if shift_rho0 is None else shift_rho0)
+    s.shift_T0 = float(0.5 if shift_T0 is None else shift_T0)
+    return s
+
+
+def make_particles(ps) -> ctypes.Array:
+    arr = (vlb_particle_desc * max(1, len(ps)))()
+    for k, p in enumerate(ps):
+        for name in ("x", "y", "theta", "ux", "uy", "omega", "radius", "rho_s",
+                     "T_init"):
+            setattr(arr[k], name, float(p[name]))
+        arr[k].fixed = int(p["fixed"])
+    return arr
+
+
+def _check(status: int, where: str, handle=None):
+    if status != VLB_OK:
+        msg = lib().vlb_last_error(handle)
+        raise VlbError(status, where, msg.decode() if msg else "")
+
+
+def _stream_handle(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except Exception:
+            pass
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+# ---- C-named wrappers -------------------------------------------------------
+
+
+def vlb_create(desc: vlb_domain_desc, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().vlb_create(ctypes.byref(desc), _stream_handle(stream),
+                            ctypes.byref(h)), "vlb_create")
+    return h
+
+
+def vlb_set_particles(h, particles) -> None:
+    arr = make_particles(particles)
+    _check(lib().vlb_set_particles(h, len(particles), arr),
+           "vlb_set_particles", h)
+
+
+def vlb_init(h) -> None:
+    _check(lib().vlb_init(h), "vlb_init", h)
+
+
+def vlb_step(h, nsteps: int) -> None:
+    _check(lib().vlb_step(h, int(nsteps)), "vlb_step", h)
+
+
+def vlb_read_field(h, field, dst_ptr: int, dst_is_device: bool) -> None:
+    fid = FIELDS[field] if isinstance(field, str) else int(field)
+    _check(lib().vlb_read_field(h, fid, ctypes.c_void_p(dst_ptr),
+                                int(bool(dst_is_device))), "vlb_read_field", h)
+
+
+def vlb_read_particles(h, n: int) -> np.ndarray:
+    arr = (vlb_particle_state * max(1, n))()
+    _check(lib().vlb_read_particles(h, n, arr), "vlb_read_particles", h)
+    names = [f[0] for f in vlb_particle_state._fields_]
+    out = np.zeros(n, dtype=[(k, np.float64) for k in names])
+    for i in range(n):
+        out[i] = tuple(getattr(arr[i], k) for k in names)
+    return out
+
+
+def vlb_read_ownership(h, nx, ny, kmax):
+    cnt = np.zeros((ny, nx), np.int32)
+    ids = np.zeros((ny, nx, kmax), np.int32)
+    full = np.zeros((ny, nx, kmax), np.int32)
+    _check(lib().vlb_read_ownership(h, cnt.ctypes.data, ids.ctypes.data,
+                                    full.ctypes.data), "vlb_read_ownership", h)
+    return cnt, ids, full
+
+
+def vlb_save(h) -> bytes:
+    n = ctypes.c_size_t(0)
+    _check(lib().vlb_save(h, None, ctypes.byref(n)), "vlb_save", h)
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().vlb_save(h, buf, ctypes.byref(n)), "vlb_save", h)
+    return buf.raw[: n.value]
+
+
+def vlb_load(h, data: bytes) -> None:
+    buf = ctypes.create_string_buffer(data, len(data))
+    _check(lib().vlb_load(h, buf, len(data)), "vlb_load", h)
+
+
+def vlb_step_count(h) -> int:
+    return int(lib().vlb_step_count(h))
+
+
+def vlb_timing_enable(h, on: bool) -> None:
+    _check(lib().vlb_timing_enable(h, int(bool(on))), "vlb_timing_enable", h)
+
+
+def vlb_timing_read(h):
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().vlb_timing_read(h, ctypes.byref(ms), ctypes.byref(n)),
+           "vlb_timing_read", h)
+    return ms.value, n.value
+
+
+def vlb_device_bytes(h) -> int:
+    return int(lib().vlb_device_bytes(h))
+
+
+def vlb_last_error(h=None) -> str:
+    m = lib().vlb_last_error(h)
+    return m.decode() if m else ""
+
+
+def vlb_destroy(h) -> None:
+    lib().vlb_destroy(h)
+
+
+# ---- convenience wrapper ----------------------------------------------------
+
+
+class Domain:
+    """One simulation context.  `domain` and `particles` are the plain dicts
+    of the `workloads` module."""
+
+    def __init__(self, domain: dict, particles=(), precision="fp64",
+                 stream=None, shift_rho0=None, shift_T0=None):
+        self.domain = dict(domain)
+        self.nx, self.ny = int(domain["nx"]), int(domain["ny"])
+        self.kmax = int(domain["kmax"])
+        self.np_ = len(particles)
+        self.precision = precision
+        self._desc = make_domain_desc(domain, precision, shift_rho0, shift_T0)
+        self.h = vlb_create(self._desc, stream)
+        try:
+            vlb_set_particles(self.h, list(particles))
+        except Exception:
+            self.close()
+            raise
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            vlb_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def init(self):
+        vlb_init(self.h)
+        return self
+
+    def step(self, n: int = 1):
+        vlb_step(self.h, n)
+        return self
+
+    @property
+    def step_count(self) -> int:
+        return vlb_step_count(self.h)
+
+    def field(self, name: str) -> np.ndarray:
+        """Host copy, (ny, nx) or (9, ny, nx) for 'f' and 'g'."""
+        shape = (9, self.ny, self.nx) if name in ("f", "g") else (self.ny, self.nx)
+        out = np.empty(shape, np.float64)
+        vlb_read_field(self.h, name, out.ctypes.data, False)
+        return out
+
+    def field_device(self, name: str, out):
+        """Copy into a CUDA/HIP torch tensor of float64 on this device."""
+        vlb_read_field(self.h, name, out.data_ptr(), True)
+        return out
+
+    def particles(self) -> np.ndarray:
+        return vlb_read_particles(self.h, self.np_)
+
+    def ownership(self):
+        return vlb_read_ownership(self.h, self.nx, self.ny, self.kmax)
+
+    def save(self) -> bytes:
+        return vlb_save(self.h)
+
+    def load(self, data: bytes):
+        vlb_load(self.h, data)
+        return self
+
+    def timing(self, on: bool = True):
+        vlb_timing_enable(self.h, on)
+
+    def timing_read(self):
+        return vlb_timing_read(self.h)

@@ -1,0 +1,69 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, and rejects bad descriptors before touching the GPU."""
+import ctypes
+import os
+
+import pytest
+
+import workloads as W
+
+
+@pytest.fixture(scope="module")
+def vlb():
+    from paper_2410_23802_amd import build as hb
+    from paper_2410_23802_amd import vlb as v
+    if not os.path.exists(v.LIB_PATH):
+        hb.build()
+    return v
+
+
+def test_library_exports_header_symbols(vlb):
+    names = vlb.header_functions()
+    assert "vlb_step" in names and "vlb_create" in names
+    L = vlb.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_descriptor_mirror_matches_header_field_order(vlb):
+    """The ctypes mirror lists the header's struct members in order."""
+    import re
+    with open(vlb.HEADER) as fh:
+        txt = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+    body = re.search(r"typedef struct \{(.*?)\} vlb_domain_desc;", txt, re.S)
+    decl = re.findall(r"\b([A-Za-z_]\w*)\s*(?:\[[^\]]*\])*\s*[,;]", body.group(1))
+    assert decl == [f[0] for f in vlb.vlb_domain_desc._fields_]
+
+
+@pytest.mark.parametrize("patch,msg", [
+    ({"nx": 0}, "nx and ny"),
+    ({"tau_f": 0.5}, "tau_f"),
+    ({"face_flow": ["periodic", "wall", "periodic", "periodic"]}, "pairs"),
+    ({"kmax": 0}, "kmax"),
+    ({"lambda_f": -1.0}, "> 0"),
+    ({"sigma_rule": 3}, "sigma_rule"),
+])
+def test_create_rejects_bad_descriptor(vlb, patch, msg):
+    d = W.domain(16, 16)
+    d.update(patch)
+    desc = vlb.make_domain_desc(d)
+    h = ctypes.c_void_p()
+    rc = vlb.lib().vlb_create(ctypes.byref(desc), None, ctypes.byref(h))
+    assert rc == vlb.VLB_EINVAL
+    assert h.value is None
+    assert msg in vlb.vlb_last_error(None)
+
+
+def test_create_rejects_unknown_precision(vlb):
+    desc = vlb.make_domain_desc(W.domain(8, 8), precision=7)
+    h = ctypes.c_void_p()
+    assert vlb.lib().vlb_create(ctypes.byref(desc), None, ctypes.byref(h)) == vlb.VLB_EINVAL
+
+
+def test_null_arguments(vlb):
+    L = vlb.lib()
+    assert L.vlb_create(None, None, None) == vlb.VLB_EINVAL
+    assert L.vlb_step(None, 1) == vlb.VLB_EINVAL
+    assert L.vlb_init(None) == vlb.VLB_EINVAL
+    assert L.vlb_step_count(None) == -1
+    L.vlb_destroy(None)
