@@ -1,0 +1,199 @@
+"""Throughput of the coupled flow + thermal lattice update on one MI355X.
+
+One step = the whole per-time-step update (particle pass + fused lattice
+pass) over the workload, driven through the C ABI.  The headline workload is
+the 200 x 4000 channel with one cold sedimenting disk; the headline value is
+its FP64 throughput in MLUPS (every cell counts).  The same line reports the
+FP32 / FP16-shifted / BF16-shifted forms, the lattice kernel's achieved HBM
+bandwidth against the 8 TB/s peak, and the FP64 CPU oracle timed on a bounded
+sample on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coupled flow+thermal MLUPS & %HBM roofline, FP64 vs FP32 vs FP16-shifted"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per cell and step: both D2Q9 population sets read once
+# and written once, plus the [df_s/dt] carrier read and written once.
+BYTES_PER_CELL = {"fp64": 2 * 18 * 8 + 2 * 8, "fp32": 2 * 18 * 4 + 2 * 4,
+                  "fp16s": 2 * 18 * 2 + 2 * 4, "bf16s": 2 * 18 * 2 + 2 * 4}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16 storage, f32 arithmetic",
+         "bf16s": "bf16 storage, f32 arithmetic"}
+KERNEL_SOURCES = ["paper_2410_23802_amd/csrc/vlb_kernels.hip",
+                  "paper_2410_23802_amd/csrc/vlb_internal.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per lattice launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_lattice_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    ent = rec.get("per_precision", {}).get(precision)
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def run_gpu(vlb, d, ps, precision, steps, warmup):
+    import torch
+    dom = vlb.Domain(d, ps, precision).init()
+    if warmup:
+        dom.step(warmup)
+    dom.timing(True)
+    dom.timing_read()                      # reset the event pairs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dom.step(steps)                        # returns after the stream drained
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ker_ms, nker = dom.timing_read()
+    dom.timing(False)
+    p = dom.particles()
+    dom.close()
+    cells = d["nx"] * d["ny"]
+    wall = t1 - t0
+    return {
+        "mlups": cells * steps / wall / 1e6,
+        "ms_per_step": wall * 1e3 / steps,
+        "lattice_ms": ker_ms / max(nker, 1),
+        "launches": nker,
+        "particle_y": float(p["y"][0]) if len(p) else None,
+    }
+
+
+def cpu_baseline(d, ps, target_s=15.0):
+    """The FP64 oracle as it stands, on a bounded sample of the same
+    workload: as many steps as take about `target_s` seconds."""
+    from oracle import oracle as O
+    if not os.path.exists(O.LIB):
+        O.build()
+    threads = min(os.cpu_count() or 1, 16)
+    O.set_threads(threads)
+    o = O.Oracle(d, ps).init()
+    t0 = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t0
+    n = max(1, int(target_s / max(one, 1e-6)) - 1)
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    cells = d["nx"] * d["ny"]
+    return {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{d['nx']}x{d['ny']} channel, {len(ps)} particle, "
+                      f"{n} steps after one untimed step, FP64, "
+                      f"{threads} OpenMP threads, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--precisions", default="fp64,fp32,fp16s,bf16s")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU decomposition is not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2410_23802_amd import vlb
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if not os.path.exists(vlb.LIB_PATH):
+        from paper_2410_23802_amd import build as hb
+        hb.build()
+    torch.cuda.set_device(0)
+
+    workload = "c2_channel"
+    d, ps = W.c2_channel()
+    cells = d["nx"] * d["ny"]
+    precs = [p for p in args.precisions.split(",") if p]
+    res = {}
+    for prec in precs:
+        r = run_gpu(vlb, d, ps, prec, args.steps, args.warmup)
+        gbs = BYTES_PER_CELL[prec] * cells / (r["lattice_ms"] * 1e-3) / 1e9
+        r["achieved_GBs"] = gbs
+        r["frac"] = gbs / HBM_PEAK_GBS
+        res[prec] = r
+        print(f"# {prec}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step, "
+              f"lattice {r['lattice_ms'] * 1e3:.1f} us -> {gbs:.0f} GB/s "
+              f"({100 * r['frac']:.1f}% of HBM peak)", file=sys.stderr,
+              flush=True)
+
+    head = res[precs[0]]
+    traffic = measured_traffic(workload, precs[0])
+    line = {
+        "metric": METRIC,
+        "value": round(head["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[precs[0]],
+        "data": "synthetic",
+        "config": {"workload": workload, "nx": d["nx"], "ny": d["ny"],
+                   "particles": len(ps), "particle_diameter": 2 * ps[0]["radius"],
+                   "lattices": "D2Q9 flow + D2Q9 energy, MRT",
+                   "precision": precs[0]},
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(head["achieved_GBs"], 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(head["frac"], 4),
+            "traffic": traffic,
+            "kernel": "k_lattice",
+            "bytes_per_cell": BYTES_PER_CELL[precs[0]],
+            "cells_per_launch": cells,
+            "avg_launch_us": round(head["lattice_ms"] * 1e3, 2),
+        },
+        "precisions": {
+            DTYPE[p].split(" ")[0] + ("-shifted" if p.endswith("s") else ""): {
+                "mlups": round(res[p]["mlups"], 1),
+                "ms_per_step": round(res[p]["ms_per_step"], 5),
+                "lattice_us": round(res[p]["lattice_ms"] * 1e3, 2),
+                "achieved_GBs": round(res[p]["achieved_GBs"], 1),
+                "frac_hbm": round(res[p]["frac"], 4),
+                "bytes_per_cell": BYTES_PER_CELL[p],
+            } for p in precs},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(d, ps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -52,9 +52,11 @@ typedef enum {
   VLB_ESTATE = -6      /* call out of order (e.g. step before init)       */
 } vlb_status;
 
-/* Storage of the populations.  FP16/BF16 forms store the deviations
- * f_i - w_i rho_0 and g_i - w_i c_ref T_0 and compute in FP32; the
- * per-particle sums and the particle integration are FP64 in every form. */
+/* Storage of the populations.  FP64 stores f_i and g_i.  FP32, FP16 and
+ * BF16 store the deviations f_i - w_i rho_0 and g_i - w_i c_ref T_0
+ * (rho_0 = shift_rho0, T_0 = shift_T0) and compute on deviations in FP32;
+ * the per-particle sums and the particle integration are FP64 in every
+ * form. */
 typedef enum {
   VLB_FP64 = 0,
   VLB_FP32 = 1,
@@ -90,10 +92,10 @@ typedef struct {
   double  coll_stiff_pp;     /* particle-particle repulsion at contact        */
   double  coll_stiff_pw;     /* particle-wall repulsion at contact            */
   double  init_rho, init_u[2], init_T;   /* initial fluid state               */
-  int32_t kmax;              /* max particles touching one cell (1..4)        */
+  int32_t kmax;              /* max particles touching one cell (1..8)        */
   int32_t precision;         /* vlb_precision                                 */
-  double  shift_rho0;        /* rho_0 of the 16-bit shifted storage           */
-  double  shift_T0;          /* T_0 of the 16-bit shifted storage             */
+  double  shift_rho0;        /* rho_0 of the deviation storage (not FP64)     */
+  double  shift_T0;          /* T_0 of the deviation storage (not FP64)       */
 } vlb_domain_desc;
 
 typedef struct {

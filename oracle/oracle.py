@@ -15,20 +15,35 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "vlb_oracle.c")
 LIB = os.path.join(HERE, "liboracle_vlb.so")
+# The same source built with fused multiply-adds: a second FP64
+# implementation that differs from the first only in rounding.  The gap
+# between the two measures how closely FP64 can reproduce a result at all.
+LIB_FMA = os.path.join(HERE, "liboracle_vlb_fma.so")
 
 FACE_FLOW = {"periodic": 0, "wall": 1}
 FACE_THERMAL = {"adiabatic": 0, "dirichlet": 1}
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, no contraction of multiply-adds)."""
-    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
-           "-shared", "-Wall", "-o", LIB + ".tmp", SRC, "-lm"]
-    if verbose:
-        print(" ".join(cmd))
-    subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    """Compile the oracle with gcc (-O2, no contraction of multiply-adds),
+    and its rounding twin with contraction into fused multiply-adds."""
+    for out, flags in ((LIB, ["-ffp-contract=off"]),
+                       (LIB_FMA, ["-mfma", "-ffp-contract=fast"])):
+        cmd = ["gcc", "-std=c11", "-O2", *flags, "-fopenmp", "-fPIC",
+               "-shared", "-Wall", "-o", out + ".tmp", SRC, "-lm"]
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
     return LIB
+
+
+def host_has_fma() -> bool:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            return " fma " in fh.read().replace("\n", " ")
+    except OSError:
+        return False
 
 
 class _Domain(ctypes.Structure):
@@ -61,7 +76,7 @@ class _Particle(ctypes.Structure):
 class _PState(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("x", "y", "theta", "ux", "uy", "omega", "Fx", "Fy", "Tz",
-                 "T_mean", "T_min", "E_solid", "fs_sum")]
+                 "T_mean", "T_min", "E_solid", "fs_sum", "F_abs")]
 
 
 class _Hooks(ctypes.Structure):
@@ -71,15 +86,15 @@ class _Hooks(ctypes.Structure):
                 ("fs_from_array", ctypes.c_int32)]
 
 
-_lib = None
+_libs: dict = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB):
+def lib(variant: str = "plain"):
+    if variant not in _libs:
+        path = LIB if variant == "plain" else LIB_FMA
+        if not os.path.exists(path):
             build()
-        L = ctypes.CDLL(LIB)
+        L = ctypes.CDLL(path)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         dptr = ctypes.POINTER(ctypes.c_double)
         iptr = ctypes.POINTER(ctypes.c_int32)
@@ -111,8 +126,8 @@ def lib():
         L.or_cell_in_band.argtypes = [ctypes.c_double] * 3 + [i32, i32]
         L.or_cell_inside.argtypes = [ctypes.c_double] * 3 + [i32, i32]
         L.or_collision_force.argtypes = [vp, i32, dptr, dptr]
-        _lib = L
-    return _lib
+        _libs[variant] = L
+    return _libs[variant]
 
 
 def set_threads(n: int) -> int:
@@ -159,8 +174,10 @@ class Oracle:
     """One oracle domain.  Field accessors return numpy copies shaped
     (ny, nx) or (9, ny, nx)."""
 
-    def __init__(self, domain: dict, particles=(), hooks: dict | None = None):
-        L = lib()
+    def __init__(self, domain: dict, particles=(), hooks: dict | None = None,
+                 variant: str = "plain"):
+        self._variant = variant
+        L = lib(variant)
         self.domain = dict(domain)
         self.nx, self.ny = int(domain["nx"]), int(domain["ny"])
         self.np_ = len(particles)
@@ -186,29 +203,29 @@ class Oracle:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().or_destroy(self._h)
+            lib(self._variant).or_destroy(self._h)
             self._h = None
 
     __del__ = close
 
     def init(self):
-        rc = lib().or_init(self._h)
+        rc = lib(self._variant).or_init(self._h)
         if rc != 0:
             raise OracleError(rc, "init")
         return self
 
     def step(self, n: int = 1):
-        rc = lib().or_step(self._h, int(n))
+        rc = lib(self._variant).or_step(self._h, int(n))
         if rc != 0:
             raise OracleError(rc, "step")
         return self
 
     @property
     def step_count(self) -> int:
-        return int(lib().or_step_count(self._h))
+        return int(lib(self._variant).or_step_count(self._h))
 
     def _view(self, name, shape, dtype=np.float64):
-        ptr = getattr(lib(), name)(self._h)
+        ptr = getattr(lib(self._variant), name)(self._h)
         n = int(np.prod(shape))
         ct = ctypes.c_double if dtype == np.float64 else ctypes.c_int32
         buf = ctypes.cast(ptr, ctypes.POINTER(ct * n)).contents
@@ -236,7 +253,7 @@ class Oracle:
         """Structured array with the fields of or_particle_state."""
         n = self.np_
         arr = (_PState * max(1, n))()
-        rc = lib().or_read_particles(self._h, n, arr)
+        rc = lib(self._variant).or_read_particles(self._h, n, arr)
         if rc != 0:
             raise OracleError(rc, "read_particles")
         names = [f[0] for f in _PState._fields_]
@@ -247,11 +264,11 @@ class Oracle:
         return out
 
     def overlap_count(self) -> int:
-        return int(lib().or_overlap_count(self._h))
+        return int(lib(self._variant).or_overlap_count(self._h))
 
     def collision_force(self, i: int):
         fx, fy = ctypes.c_double(), ctypes.c_double()
-        lib().or_collision_force(self._h, int(i), ctypes.byref(fx),
+        lib(self._variant).or_collision_force(self._h, int(i), ctypes.byref(fx),
                                  ctypes.byref(fy))
         return fx.value, fy.value
 

@@ -75,7 +75,7 @@ struct or_state {
   double *R, *rhos, *Tp0;
   int *fixed;
   double *Fx, *Fy, *Tz; /* momentum-exchange force/torque, current step */
-  double *Tmean, *Tmin, *E, *fssum;
+  double *Tmean, *Tmin, *E, *fssum, *Fabs;
   /* fields */
   double *f, *g;     /* post-collision populations [q][cell] */
   double *fst, *gst; /* post-streaming populations [q][cell] */
@@ -302,7 +302,7 @@ void or_destroy(or_state* s) {
   double* dp[] = {s->X,    s->Y,   s->th,  s->Ux,  s->Uy,    s->Om,
                   s->Uxp,  s->Uyp, s->Omp, s->R,   s->rhos,  s->Tp0,
                   s->Fx,   s->Fy,  s->Tz,  s->Tmean, s->Tmin, s->E,
-                  s->fssum, s->f,  s->g,   s->fst, s->gst,   s->dfs,
+                  s->fssum, s->Fabs, s->f, s->g, s->fst, s->gst, s->dfs,
                   s->fs,   s->fs_next, s->rho, s->ux, s->uy, s->T,
                   s->eps,  s->qc,  s->fsp, s->usx, s->usy,   s->dPx,
                   s->dPy};
@@ -342,7 +342,7 @@ int or_create(const or_domain* d, int32_t np, const or_particle* p,
   double** dp[] = {&s->X,   &s->Y,    &s->th,  &s->Ux,    &s->Uy,
                    &s->Om,  &s->Uxp,  &s->Uyp, &s->Omp,   &s->R,
                    &s->rhos, &s->Tp0, &s->Fx,  &s->Fy,    &s->Tz,
-                   &s->Tmean, &s->Tmin, &s->E, &s->fssum};
+                   &s->Tmean, &s->Tmin, &s->E, &s->fssum, &s->Fabs};
   for (size_t k = 0; k < sizeof(dp) / sizeof(dp[0]); ++k)
     *dp[k] = (double*)zalloc(sizeof(double) * n);
   s->fixed = (int*)zalloc(sizeof(int) * n);
@@ -798,6 +798,7 @@ static void particle_sums(or_state* s, int with_mes) {
       s->Fx[p] = 0.0;
       s->Fy[p] = 0.0;
       s->Tz[p] = 0.0;
+      s->Fabs[p] = 0.0;
     }
   }
   double cvs = cv_solid(s);
@@ -821,6 +822,7 @@ static void particle_sums(or_state* s, int with_mes) {
         s->Fx[p] -= s->dPx[sl];
         s->Fy[p] -= s->dPy[sl];
         s->Tz[p] -= rx * s->dPy[sl] - ry * s->dPx[sl];
+        s->Fabs[p] += fabs(s->dPx[sl]) + fabs(s->dPy[sl]);
       }
     }
   }
@@ -967,6 +969,7 @@ int or_read_particles(or_state* s, int32_t n, or_particle_state* out) {
     o->T_min = s->Tmin[p];
     o->E_solid = s->E[p];
     o->fs_sum = s->fssum[p];
+    o->F_abs = s->Fabs[p];
   }
   return OR_OK;
 }

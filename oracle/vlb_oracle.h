@@ -63,6 +63,9 @@ typedef struct {
   double x, y, theta, ux, uy, omega;
   double Fx, Fy, Tz;         /* momentum-exchange force / torque (MES)       */
   double T_mean, T_min, E_solid, fs_sum;
+  double F_abs;              /* sum over cells of |share of sum_i (f_i - f*_i) e_i|
+                                (x and y added): the size of the terms the
+                                momentum-exchange sum adds up               */
 } or_particle_state;
 
 /* Switches that exist only to plant the paper's own negative controls

@@ -22,8 +22,8 @@ struct vlb_ctx {
   size_t plane = 0, pop_elem = 0, h_elem = 0;
   void* f[2] = {nullptr, nullptr};
   void* g[2] = {nullptr, nullptr};
-  void* h = nullptr;
-  int cur = 0;
+  void* h[2] = {nullptr, nullptr};   // [df_s/dt] carrier, alternating
+  int cur = 0;                       // f[cur], g[cur], h[cur]: step n
   double* macro = nullptr;
   int* blk_cnt = nullptr;
   int2* blk_ent = nullptr;
@@ -37,7 +37,8 @@ struct vlb_ctx {
   double* pconst = nullptr;
   int* pfixed = nullptr;
   PConst pc;
-  double* partial = nullptr;
+  double* partial[2] = {nullptr, nullptr};  // step n / step n+1, alternating
+  int pp = 0;                                // partial[pp]: the latest pass
   double* thermal4 = nullptr;
   std::vector<vlb_particle_desc> parts;
   // status
@@ -96,11 +97,13 @@ static void free_particles(vlb_ctx* c) {
   }
   if (c->pconst) (void)hipFree(c->pconst);
   if (c->pfixed) (void)hipFree(c->pfixed);
-  if (c->partial) (void)hipFree(c->partial);
+  for (int k = 0; k < 2; ++k) {
+    if (c->partial[k]) (void)hipFree(c->partial[k]);
+    c->partial[k] = nullptr;
+  }
   if (c->thermal4) (void)hipFree(c->thermal4);
   c->pconst = nullptr;
   c->pfixed = nullptr;
-  c->partial = nullptr;
   c->thermal4 = nullptr;
 }
 
@@ -169,21 +172,25 @@ static void derive_params(vlb_ctx* c) {
   P.init_ux = d.init_u[0];
   P.init_uy = d.init_u[1];
   P.init_T = d.init_T;
+  // storage reference of the deviation form (not used by FP64)
+  const bool shifted = d.precision != VLB_FP64;
+  P.rho0s = shifted ? d.shift_rho0 : 0.0;
+  const double T0s = shifted ? d.shift_T0 : 0.0;
+  P.cT0s = P.cref * T0s;
   for (int w = 0; w < 4; ++w) {
     const bool dir = d.face_thermal[w] == VLB_DIRICHLET;
     P.gsign[w] = dir ? -1.0 : 1.0;
     for (int q = 0; q < 9; ++q) {
       const double eu = kEx[q] * d.u_wall[w][0] + kEy[q] * d.u_wall[w][1];
       P.fadd[w][q] = 6.0 * kW[q] * d.init_rho * eu;
-      P.gadd[w][q] = dir ? 2.0 * kW[q] * P.cref * d.T_wall[w] : 0.0;
+      // anti-bounce-back on deviations: g'_i = -g'_opp + 2 w_i c_ref (T_w - T0s)
+      P.gadd[w][q] = dir ? 2.0 * kW[q] * P.cref * (d.T_wall[w] - T0s) : 0.0;
     }
     P.wall_face[w] = d.face_flow[w] == VLB_WALL;
   }
-  const bool shifted =
-      d.precision == VLB_FP16_SHIFT || d.precision == VLB_BF16_SHIFT;
   for (int q = 0; q < 9; ++q) {
-    P.fshift[q] = shifted ? kW[q] * d.shift_rho0 : 0.0;
-    P.gshift[q] = shifted ? kW[q] * P.cref * d.shift_T0 : 0.0;
+    P.fshift[q] = kW[q] * P.rho0s;
+    P.gshift[q] = kW[q] * P.cT0s;
   }
   P.rho_f = d.rho_f;
   P.grav_x = d.gravity[0];
@@ -220,7 +227,8 @@ vlb_status vlb_create(const vlb_domain_desc* desc, void* hip_stream,
     ok = ok && dalloc(c, &c->f[k], 9 * c->plane * c->pop_elem);
     ok = ok && dalloc(c, &c->g[k], 9 * c->plane * c->pop_elem);
   }
-  ok = ok && dalloc(c, &c->h, N * c->h_elem);
+  ok = ok && dalloc(c, &c->h[0], N * c->h_elem);
+  ok = ok && dalloc(c, &c->h[1], N * c->h_elem);
   ok = ok && dalloc(c, (void**)&c->macro, 6 * N * sizeof(double));
   ok = ok && dalloc(c, (void**)&c->blk_cnt, c->P.nblocks * sizeof(int));
   ok = ok && dalloc(c, (void**)&c->blk_ent,
@@ -270,6 +278,15 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
   c->maxb = 4 * (2 * (int)ceil(rmax) + 5);
   c->P.np = n;
   c->P.maxb = c->maxb;
+  // scan form for few particles: partials [particle][tile] must stay small
+  const size_t scan_bytes = (size_t)n * c->P.nblocks * kRedVals * sizeof(double);
+  c->P.scan = (n > 0 && n <= kScanMax && scan_bytes <= ((size_t)512 << 20)) ? 1 : 0;
+  // tiles one particle reaches: its band rows (<= 2R + 4) as whole rows,
+  // plus the ends and a second range when the box wraps around y
+  const int rows = 2 * (int)ceil(rmax) + 5;
+  c->P.maxr = (int)(((int64_t)rows * c->d.nx + kBlock - 1) / kBlock) + 3;
+  const size_t part_slots =
+      c->P.scan ? (size_t)n * c->P.nblocks : (size_t)n * c->maxb;
   c->initialized = false;
   if (n == 0) return VLB_OK;
   bool ok = true;
@@ -279,8 +296,9 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
   }
   ok = ok && dalloc(c, (void**)&c->pconst, 3 * (size_t)n * sizeof(double));
   ok = ok && dalloc(c, (void**)&c->pfixed, (size_t)n * sizeof(int));
-  ok = ok && dalloc(c, (void**)&c->partial,
-                    (size_t)n * c->maxb * kRedVals * sizeof(double));
+  for (int k = 0; k < 2; ++k)
+    ok = ok && dalloc(c, (void**)&c->partial[k],
+                      part_slots * kRedVals * sizeof(double));
   ok = ok && dalloc(c, (void**)&c->thermal4, 4 * (size_t)n * sizeof(double));
   if (!ok) {
     free_particles(c);
@@ -363,9 +381,12 @@ vlb_status vlb_init(vlb_ctx* c) {
   }
   HIP_TRY(c, hipMemsetAsync(c->blk_cnt, 0, c->P.nblocks * sizeof(int), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->flags, 0, 4 * sizeof(int), c->stream));
-  HIP_TRY(c, launch_particles(c->P, c->ps[0], c->ps[1], c->pc, lists(c),
-                              c->partial, 0, kModeBinOnly, c->flags, c->stream));
-  HIP_TRY(c, launch_init(c->prec, c->P, c->f[0], c->g[0], c->h, c->plane,
+  c->pp = 0;
+  if (!c->P.scan)
+    HIP_TRY(c, launch_particles(c->P, c->ps[0], c->ps[1], c->pc, lists(c),
+                                c->partial[0], 0, kModeBinOnly, c->flags,
+                                c->stream));
+  HIP_TRY(c, launch_init(c->prec, c->P, c->f[0], c->g[0], c->h[0], c->plane,
                          c->ps[0], c->pc, lists(c), c->macro, c->flags,
                          c->stream));
   vlb_status st = check_flags(c);
@@ -375,11 +396,33 @@ vlb_status vlb_init(vlb_ctx* c) {
 
 static vlb_status one_step(vlb_ctx* c, bool last) {
   PState cur = c->ps[c->pcur], nxt = c->ps[1 - c->pcur];
-  HIP_TRY(c, launch_particles(c->P, cur, nxt, c->pc, lists(c), c->partial,
-                              c->have_partials, kModeUpdate, c->flags,
-                              c->stream));
-  const bool timed = c->timing;
-  if (timed) {
+  const double* pin = c->partial[c->pp];
+  double* pout = c->partial[1 - c->pp];
+  if (c->np > 0 && !c->P.scan)
+    HIP_TRY(c, launch_particles(c->P, cur, nxt, c->pc, lists(c), pin,
+                                c->have_partials, kModeUpdate, c->flags,
+                                c->stream));
+  LatticeLaunch a;
+  a.P = &c->P;
+  a.out = last;
+  a.fi = c->f[c->cur];
+  a.fo = c->f[1 - c->cur];
+  a.gi = c->g[c->cur];
+  a.go = c->g[1 - c->cur];
+  a.hin = c->h[c->cur];
+  a.hout = c->h[1 - c->cur];
+  a.plane = c->plane;
+  a.cur = cur;
+  a.nxt = nxt;
+  a.pc = c->pc;
+  a.L = lists(c);
+  a.partial_in = pin;
+  a.partial_out = pout;
+  a.have = c->have_partials;
+  a.macro = c->macro;
+  a.flags = c->flags;
+  a.ev_start = a.ev_stop = nullptr;
+  if (c->timing) {
     if (c->ev_used + 2 > c->ev.size()) {
       for (int k = 0; k < 64; ++k) {
         hipEvent_t e;
@@ -387,19 +430,16 @@ static vlb_status one_step(vlb_ctx* c, bool last) {
         c->ev.push_back(e);
       }
     }
-    HIP_TRY(c, hipEventRecord(c->ev[c->ev_used], c->stream));
-  }
-  HIP_TRY(c, launch_lattice(c->prec, last, c->P, c->f[c->cur],
-                            c->f[1 - c->cur], c->g[c->cur], c->g[1 - c->cur],
-                            c->h, c->plane, c->np ? nxt : cur, c->pc, lists(c),
-                            c->partial, c->macro, c->flags, c->stream));
-  if (timed) {
-    HIP_TRY(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+    a.ev_start = c->ev[c->ev_used];
+    a.ev_stop = c->ev[c->ev_used + 1];
     c->ev_used += 2;
   }
+  HIP_TRY(c, launch_lattice(c->prec, a, c->stream));
+  HIP_TRY(c, launch_lattice_particles(c->prec, a, c->stream));
   if (c->np > 0) {
     c->have_partials = 1;
     c->pcur ^= 1;
+    c->pp ^= 1;
   }
   c->cur ^= 1;
   c->step++;
@@ -459,8 +499,8 @@ vlb_status vlb_read_particles(vlb_ctx* c, int32_t n, vlb_particle_state* dst) {
   const int np = c->np;
   PState cur = c->ps[c->pcur];
   HIP_TRY(c, launch_particles(c->P, cur, c->ps[1 - c->pcur], c->pc, lists(c),
-                              c->partial, c->have_partials, kModeReduceOnly,
-                              c->flags, c->stream));
+                              c->partial[c->pp], c->have_partials,
+                              kModeReduceOnly, c->flags, c->stream));
   HIP_TRY(c, launch_particle_sums(c->P, cur, c->pc, c->macro, c->thermal4,
                                   c->stream));
   std::vector<double> st(12 * (size_t)np), th(4 * (size_t)np);
@@ -498,9 +538,9 @@ vlb_status vlb_read_ownership(vlb_ctx* c, int32_t* count, int32_t* ids,
   if (e == hipSuccess) e = hipMalloc((void**)&di, N * K * sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&df, N * K * sizeof(int));
   PState cur = c->ps[c->pcur];
-  if (e == hipSuccess)
-    e = launch_particles(c->P, cur, cur, c->pc, lists(c), c->partial, 0,
-                         kModeBinOnly, c->flags, c->stream);
+  if (e == hipSuccess && !c->P.scan)
+    e = launch_particles(c->P, cur, cur, c->pc, lists(c), c->partial[c->pp],
+                         0, kModeBinOnly, c->flags, c->stream);
   if (e == hipSuccess)
     e = launch_ownership(c->P, cur, c->pc, lists(c), dc, di, df, c->flags,
                          c->stream);
@@ -527,11 +567,17 @@ struct SaveHeader {
   int64_t step;
 };
 
+static size_t partial_bytes(const vlb_ctx* c) {
+  const size_t slots = c->P.scan ? (size_t)c->np * c->P.nblocks
+                                 : (size_t)c->np * c->maxb;
+  return slots * kRedVals * sizeof(double);
+}
+
 static size_t save_size(const vlb_ctx* c) {
   const size_t N = (size_t)c->P.N;
   return sizeof(SaveHeader) + 2 * 9 * c->plane * c->pop_elem + N * c->h_elem +
          6 * N * 8 + 12 * (size_t)c->np * 8 + (size_t)c->np * 4 +
-         (size_t)c->np * c->maxb * kRedVals * 8;
+         partial_bytes(c);
 }
 
 vlb_status vlb_save(vlb_ctx* c, void* buf, size_t* inout_len) {
@@ -555,13 +601,13 @@ vlb_status vlb_save(vlb_ctx* c, void* buf, size_t* inout_len) {
   const hipMemcpyKind D2H = hipMemcpyDeviceToHost;
   HIP_TRY(c, hipMemcpyAsync(o, c->f[c->cur], pb, D2H, c->stream)); o += pb;
   HIP_TRY(c, hipMemcpyAsync(o, c->g[c->cur], pb, D2H, c->stream)); o += pb;
-  HIP_TRY(c, hipMemcpyAsync(o, c->h, N * c->h_elem, D2H, c->stream)); o += N * c->h_elem;
+  HIP_TRY(c, hipMemcpyAsync(o, c->h[c->cur], N * c->h_elem, D2H, c->stream)); o += N * c->h_elem;
   HIP_TRY(c, hipMemcpyAsync(o, c->macro, 6 * N * 8, D2H, c->stream)); o += 6 * N * 8;
   if (c->np > 0) {
     const size_t n = (size_t)c->np;
     HIP_TRY(c, hipMemcpyAsync(o, c->pmem[c->pcur], 12 * n * 8, D2H, c->stream)); o += 12 * n * 8;
     HIP_TRY(c, hipMemcpyAsync(o, c->pslot[c->pcur], n * 4, D2H, c->stream)); o += n * 4;
-    HIP_TRY(c, hipMemcpyAsync(o, c->partial, n * c->maxb * kRedVals * 8, D2H, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(o, c->partial[c->pp], partial_bytes(c), D2H, c->stream));
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   *inout_len = need;
@@ -587,7 +633,7 @@ vlb_status vlb_load(vlb_ctx* c, const void* buf, size_t len) {
   c->pcur = 0;
   HIP_TRY(c, hipMemcpyAsync(c->f[0], o, pb, H2D, c->stream)); o += pb;
   HIP_TRY(c, hipMemcpyAsync(c->g[0], o, pb, H2D, c->stream)); o += pb;
-  HIP_TRY(c, hipMemcpyAsync(c->h, o, N * c->h_elem, H2D, c->stream)); o += N * c->h_elem;
+  HIP_TRY(c, hipMemcpyAsync(c->h[0], o, N * c->h_elem, H2D, c->stream)); o += N * c->h_elem;
   HIP_TRY(c, hipMemcpyAsync(c->macro, o, 6 * N * 8, H2D, c->stream)); o += 6 * N * 8;
   if (c->np > 0) {
     const size_t n = (size_t)c->np;
@@ -601,7 +647,8 @@ vlb_status vlb_load(vlb_ctx* c, const void* buf, size_t len) {
     }
     HIP_TRY(c, hipMemcpyAsync(c->pmem[0], o, 12 * n * 8, H2D, c->stream)); o += 12 * n * 8;
     HIP_TRY(c, hipMemcpyAsync(c->pslot[0], o, n * 4, H2D, c->stream)); o += n * 4;
-    HIP_TRY(c, hipMemcpyAsync(c->partial, o, n * c->maxb * kRedVals * 8, H2D, c->stream));
+    c->pp = 0;
+    HIP_TRY(c, hipMemcpyAsync(c->partial[0], o, partial_bytes(c), H2D, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->pconst, cst.data(), cst.size() * 8, H2D, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->pfixed, fx.data(), fx.size() * 4, H2D, c->stream));
   }
@@ -652,7 +699,8 @@ void vlb_destroy(vlb_ctx* c) {
     if (c->f[k]) (void)hipFree(c->f[k]);
     if (c->g[k]) (void)hipFree(c->g[k]);
   }
-  if (c->h) (void)hipFree(c->h);
+  for (int k = 0; k < 2; ++k)
+    if (c->h[k]) (void)hipFree(c->h[k]);
   if (c->macro) (void)hipFree(c->macro);
   if (c->blk_cnt) (void)hipFree(c->blk_cnt);
   if (c->blk_ent) (void)hipFree(c->blk_ent);

@@ -13,6 +13,7 @@ constexpr int kBlock = 256;       // cells per lattice block (one per thread)
 constexpr int kListCap = 32;      // particle entries per block list
 constexpr int kMaxRadius = 28;    // band rows of one particle fit one wave
 constexpr int kRedVals = 3;       // Fx, Fy, Tz per partial slot
+constexpr int kScanMax = 64;      // scan form up to this many particles
 
 enum : int {
   kFlagUnstable = 1,    // rho <= 0 or non-finite value in a cell
@@ -38,14 +39,52 @@ struct Params {
   double fadd[4][9];
   double gadd[4][9];
   double gsign[4];
-  // storage shifts of the 16-bit forms (zero otherwise)
+  // storage reference: populations are kept as f_i - w_i rho0s and
+  // g_i - w_i c_ref T0s (both zero for FP64); fshift/gshift = the products
+  double rho0s, cT0s;
   double fshift[9], gshift[9];
   // particles
   double rho_f, grav_x, grav_y;
   double coll_range, coll_pp, coll_pw;
   int wall_face[4];   // 1 where the face is a wall (collisions)
   int np, maxb;
+  int scan;           // 1: scan form (few particles, one launch per step)
+  int maxr;           // scan form: bound on the tiles one particle reaches
 };
+
+// The constants the per-cell arithmetic uses, in the compute precision C
+// (built on the host so the hot path converts nothing).
+template <class C>
+struct Hot {
+  C s_e, s_q, s_p;
+  C cvf, dcv, lamf, dlam, cref, taug_coef, grad_coef;
+  C A0x, A0y, B0x, B0y;
+  C rho0s, cT0s;
+  C fadd[4][9];
+  C gadd[4][9];
+  C gsign[4];
+  int sigma_rule;
+};
+
+template <class C>
+inline Hot<C> make_hot(const Params& P) {
+  Hot<C> H;
+  H.s_e = (C)P.s_e; H.s_q = (C)P.s_q; H.s_p = (C)P.s_p;
+  H.cvf = (C)P.cvf; H.dcv = (C)P.dcv; H.lamf = (C)P.lamf; H.dlam = (C)P.dlam;
+  H.cref = (C)P.cref; H.taug_coef = (C)P.taug_coef;
+  H.grad_coef = (C)(-3.0 / P.cref);   // -6/(4+alpha1)/c_ref, alpha1 = -2
+  H.A0x = (C)P.A0x; H.A0y = (C)P.A0y; H.B0x = (C)P.B0x; H.B0y = (C)P.B0y;
+  H.rho0s = (C)P.rho0s; H.cT0s = (C)P.cT0s;
+  for (int w = 0; w < 4; ++w) {
+    for (int q = 0; q < 9; ++q) {
+      H.fadd[w][q] = (C)P.fadd[w][q];
+      H.gadd[w][q] = (C)P.gadd[w][q];
+    }
+    H.gsign[w] = (C)P.gsign[w];
+  }
+  H.sigma_rule = P.sigma_rule;
+  return H;
+}
 
 // Structure-of-arrays particle state; two copies alternate between steps.
 struct PState {
@@ -63,16 +102,39 @@ struct Lists {
   int2* ent;    // [nblocks][kListCap] (particle id, partial slot)
 };
 
+// Arguments of one lattice launch.  `cur` is the particle state of step n;
+// `nxt` receives step n+1 (scan form) or already holds it (list form).
+// Partials of step n are read from `partial_in`, those of step n+1 written
+// to `partial_out`.  ev_start/ev_stop (may be null) are recorded by the
+// dispatch itself.
+struct LatticeLaunch {
+  const Params* P;
+  bool out;                  // also store the macroscopic fields
+  const void* fi; void* fo;
+  const void* gi; void* go;
+  const void* hin; void* hout;   // [df_s/dt] carrier, step n / step n+1
+  size_t plane;
+  PState cur, nxt;
+  PConst pc;
+  Lists L;
+  const double* partial_in;
+  double* partial_out;
+  int have;                  // partial_in holds a previous step
+  double* macro;
+  int* flags;
+  hipEvent_t ev_start, ev_stop;
+};
+
 // Launchers (defined in vlb_kernels.hip).  All run on `s`.
 hipError_t launch_particles(const Params& P, PState cur, PState next,
-                            PConst pc, Lists L, double* partial,
+                            PConst pc, Lists L, const double* partial,
                             int have_partials, int mode, int* flags,
                             hipStream_t s);
-hipError_t launch_lattice(int prec, bool write_macro, const Params& P,
-                          const void* f_in, void* f_out, const void* g_in,
-                          void* g_out, void* h, size_t plane, PState pn,
-                          PConst pc, Lists L, double* partial, double* macro,
-                          int* flags, hipStream_t s);
+// k_lattice over every cell (events, if given, bracket this launch)
+hipError_t launch_lattice(int prec, const LatticeLaunch& a, hipStream_t s);
+// k_lattice_particles over the tiles particles reach (after launch_lattice)
+hipError_t launch_lattice_particles(int prec, const LatticeLaunch& a,
+                                    hipStream_t s);
 hipError_t launch_init(int prec, const Params& P, void* f, void* g, void* h,
                        size_t plane, PState pn, PConst pc, Lists L,
                        double* macro, int* flags, hipStream_t s);

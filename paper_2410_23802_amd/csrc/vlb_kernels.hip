@@ -10,24 +10,40 @@
 //                       of the eq. dfs_dt recursion (updated in place).
 //   macro             : rho, ux, uy, T, f_s, [df_s/dt] as FP64 planes,
 //                       written only by the last step of a vlb_step call.
-//   block lists       : per 256-cell block, the particles whose band box
-//                       reaches it, with the partial slot to write.
-//   partials          : per particle and touched block, the block's share of
-//                       the momentum-exchange force and torque (FP64).
+//   partials          : FP64 shares of the momentum-exchange force and
+//                       torque, one slot per (particle, 256-cell block).
 //
-// One time step is two launches: k_particles (reduce the partials of the
-// previous step, Newton-Euler update, fill the block lists) and k_lattice
-// (everything per cell, one HBM pass).  No floating-point atomics: every sum
-// runs in a fixed order, so a run is bitwise reproducible.
+// A step is k_lattice -- the fluid lattice over every cell, with no particle
+// code, so it keeps the register budget (and occupancy) of a plain LB
+// kernel -- followed by k_lattice_particles over the 256-cell tiles the
+// particles reach, which recomputes those tiles from the same step-n inputs
+// with the volumetric step and the momentum exchange and overwrites them.
+// The particles themselves are handled in one of two forms:
+//   scan (few particles): each particle tile finds the particles whose band
+//     box reaches it at the new position X + U (forward Euler needs no force
+//     for the position) and rebuilds their new velocities itself from the
+//     previous step's partials -- the same inputs in the same order in every
+//     tile, hence the same bits; the first tile a particle reaches stores its
+//     new state.  Partials [particle][tile].
+//   list (many particles): k_particles first updates every particle (one
+//     wave each) and fills per-tile particle lists.  Partials [particle][k-th
+//     tile reached].
+// No floating-point atomics anywhere: every sum runs in a fixed order, so a
+// run is bitwise reproducible.
 #include <math.h>
+
+#include <hip/hip_ext.h>
 
 #include "vlb_internal.h"
 
 namespace vlb {
 
 // -------------------------------------------------------------------------
-// Storage forms.  FP16/BF16 keep the deviation from a per-direction shift
-// and compute in FP32; the [df_s/dt] carrier stays FP32 there.
+// Storage forms.  Populations are stored as deviations from a fixed
+// per-direction reference (f_i - w_i rho_0, g_i - w_i c_ref T_0) and the
+// kernel computes on deviations, so the low-Mach momentum is never formed
+// by cancelling O(1) numbers.  FP64 uses a zero reference (literal values);
+// FP16/BF16 compute in FP32 and keep the [df_s/dt] carrier in FP32.
 
 template <int PREC>
 struct Prec;
@@ -37,8 +53,8 @@ struct Prec<VLB_FP64> {
   typedef double S;
   typedef double C;
   typedef double H;
-  static __device__ __forceinline__ C ld(const S* p, size_t i, C) { return p[i]; }
-  static __device__ __forceinline__ void st(S* p, size_t i, C v, C) { p[i] = v; }
+  static __device__ __forceinline__ C ld(const S* p, size_t i) { return p[i]; }
+  static __device__ __forceinline__ void st(S* p, size_t i, C v) { p[i] = v; }
 };
 
 template <>
@@ -46,8 +62,8 @@ struct Prec<VLB_FP32> {
   typedef float S;
   typedef float C;
   typedef float H;
-  static __device__ __forceinline__ C ld(const S* p, size_t i, C) { return p[i]; }
-  static __device__ __forceinline__ void st(S* p, size_t i, C v, C) { p[i] = v; }
+  static __device__ __forceinline__ C ld(const S* p, size_t i) { return p[i]; }
+  static __device__ __forceinline__ void st(S* p, size_t i, C v) { p[i] = v; }
 };
 
 template <>
@@ -55,11 +71,11 @@ struct Prec<VLB_FP16_SHIFT> {
   typedef _Float16 S;
   typedef float C;
   typedef float H;
-  static __device__ __forceinline__ C ld(const S* p, size_t i, C sh) {
-    return (float)p[i] + sh;
+  static __device__ __forceinline__ C ld(const S* p, size_t i) {
+    return (float)p[i];
   }
-  static __device__ __forceinline__ void st(S* p, size_t i, C v, C sh) {
-    p[i] = (_Float16)(v - sh);
+  static __device__ __forceinline__ void st(S* p, size_t i, C v) {
+    p[i] = (_Float16)v;
   }
 };
 
@@ -68,12 +84,12 @@ struct Prec<VLB_BF16_SHIFT> {
   typedef uint16_t S;
   typedef float C;
   typedef float H;
-  static __device__ __forceinline__ C ld(const S* p, size_t i, C sh) {
-    return __uint_as_float(((uint32_t)p[i]) << 16) + sh;
+  static __device__ __forceinline__ C ld(const S* p, size_t i) {
+    return __uint_as_float(((uint32_t)p[i]) << 16);
   }
-  static __device__ __forceinline__ void st(S* p, size_t i, C v, C sh) {
+  static __device__ __forceinline__ void st(S* p, size_t i, C v) {
     // round to nearest even on the upper 16 bits
-    uint32_t b = __float_as_uint(v - sh);
+    uint32_t b = __float_as_uint(v);
     b += 0x7fffu + ((b >> 16) & 1u);
     p[i] = (uint16_t)(b >> 16);
   }
@@ -197,453 +213,7 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c,
 }
 
 // -------------------------------------------------------------------------
-// Block particle list: load, sort by particle id, stage the particle data in
-// LDS, and reset the global count for the next particle pass.
-
-struct BlockParticles {
-  int cnt;
-  int pid[kListCap];
-  int slot[kListCap];
-  double X[kListCap], Y[kListCap], R[kListCap];
-  double Ux[kListCap], Uy[kListCap], Om[kListCap], Tp[kListCap];
-};
-
-__device__ __forceinline__ void load_block_list(BlockParticles& bp, int* tmp,
-                                                Lists L, PState pn, PConst pc,
-                                                int* flags) {
-  const int b = blockIdx.x, t = threadIdx.x;
-  if (t == 0) {
-    int n = L.cnt[b];
-    if (n > kListCap) {
-      atomicOr(flags, kFlagListFull);
-      n = kListCap;
-    }
-    bp.cnt = n;
-    L.cnt[b] = 0;  // consumed
-  }
-  __syncthreads();
-  const int n = bp.cnt;
-  if (n == 0) return;
-  int2 e = make_int2(0, 0);
-  if (t < n) {
-    e = L.ent[(size_t)b * kListCap + t];
-    tmp[t] = e.x;
-  }
-  __syncthreads();
-  if (t < n) {
-    int rank = 0;
-    for (int k = 0; k < n; ++k) rank += tmp[k] < e.x;
-    bp.pid[rank] = e.x;
-    bp.slot[rank] = e.y;
-    bp.X[rank] = pn.X[e.x];
-    bp.Y[rank] = pn.Y[e.x];
-    bp.R[rank] = pc.R[e.x];
-    bp.Ux[rank] = pn.Ux[e.x];
-    bp.Uy[rank] = pn.Uy[e.x];
-    bp.Om[rank] = pn.Om[e.x];
-    bp.Tp[rank] = pc.Tinit[e.x];
-  }
-  __syncthreads();
-}
-
-// Geometry of slot s for the cell (i, j): covered share and solid velocity
-// u_s = U + Omega x (x - X) at the node (eq. us).  Returns false when the
-// particle does not reach the cell.
-struct SlotGeom {
-  double fs, usx, usy, rx, ry;
-  bool full;
-};
-
-__device__ __forceinline__ bool slot_geometry(const BlockParticles& bp, int s,
-                                              const Params& P, int i, int j,
-                                              SlotGeom& g) {
-  double xn = (double)i + 0.5, yn = (double)j + 0.5;
-  double X = near_copy(bp.X[s], xn, (double)P.nx, P.perx);
-  double Y = near_copy(bp.Y[s], yn, (double)P.ny, P.pery);
-  double R = bp.R[s];
-  if (!owns_cell(X, Y, R, i, j)) return false;
-  g.full = cell_within(X, Y, R, i, j);
-  g.fs = g.full ? 1.0 : covered_share(X, Y, R, i, j);
-  g.rx = xn - X;
-  g.ry = yn - Y;
-  g.usx = bp.Ux[s] - bp.Om[s] * g.ry;
-  g.usy = bp.Uy[s] + bp.Om[s] * g.rx;
-  return true;
-}
-
-// -------------------------------------------------------------------------
-// The fused lattice pass.
-
-template <int PREC, bool OUT>
-__global__ __launch_bounds__(kBlock) void k_lattice(
-    const Params P, const typename Prec<PREC>::S* __restrict__ fin,
-    typename Prec<PREC>::S* __restrict__ fout,
-    const typename Prec<PREC>::S* __restrict__ gin,
-    typename Prec<PREC>::S* __restrict__ gout,
-    typename Prec<PREC>::H* __restrict__ hcar, size_t plane, PState pn,
-    PConst pc, Lists L, double* __restrict__ partial,
-    double* __restrict__ macro, int* flags) {
-  typedef Prec<PREC> T;
-  typedef typename T::C C;
-  typedef typename T::H H;
-  __shared__ BlockParticles bp;
-  __shared__ int tmp[kListCap];
-  __shared__ double red[4][3];
-
-  load_block_list(bp, tmp, L, pn, pc, flags);
-  const int cnt = bp.cnt;
-
-  const int c = blockIdx.x * kBlock + threadIdx.x;
-  const bool act = c < P.N;
-  const int cc = act ? c : P.N - 1;
-  const int y = cc / P.nx;
-  const int x = cc - y * P.nx;
-
-  // ---- pull streaming with the wall rules (eq. lbe.rho.str, lbe.e.str)
-  int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
-  bool oxm = false, oxp = false, oym = false, oyp = false;
-  if (xm < 0) { if (P.perx) xm += P.nx; else oxm = true; }
-  if (xp >= P.nx) { if (P.perx) xp -= P.nx; else oxp = true; }
-  if (ym < 0) { if (P.pery) ym += P.ny; else oym = true; }
-  if (yp >= P.ny) { if (P.pery) yp -= P.ny; else oyp = true; }
-  const int rx_m = xm, rx_p = xp, ry_m = ym * P.nx, ry_p = yp * P.nx,
-            r0 = y * P.nx;
-  // upstream cell, whether it lies beyond a wall, and which wall decides
-  int src[9];
-  bool out[9];
-  int wall[9];
-  src[0] = cc;                 out[0] = false;          wall[0] = 0;
-  src[1] = r0 + rx_m;          out[1] = oxm;            wall[1] = VLB_FACE_XLO;
-  src[2] = ry_m + x;           out[2] = oym;            wall[2] = VLB_FACE_YLO;
-  src[3] = r0 + rx_p;          out[3] = oxp;            wall[3] = VLB_FACE_XHI;
-  src[4] = ry_p + x;           out[4] = oyp;            wall[4] = VLB_FACE_YHI;
-  src[5] = ry_m + rx_m;        out[5] = oxm || oym;     wall[5] = oym ? VLB_FACE_YLO : VLB_FACE_XLO;
-  src[6] = ry_m + rx_p;        out[6] = oxp || oym;     wall[6] = oym ? VLB_FACE_YLO : VLB_FACE_XHI;
-  src[7] = ry_p + rx_p;        out[7] = oxp || oyp;     wall[7] = oyp ? VLB_FACE_YHI : VLB_FACE_XHI;
-  src[8] = ry_p + rx_m;        out[8] = oxm || oyp;     wall[8] = oyp ? VLB_FACE_YHI : VLB_FACE_XLO;
-  const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-
-  C f[9], g[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const int sq = out[q] ? opp[q] : q;
-    const size_t idx = (size_t)sq * plane + (size_t)(out[q] ? cc : src[q]);
-    C fv = 0, gv = 0;
-    if (act) {
-      fv = T::ld(fin, idx, (C)P.fshift[sq]);
-      gv = T::ld(gin, idx, (C)P.gshift[sq]);
-    }
-    if (out[q]) {
-      const int w = wall[q];
-      fv = fv + (C)P.fadd[w][q];
-      gv = (C)P.gsign[w] * gv + (C)P.gadd[w][q];
-    }
-    f[q] = fv;
-    g[q] = gv;
-  }
-  H hn = act ? hcar[cc] : (H)0;
-
-  // ---- moments of f* (rows of M, Sec. 2.1)
-  const C a14 = f[1] + f[2] + f[3] + f[4];
-  const C a58 = f[5] + f[6] + f[7] + f[8];
-  C m[9];
-  m[0] = f[0] + a14 + a58;
-  m[1] = -4 * f[0] - a14 + 2 * a58;
-  m[2] = 4 * f[0] - 2 * a14 + a58;
-  m[3] = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-  m[4] = -2 * f[1] + 2 * f[3] + f[5] - f[6] - f[7] + f[8];
-  m[5] = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-  m[6] = -2 * f[2] + 2 * f[4] + f[5] + f[6] - f[7] - f[8];
-  m[7] = f[1] - f[2] + f[3] - f[4];
-  m[8] = f[5] - f[6] + f[7] - f[8];
-  const C rho = m[0];          // rho = sum f*_i, kept by eq. fi
-  const C jxs = m[3], jys = m[5];
-
-  // ---- particles: solid fraction, u_s, momentum exchange (Sec. 2.3)
-  C S0 = 0, S1x = 0, S1y = 0, S2xx = 0, S2yy = 0, S2xy = 0;
-  int nin = 0;
-  for (int s = 0; s < cnt; ++s) {
-    double cfx = 0.0, cfy = 0.0, ctz = 0.0;
-    SlotGeom sg;
-    if (act && slot_geometry(bp, s, P, x, y, sg)) {
-      ++nin;
-      const C a = (C)sg.fs, ux = (C)sg.usx, uy = (C)sg.usy;
-      S0 += a;
-      S1x += a * ux;
-      S1y += a * uy;
-      S2xx += a * ux * ux;
-      S2yy += a * uy * uy;
-      S2xy += a * ux * uy;
-      // this particle's share of sum_i (f_i - f*_i) e_i = f_s,p (rho u_s - j*)
-      const double dpx = (double)(a * (rho * ux - jxs));
-      const double dpy = (double)(a * (rho * uy - jys));
-      cfx = -dpx;
-      cfy = -dpy;
-      ctz = -(sg.rx * dpy - sg.ry * dpx);
-    }
-    block_sum3(cfx, cfy, ctz, red);
-    if (threadIdx.x == 0) {
-      double* o = partial + (size_t)bp.slot[s] * kRedVals;
-      o[0] = cfx;
-      o[1] = cfy;
-      o[2] = ctz;
-    }
-  }
-  if (nin > P.kmax) atomicOr(flags, kFlagOverlap);
-  // Overlapping disks: shares are scaled to sum to one (rare path; the
-  // momentum-exchange partials get the matching correction).
-  if (cnt > 0 && __syncthreads_or(S0 > (C)1)) {
-    const bool over = S0 > (C)1;
-    const C inv = over ? (C)1 / S0 : (C)1;
-    for (int s = 0; s < cnt; ++s) {
-      double cfx = 0.0, cfy = 0.0, ctz = 0.0;
-      SlotGeom sg;
-      if (act && over && slot_geometry(bp, s, P, x, y, sg)) {
-        const C a = (C)sg.fs, ux = (C)sg.usx, uy = (C)sg.usy;
-        const double k = (double)(inv - (C)1);
-        const double dpx = (double)(a * (rho * ux - jxs));
-        const double dpy = (double)(a * (rho * uy - jys));
-        cfx = -dpx * k;
-        cfy = -dpy * k;
-        ctz = -(sg.rx * dpy - sg.ry * dpx) * k;
-      }
-      block_sum3(cfx, cfy, ctz, red);
-      if (threadIdx.x == 0) {
-        double* o = partial + (size_t)bp.slot[s] * kRedVals;
-        o[0] += cfx;
-        o[1] += cfy;
-        o[2] += ctz;
-      }
-    }
-    if (over) {
-      S1x *= inv; S1y *= inv; S2xx *= inv; S2yy *= inv; S2xy *= inv;
-      S0 = (C)1;
-    }
-  }
-
-  // ---- volumetric no-slip step in moment space (eq. fi):
-  // m = (1 - f_s) M f* + rho * sum_p f_s,p m^eq(1, u_s,p)
-  const C fs = S0;
-  const C wf = (C)1 - fs;
-  {
-    const C tr = S2xx + S2yy;
-    m[0] = wf * m[0] + rho * S0;
-    m[1] = wf * m[1] + rho * (-2 * S0 + 3 * tr);
-    m[2] = wf * m[2] + rho * (S0 - 3 * tr);
-    m[3] = wf * m[3] + rho * S1x;
-    m[4] = wf * m[4] - rho * S1x;
-    m[5] = wf * m[5] + rho * S1y;
-    m[6] = wf * m[6] - rho * S1y;
-    m[7] = wf * m[7] + rho * (S2xx - S2yy);
-    m[8] = wf * m[8] + rho * S2xy;
-  }
-
-  // ---- [df_s/dt] by eq. dfs_dt through the carrier h = 2 f_s + d:
-  // d^{n+1} = 2 f_s^{n+1} - h^n,  h^{n+1} = 2 f_s^{n+1} + d^{n+1}
-  const C dfs = 2 * fs - (C)hn;
-  const H hnew = (H)(2 * fs + dfs);
-
-  // ---- per-cell properties (Sec. 2.2) and relaxation rates (Sec. 3)
-  const C cv = (C)P.cvf + (C)P.dcv * fs;
-  const C lam = (C)P.lamf + (C)P.dlam * fs;
-  const C tau_g = (C)0.5 + (C)P.taug_coef * lam;
-  const C sig_j = (C)1 / tau_g;
-  // (1/sig_j - 1/2)(1/sig_e - 1/2) = 1/4 is sig_e = 2 - sig_j
-  const C sig_e = P.sigma_rule == 0 ? (C)2 - sig_j : (C)1;
-
-  // ---- energy moments and the local temperature gradient (Sec. 2.2)
-  const C b14 = g[1] + g[2] + g[3] + g[4];
-  const C b58 = g[5] + g[6] + g[7] + g[8];
-  C n[9];
-  n[0] = g[0] + b14 + b58;
-  n[1] = -4 * g[0] - b14 + 2 * b58;
-  n[2] = 4 * g[0] - 2 * b14 + b58;
-  n[3] = g[1] - g[3] + g[5] - g[6] - g[7] + g[8];
-  n[4] = -2 * g[1] + 2 * g[3] + g[5] - g[6] - g[7] + g[8];
-  n[5] = g[2] - g[4] + g[5] + g[6] - g[7] - g[8];
-  n[6] = -2 * g[2] + 2 * g[4] + g[5] + g[6] - g[7] - g[8];
-  n[7] = g[1] - g[2] + g[3] - g[4];
-  n[8] = g[5] - g[6] + g[7] - g[8];
-  const C gcoef = (C)(-3.0) * sig_j / (C)P.cref;   // -6/(4+alpha1) / (c_ref tau_g)
-  const C gTx = gcoef * n[3], gTy = gcoef * n[5];
-
-  // ---- coupled macroscopic solve: u from eq. rho.rhou with F = a + b T,
-  // T from the implicit relation of Sec. 2.2 (linear in T)
-  const C ax = wf * (C)P.A0x, ay = wf * (C)P.A0y;
-  const C bx = wf * (C)P.B0x, by = wf * (C)P.B0y;
-  const C irho = (C)1 / rho;
-  const C jx = m[3], jy = m[5];
-  const C num = n[0] - (C)0.5 * cv * ((jx + (C)0.5 * ax) * gTx + (jy + (C)0.5 * ay) * gTy) * irho;
-  const C den = cv - (C)0.5 * (C)P.dcv * dfs + (C)0.25 * cv * (bx * gTx + by * gTy) * irho;
-  const C Tc = num / den;
-  const C Fx = ax + bx * Tc, Fy = ay + by * Tc;
-  const C ux = (jx + (C)0.5 * Fx) * irho, uy = (jy + (C)0.5 * Fy) * irho;
-  const C eps = cv * Tc;
-  const C qc = -cv * (ux * gTx + uy * gTy) + (C)P.dcv * Tc * dfs;
-
-  if (act && !(rho > (C)0 && isfinite(Tc) && isfinite(ux) && isfinite(uy)))
-    atomicOr(flags, kFlagUnstable);
-
-  // ---- flow collision with the discrete force term (eq. lbe.rho.col)
-  {
-    const C u2 = ux * ux + uy * uy;
-    const C se = (C)P.s_e, sq = (C)P.s_q, sp = (C)P.s_p;
-    const C Fu = Fx * ux + Fy * uy;
-    C mb[9];
-    mb[0] = rho;
-    mb[1] = m[1] - se * (m[1] - (-2 * rho + 3 * rho * u2)) + ((C)1 - (C)0.5 * se) * (6 * Fu);
-    mb[2] = m[2] - se * (m[2] - (rho - 3 * rho * u2)) + ((C)1 - (C)0.5 * se) * (-6 * Fu);
-    mb[3] = rho * ux + (C)0.5 * Fx;
-    mb[4] = m[4] - sq * (m[4] + rho * ux) + ((C)1 - (C)0.5 * sq) * (-Fx);
-    mb[5] = rho * uy + (C)0.5 * Fy;
-    mb[6] = m[6] - sq * (m[6] + rho * uy) + ((C)1 - (C)0.5 * sq) * (-Fy);
-    mb[7] = m[7] - sp * (m[7] - rho * (ux * ux - uy * uy)) + ((C)1 - (C)0.5 * sp) * (2 * (Fx * ux - Fy * uy));
-    mb[8] = m[8] - sp * (m[8] - rho * ux * uy) + ((C)1 - (C)0.5 * sp) * (Fx * uy + Fy * ux);
-    // M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
-    const C k0 = mb[0] / 9, k1 = mb[1] / 36, k2 = mb[2] / 36, k3 = mb[3] / 6,
-            k4 = mb[4] / 12, k5 = mb[5] / 6, k6 = mb[6] / 12, k7 = mb[7] / 4,
-            k8 = mb[8] / 4;
-    C o[9];
-    o[0] = k0 - 4 * k1 + 4 * k2;
-    const C ax_ = k0 - k1 - 2 * k2;
-    o[1] = ax_ + k3 - 2 * k4 + k7;
-    o[2] = ax_ + k5 - 2 * k6 - k7;
-    o[3] = ax_ - k3 + 2 * k4 + k7;
-    o[4] = ax_ - k5 + 2 * k6 - k7;
-    const C dg = k0 + 2 * k1 + k2;
-    o[5] = dg + k3 + k4 + k5 + k6 + k8;
-    o[6] = dg - k3 - k4 + k5 + k6 - k8;
-    o[7] = dg - k3 - k4 - k5 - k6 + k8;
-    o[8] = dg + k3 + k4 - k5 - k6 - k8;
-    if (act) {
-#pragma unroll
-      for (int q = 0; q < 9; ++q)
-        T::st(fout, (size_t)q * plane + cc, o[q], (C)P.fshift[q]);
-    }
-  }
-
-  // ---- energy collision with the discrete source term (eq. lbe.e.col):
-  // n^eq = [eps, -4 eps + 2 c_ref T, 4 eps - 3 c_ref T, 0...] (alpha1 = -2,
-  // alpha2 = 1), q_m = [q, -4 q, 4 q, 0...] (beta1 = -4, beta2 = 4),
-  // R = diag(1, se, se, sj, sj, sj, sj, se, se)
-  {
-    const C cT = (C)P.cref * Tc;
-    C nb[9];
-    nb[0] = eps + (C)0.5 * qc;
-    nb[1] = n[1] - sig_e * (n[1] - (-4 * eps + 2 * cT)) + ((C)1 - (C)0.5 * sig_e) * (-4 * qc);
-    nb[2] = n[2] - sig_e * (n[2] - (4 * eps - 3 * cT)) + ((C)1 - (C)0.5 * sig_e) * (4 * qc);
-    const C rj = (C)1 - sig_j, re = (C)1 - sig_e;
-    nb[3] = rj * n[3];
-    nb[4] = rj * n[4];
-    nb[5] = rj * n[5];
-    nb[6] = rj * n[6];
-    nb[7] = re * n[7];
-    nb[8] = re * n[8];
-    const C k0 = nb[0] / 9, k1 = nb[1] / 36, k2 = nb[2] / 36, k3 = nb[3] / 6,
-            k4 = nb[4] / 12, k5 = nb[5] / 6, k6 = nb[6] / 12, k7 = nb[7] / 4,
-            k8 = nb[8] / 4;
-    C o[9];
-    o[0] = k0 - 4 * k1 + 4 * k2;
-    const C ax_ = k0 - k1 - 2 * k2;
-    o[1] = ax_ + k3 - 2 * k4 + k7;
-    o[2] = ax_ + k5 - 2 * k6 - k7;
-    o[3] = ax_ - k3 + 2 * k4 + k7;
-    o[4] = ax_ - k5 + 2 * k6 - k7;
-    const C dg = k0 + 2 * k1 + k2;
-    o[5] = dg + k3 + k4 + k5 + k6 + k8;
-    o[6] = dg - k3 - k4 + k5 + k6 - k8;
-    o[7] = dg - k3 - k4 - k5 - k6 + k8;
-    o[8] = dg + k3 + k4 - k5 - k6 - k8;
-    if (act) {
-#pragma unroll
-      for (int q = 0; q < 9; ++q)
-        T::st(gout, (size_t)q * plane + cc, o[q], (C)P.gshift[q]);
-      hcar[cc] = hnew;
-    }
-  }
-
-  if (OUT && act) {
-    const size_t N = (size_t)P.N;
-    macro[cc] = (double)rho;
-    macro[N + cc] = (double)ux;
-    macro[2 * N + cc] = (double)uy;
-    macro[3 * N + cc] = (double)Tc;
-    macro[4 * N + cc] = (double)fs;
-    macro[5 * N + cc] = (double)dfs;
-  }
-}
-
-// -------------------------------------------------------------------------
-// Initial state: equilibria of the mixed fluid/particle state per cell.
-
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_init(
-    const Params P, typename Prec<PREC>::S* __restrict__ fo,
-    typename Prec<PREC>::S* __restrict__ go,
-    typename Prec<PREC>::H* __restrict__ hcar, size_t plane, PState pn,
-    PConst pc, Lists L, double* __restrict__ macro, int* flags) {
-  typedef Prec<PREC> T;
-  typedef typename T::C C;
-  __shared__ BlockParticles bp;
-  __shared__ int tmp[kListCap];
-  load_block_list(bp, tmp, L, pn, pc, flags);
-  const int c = blockIdx.x * kBlock + threadIdx.x;
-  if (c >= P.N) return;
-  const int y = c / P.nx, x = c - y * P.nx;
-  double S0 = 0, Sx = 0, Sy = 0, Se = 0;
-  int nin = 0;
-  for (int s = 0; s < bp.cnt; ++s) {
-    SlotGeom sg;
-    if (slot_geometry(bp, s, P, x, y, sg)) {
-      ++nin;
-      S0 += sg.fs;
-      Sx += sg.fs * sg.usx;
-      Sy += sg.fs * sg.usy;
-      Se += sg.fs * P.cvs * bp.Tp[s];
-    }
-  }
-  if (nin > P.kmax) atomicOr(flags, kFlagOverlap);
-  if (S0 > 1.0) {
-    const double inv = 1.0 / S0;
-    Sx *= inv;
-    Sy *= inv;
-    Se *= inv;
-    S0 = 1.0;
-  }
-  const double fs = S0;
-  const double ux = (1.0 - fs) * P.init_ux + Sx;
-  const double uy = (1.0 - fs) * P.init_uy + Sy;
-  const double eps = (1.0 - fs) * P.cvf * P.init_T + Se;
-  const double cv = P.cvf + P.dcv * fs;
-  const double Tt = eps / cv;
-  const double rho = P.init_rho;
-  // f^eq = w_i rho [1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u^2] (= M^{-1} m^eq);
-  // g^eq_i = w_i c_ref T (i >= 1), g^eq_0 = eps - 5/9 c_ref T (= M^{-1} n^eq)
-  const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                       1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-  const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-  const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-  const double u2 = ux * ux + uy * uy;
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const double eu = ex[q] * ux + ey[q] * uy;
-    const double feq = w[q] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * u2);
-    const double geq = q == 0 ? eps - (5.0 / 9.0) * P.cref * Tt : w[q] * P.cref * Tt;
-    T::st(fo, (size_t)q * plane + c, (C)feq, (C)P.fshift[q]);
-    T::st(go, (size_t)q * plane + c, (C)geq, (C)P.gshift[q]);
-  }
-  hcar[c] = (typename T::H)(2.0 * fs);
-  const size_t N = (size_t)P.N;
-  macro[c] = rho;
-  macro[N + c] = ux;
-  macro[2 * N + c] = uy;
-  macro[3 * N + c] = Tt;
-  macro[4 * N + c] = fs;
-  macro[5 * N + c] = 0.0;
-}
-
-// -------------------------------------------------------------------------
-// Particle pass: one wave (64 lanes) per particle.
+// Band boxes and block bookkeeping.
 
 __device__ __forceinline__ int wave_excl_scan(int v, int lane) {
   int incl = v;
@@ -726,21 +296,103 @@ __device__ __forceinline__ int row_blocks(int row, const ColSegs& cs, int nx,
   return n;
 }
 
-// Reduce the partials written by the previous lattice pass, update the
-// particle (Newton-Euler, Sec. 2.3) and append it to the lists of the blocks
-// its band box touches.  Modes: update, reduce only, bin only.
-__global__ __launch_bounds__(256) void k_particles(
-    const Params P, PState cur, PState next, PConst pc, Lists L,
-    double* __restrict__ partial, int have_partials, int mode, int* flags) {
-  const int lane = threadIdx.x & 63;
-  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (p >= P.np) return;  // whole wave
 
-  double nX = cur.X[p], nY = cur.Y[p];
-  if (mode != kModeBinOnly) {
-    // ---- momentum-exchange force and torque: sum over the touched blocks
-    double fx = 0.0, fy = 0.0, tz = 0.0;
-    if (have_partials) {
+// -------------------------------------------------------------------------
+// Particle helpers shared by both forms.
+
+// Forward Euler of the position (Sec. 2.3): X^{n+1} = X^n + U^n, wrapped
+// into [0, L) on periodic axes.
+__device__ __forceinline__ void advance_position(const Params& P, double& X,
+                                                 double& Y, double Ux,
+                                                 double Uy) {
+  X = X + Ux;
+  Y = Y + Uy;
+  if (P.perx) {
+    if (X >= (double)P.nx) X -= (double)P.nx;
+    if (X < 0.0) X += (double)P.nx;
+  }
+  if (P.pery) {
+    if (Y >= (double)P.ny) Y -= (double)P.ny;
+    if (Y < 0.0) Y += (double)P.ny;
+  }
+}
+
+// The units of `unit` consecutive cells (64: a wave, 256: a block) a
+// particle's band box reaches: at most two ascending, disjoint ranges (two
+// when the box wraps around a periodic y axis).  Every cell of the box lies
+// in a listed unit.
+struct BlockRanges {
+  int n;
+  int lo[2], hi[2];
+  __device__ __forceinline__ int count() const {
+    return n == 0 ? 0
+                  : (hi[0] - lo[0] + 1) + (n > 1 ? hi[1] - lo[1] + 1 : 0);
+  }
+  __device__ __forceinline__ int at(int k) const {
+    const int l0 = hi[0] - lo[0] + 1;
+    return k < l0 ? lo[0] + k : lo[1] + (k - l0);
+  }
+  __device__ __forceinline__ bool contains(int b) const {
+    return (n > 0 && b >= lo[0] && b <= hi[0]) ||
+           (n > 1 && b >= lo[1] && b <= hi[1]);
+  }
+};
+
+__device__ BlockRanges block_ranges(const Params& P, double X, double Y,
+                                    double R, int unit) {
+  BlockRanges r;
+  r.n = 0;
+  r.lo[0] = r.lo[1] = 0;
+  r.hi[0] = r.hi[1] = -1;
+  if (!centre_ok(P, X, Y)) return r;
+  int i0, i1, j0, j1;
+  band_box(P, X, Y, R, i0, i1, j0, j1);
+  if (i1 < i0 || j1 < j0) return r;
+  int a0[2] = {j0, 0}, a1[2] = {j1, -1}, na = 1;
+  if (P.pery && j0 < 0) {          // rows 0..j1 and j0+ny..ny-1
+    na = 2; a0[0] = 0; a1[0] = j1; a0[1] = j0 + P.ny; a1[1] = P.ny - 1;
+  } else if (P.pery && j1 >= P.ny) {  // rows 0..j1-ny and j0..ny-1
+    na = 2; a0[0] = 0; a1[0] = j1 - P.ny; a0[1] = j0; a1[1] = P.ny - 1;
+  }
+  const bool xfull = P.perx && (i0 < 0 || i1 >= P.nx);
+  const int ca = xfull ? 0 : i0, cb = xfull ? P.nx - 1 : i1;
+  for (int k = 0; k < na; ++k) {
+    r.lo[k] = (a0[k] * P.nx + ca) / unit;
+    r.hi[k] = (a1[k] * P.nx + cb) / unit;
+  }
+  r.n = na;
+  if (na == 2 && r.hi[0] >= r.lo[1]) {  // the two ranges touch: merge
+    r.hi[0] = max(r.hi[0], r.hi[1]);
+    r.n = 1;
+  }
+  return r;
+}
+
+// Momentum-exchange force and torque of particle p: the sum of the partials
+// the last lattice pass wrote, lanes striding the slots, then an xor
+// butterfly (every lane ends with the same bits).
+__device__ __forceinline__ void reduce_partials(const Params& P,
+                                                const PState& cur,
+                                                const PConst& pc,
+                                                const double* partial,
+                                                int have, int p, int lane,
+                                                double& fx, double& fy,
+                                                double& tz) {
+  fx = fy = tz = 0.0;
+  if (have) {
+    if (P.scan) {
+      // scan form: one slot per (particle, 256-cell tile)
+      const BlockRanges r =
+          block_ranges(P, cur.X[p], cur.Y[p], pc.R[p], kBlock);
+      const int nb = r.count();
+      const double* src = partial + (size_t)p * P.nblocks * kRedVals;
+      for (int k = lane; k < nb; k += 64) {
+        const double* o = src + (size_t)r.at(k) * kRedVals;
+        fx += o[0];
+        fy += o[1];
+        tz += o[2];
+      }
+    } else {
       const int ns = cur.nslot[p];
       const double* src = partial + (size_t)p * P.maxb * kRedVals;
       for (int k = lane; k < ns; k += 64) {
@@ -749,96 +401,784 @@ __global__ __launch_bounds__(256) void k_particles(
         tz += src[k * kRedVals + 2];
       }
     }
-    fx = wave_sum(fx);
-    fy = wave_sum(fy);
-    tz = wave_sum(tz);
+  }
+  fx = wave_sum(fx);
+  fy = wave_sum(fy);
+  tz = wave_sum(tz);
+}
+
+// Repulsion on particle p (the collision model the paper adopts): a
+// short-range force of range zeta, k ((R_p + R_q + zeta - d)/zeta)^2 along
+// the centre line, and against each wall the same law applied to the
+// particle's mirror image.  Positions of step n.  Every lane returns the
+// same bits.
+__device__ __forceinline__ void repulsion(const Params& P, const PState& cur,
+                                          const PConst& pc, int p, int lane,
+                                          double& cx, double& cy) {
+  cx = cy = 0.0;
+  const double zeta = P.coll_range;
+  if (!(zeta > 0.0)) return;
+  const double Xp = cur.X[p], Yp = cur.Y[p], Rp = pc.R[p];
+  for (int q = lane; q < P.np; q += 64) {
+    if (q == p) continue;
+    const double dx = Xp - near_copy(cur.X[q], Xp, (double)P.nx, P.perx);
+    const double dy = Yp - near_copy(cur.Y[q], Yp, (double)P.ny, P.pery);
+    const double d = sqrt(dx * dx + dy * dy);
+    const double reach = Rp + pc.R[q] + zeta;
+    if (d < reach && d > 0.0) {
+      const double s = (reach - d) / zeta;
+      const double mag = P.coll_pp * s * s / d;
+      cx += mag * dx;
+      cy += mag * dy;
+    }
+  }
+  cx = wave_sum(cx);
+  cy = wave_sum(cy);
+  const double dist[4] = {Xp, (double)P.nx - Xp, Yp, (double)P.ny - Yp};
+  const double nrmx[4] = {1.0, -1.0, 0.0, 0.0};
+  const double nrmy[4] = {0.0, 0.0, 1.0, -1.0};
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    if (!P.wall_face[w]) continue;
+    const double d = 2.0 * dist[w], reach = 2.0 * Rp + zeta;
+    if (d < reach) {
+      const double s = (reach - d) / zeta;
+      cx += P.coll_pw * s * s * nrmx[w];
+      cy += P.coll_pw * s * s * nrmy[w];
+    }
+  }
+}
+
+struct PUpd {
+  double X, Y, th, Ux, Uy, Om, Uxp, Uyp, Omp, Fx, Fy, Tz;
+};
+
+// One step of particle p, wave-level (every lane returns the same bits):
+// Newton-Euler (eq. particle; the gyroscopic term vanishes in 2-D) with the
+// inside-fluid correction of eq. inside.fluid by backward differences,
+// total force = hydrodynamic + (rho_s - rho_f) V g + repulsion, forward
+// Euler (Sec. 2.3 end).
+__device__ PUpd particle_update(const Params& P, const PState& cur,
+                                const PConst& pc, const double* partial,
+                                int have, int p, int lane) {
+  double fx, fy, tz, cx, cy;
+  reduce_partials(P, cur, pc, partial, have, p, lane, fx, fy, tz);
+  repulsion(P, cur, pc, p, lane, cx, cy);
+  PUpd u;
+  const double R = pc.R[p], rs = pc.rhos[p];
+  const double V = M_PI * R * R;
+  const double M = rs * V, I = 0.5 * M * R * R;
+  const double Min = P.rho_f * M / rs, Iin = P.rho_f * I / rs;
+  const double Ux = cur.Ux[p], Uy = cur.Uy[p], Om = cur.Om[p];
+  u.Ux = Ux;
+  u.Uy = Uy;
+  u.Om = Om;
+  if (!pc.fixed[p]) {
+    const double Finx = -Min * (Ux - cur.Uxp[p]);
+    const double Finy = -Min * (Uy - cur.Uyp[p]);
+    const double Tin = -Iin * (Om - cur.Omp[p]);
+    const double Fcx = (fx - Finx) + (rs - P.rho_f) * V * P.grav_x + cx;
+    const double Fcy = (fy - Finy) + (rs - P.rho_f) * V * P.grav_y + cy;
+    u.Ux = Ux + Fcx / M;
+    u.Uy = Uy + Fcy / M;
+    u.Om = Om + (tz - Tin) / I;
+  }
+  u.X = cur.X[p];
+  u.Y = cur.Y[p];
+  advance_position(P, u.X, u.Y, Ux, Uy);
+  u.th = cur.th[p] + Om;
+  u.Uxp = Ux;
+  u.Uyp = Uy;
+  u.Omp = Om;
+  u.Fx = fx;
+  u.Fy = fy;
+  u.Tz = tz;
+  return u;
+}
+
+__device__ __forceinline__ void store_particle(PState& s, int p,
+                                               const PUpd& u) {
+  s.X[p] = u.X; s.Y[p] = u.Y; s.th[p] = u.th;
+  s.Ux[p] = u.Ux; s.Uy[p] = u.Uy; s.Om[p] = u.Om;
+  s.Uxp[p] = u.Uxp; s.Uyp[p] = u.Uyp; s.Omp[p] = u.Omp;
+  s.Fx[p] = u.Fx; s.Fy[p] = u.Fy; s.Tz[p] = u.Tz;
+}
+
+// -------------------------------------------------------------------------
+// Block particle list: load, sort by particle id, stage the particle data in
+// LDS, and reset the global count for the next particle pass.
+
+struct BlockParticles {
+  int cnt;
+  int pid[kListCap];
+  int slot[kListCap];
+  double X[kListCap], Y[kListCap], R[kListCap];
+  double Ux[kListCap], Uy[kListCap], Om[kListCap], Tp[kListCap];
+};
+
+__device__ __forceinline__ void load_block_list(BlockParticles& bp, int* tmp,
+                                                Lists L, int b, PState pn,
+                                                PConst pc, int* flags) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    int n = L.cnt[b];
+    if (n > kListCap) {
+      atomicOr(flags, kFlagListFull);
+      n = kListCap;
+    }
+    bp.cnt = n;
+    L.cnt[b] = 0;  // consumed
+  }
+  __syncthreads();
+  const int n = bp.cnt;
+  if (n == 0) return;
+  int2 e = make_int2(0, 0);
+  if (t < n) {
+    e = L.ent[(size_t)b * kListCap + t];
+    tmp[t] = e.x;
+  }
+  __syncthreads();
+  if (t < n) {
+    int rank = 0;
+    for (int k = 0; k < n; ++k) rank += tmp[k] < e.x;
+    bp.pid[rank] = e.x;
+    bp.slot[rank] = e.y;
+    bp.X[rank] = pn.X[e.x];
+    bp.Y[rank] = pn.Y[e.x];
+    bp.R[rank] = pc.R[e.x];
+    bp.Ux[rank] = pn.Ux[e.x];
+    bp.Uy[rank] = pn.Uy[e.x];
+    bp.Om[rank] = pn.Om[e.x];
+    bp.Tp[rank] = pc.Tinit[e.x];
+  }
+  __syncthreads();
+}
+
+// Geometry of slot s for the cell (i, j): covered share and solid velocity
+// u_s = U + Omega x (x - X) at the node (eq. us).  Returns false when the
+// particle does not reach the cell.
+struct SlotGeom {
+  double fs, usx, usy, rx, ry;
+  bool full;
+};
+
+__device__ __forceinline__ bool slot_geometry(const BlockParticles& bp, int s,
+                                              const Params& P, int i, int j,
+                                              SlotGeom& g) {
+  double xn = (double)i + 0.5, yn = (double)j + 0.5;
+  double X = near_copy(bp.X[s], xn, (double)P.nx, P.perx);
+  double Y = near_copy(bp.Y[s], yn, (double)P.ny, P.pery);
+  double R = bp.R[s];
+  if (!owns_cell(X, Y, R, i, j)) return false;
+  g.full = cell_within(X, Y, R, i, j);
+  g.fs = g.full ? 1.0 : covered_share(X, Y, R, i, j);
+  g.rx = xn - X;
+  g.ry = yn - Y;
+  g.usx = bp.Ux[s] - bp.Om[s] * g.ry;
+  g.usy = bp.Uy[s] + bp.Om[s] * g.rx;
+  return true;
+}
+
+
+// Scan form: gather the particles that reach tile b.  With `advance` (a
+// lattice step) their positions are X + U and their velocities are rebuilt
+// from the previous step's partials, and the first tile a particle reaches
+// stores its new state in `next`; without it (init, ownership) the stored
+// state is used.  Needs P.np <= 64.
+__device__ void scan_block(BlockParticles& bp, const Params& P, int b,
+                           PState cur, PState next, PConst pc,
+                           const double* partial, int have, bool advance,
+                           int* flags) {
+  __shared__ int s_nwork;
+  __shared__ int s_work_pid[64], s_work_rank[64], s_work_store[64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if (wave == 0) {
+    bool cand = false, store = false;
+    double X = 0.0, Y = 0.0;
+    if (lane < P.np) {
+      X = cur.X[lane];
+      Y = cur.Y[lane];
+      if (advance) advance_position(P, X, Y, cur.Ux[lane], cur.Uy[lane]);
+      const BlockRanges r = block_ranges(P, X, Y, pc.R[lane], kBlock);
+      cand = r.contains(b);
+      if (r.n == 0 && b == 0) atomicOr(flags, kFlagUnstable);
+      store = advance && (r.n > 0 ? b == r.lo[0] : b == 0);
+    }
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const unsigned long long mc = __ballot(cand);
+    const int rank = __popcll(mc & below);
+    if (cand) {
+      bp.pid[rank] = lane;
+      bp.slot[rank] = lane * P.nblocks + b;
+      bp.X[rank] = X;
+      bp.Y[rank] = Y;
+      bp.R[rank] = pc.R[lane];
+      bp.Tp[rank] = pc.Tinit[lane];
+    }
+    const unsigned long long mw = __ballot(cand || store);
+    const int wrank = __popcll(mw & below);
+    if (cand || store) {
+      s_work_pid[wrank] = lane;
+      s_work_rank[wrank] = cand ? rank : -1;
+      s_work_store[wrank] = store ? 1 : 0;
+    }
+    if (lane == 0) {
+      bp.cnt = __popcll(mc);
+      s_nwork = __popcll(mw);
+    }
+  }
+  __syncthreads();
+  const int nwork = s_nwork;
+  for (int k = wave; k < nwork; k += 4) {
+    const int p = s_work_pid[k], r = s_work_rank[k];
+    if (advance) {
+      const PUpd u = particle_update(P, cur, pc, partial, have, p, lane);
+      if (lane == 0) {
+        if (r >= 0) {
+          bp.Ux[r] = u.Ux;
+          bp.Uy[r] = u.Uy;
+          bp.Om[r] = u.Om;
+        }
+        if (s_work_store[k]) store_particle(next, p, u);
+      }
+    } else if (lane == 0 && r >= 0) {
+      bp.Ux[r] = cur.Ux[p];
+      bp.Uy[r] = cur.Uy[p];
+      bp.Om[r] = cur.Om[p];
+    }
+  }
+  __syncthreads();
+}
+
+// Geometry of a particle (centre X, Y, radius R, velocity U, Omega) for the
+// cell (i, j): covered share and solid velocity u_s = U + Omega x (x - X) at
+// the node (eq. us).  False when the particle does not reach the cell.
+__device__ __forceinline__ bool particle_geometry(const Params& P, double Xp,
+                                                  double Yp, double R,
+                                                  double Ux, double Uy,
+                                                  double Om, int i, int j,
+                                                  SlotGeom& g) {
+  const double xn = (double)i + 0.5, yn = (double)j + 0.5;
+  const double X = near_copy(Xp, xn, (double)P.nx, P.perx);
+  const double Y = near_copy(Yp, yn, (double)P.ny, P.pery);
+  if (!owns_cell(X, Y, R, i, j)) return false;
+  g.full = cell_within(X, Y, R, i, j);
+  g.fs = g.full ? 1.0 : covered_share(X, Y, R, i, j);
+  g.rx = xn - X;
+  g.ry = yn - Y;
+  g.usx = Ux - Om * g.ry;
+  g.usy = Uy + Om * g.rx;
+  return true;
+}
+
+template <bool SCAN>
+__device__ __forceinline__ void gather_particles(
+    BlockParticles& bp, int* tmp, const Params& P, PState cur, PState next,
+    PConst pc, Lists L, const double* partial, int have, bool advance,
+    int* flags) {
+  if (SCAN)
+    scan_block(bp, P, blockIdx.x, cur, next, pc, partial, have, advance,
+               flags);
+  else
+    load_block_list(bp, tmp, L, blockIdx.x, advance ? next : cur, pc, flags);
+}
+
+// -------------------------------------------------------------------------
+// The fused lattice pass.
+
+// Pull of direction Q for the cell: the upstream value, or -- when the
+// upstream cell lies beyond a wall -- the rule of that wall applied to the
+// opposite population of the cell itself.  XS/YS name the wall met across
+// the x / y side (-1: none); when both apply (a corner) the y wall decides.
+// Branch-free: one load from a selected address, then selects of
+// compile-time-indexed wall constants.
+template <int Q, int OPP, int XS, int YS, class T>
+__device__ __forceinline__ void pull(const typename T::S* __restrict__ fin,
+                                     const typename T::S* __restrict__ gin,
+                                     size_t plane, int cc, int src, bool ox,
+                                     bool oy, const Hot<typename T::C>& H,
+                                     typename T::C& fv, typename T::C& gv) {
+  typedef typename T::C C;
+  const bool out = (XS >= 0 && ox) || (YS >= 0 && oy);
+  const size_t idx = out ? (size_t)OPP * plane + cc : (size_t)Q * plane + src;
+  C f = T::ld(fin, idx), g = T::ld(gin, idx);
+  if (XS >= 0 || YS >= 0) {
+    constexpr int WX = XS >= 0 ? XS : YS, WY = YS >= 0 ? YS : XS;
+    const bool useY = YS >= 0 && oy;
+    const C fa = useY ? H.fadd[WY][Q] : H.fadd[WX][Q];
+    const C ga = useY ? H.gadd[WY][Q] : H.gadd[WX][Q];
+    const C gs = useY ? H.gsign[WY] : H.gsign[WX];
+    f = out ? f + fa : f;
+    g = out ? gs * g + ga : g;
+  }
+  fv = f;
+  gv = g;
+}
+
+// M f for D2Q9 (rows of M, Sec. 2.1).
+template <class C>
+__device__ __forceinline__ void moments(const C* f, C* m) {
+  const C a14 = f[1] + f[2] + f[3] + f[4];
+  const C a58 = f[5] + f[6] + f[7] + f[8];
+  m[0] = f[0] + a14 + a58;
+  m[1] = -4 * f[0] - a14 + 2 * a58;
+  m[2] = 4 * f[0] - 2 * a14 + a58;
+  const C b57 = f[5] - f[7], b68 = f[6] - f[8];
+  m[3] = f[1] - f[3] + b57 - b68;
+  m[4] = -2 * (f[1] - f[3]) + b57 - b68;
+  m[5] = f[2] - f[4] + b57 + b68;
+  m[6] = -2 * (f[2] - f[4]) + b57 + b68;
+  m[7] = f[1] - f[2] + f[3] - f[4];
+  m[8] = f[5] - f[6] + f[7] - f[8];
+}
+
+// M^{-1} m = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m
+// (the rows of M are orthogonal with those squared norms).
+template <class C>
+__device__ __forceinline__ void inverse(const C* m, C* o) {
+  const C k0 = m[0] * (C)(1.0 / 9.0), k1 = m[1] * (C)(1.0 / 36.0),
+          k2 = m[2] * (C)(1.0 / 36.0), k3 = m[3] * (C)(1.0 / 6.0),
+          k4 = m[4] * (C)(1.0 / 12.0), k5 = m[5] * (C)(1.0 / 6.0),
+          k6 = m[6] * (C)(1.0 / 12.0), k7 = m[7] * (C)0.25,
+          k8 = m[8] * (C)0.25;
+  o[0] = k0 - 4 * k1 + 4 * k2;
+  const C ax = k0 - k1 - 2 * k2;
+  o[1] = ax + k3 - 2 * k4 + k7;
+  o[2] = ax + k5 - 2 * k6 - k7;
+  o[3] = ax - k3 + 2 * k4 + k7;
+  o[4] = ax - k5 + 2 * k6 - k7;
+  const C dg = k0 + 2 * k1 + k2;
+  const C p34 = k3 + k4, p56 = k5 + k6;
+  o[5] = dg + p34 + p56 + k8;
+  o[6] = dg - p34 + p56 - k8;
+  o[7] = dg - p34 - p56 + k8;
+  o[8] = dg + p34 - p56 - k8;
+}
+
+// Particle sums of one cell: total solid fraction f_s = sum_p f_s,p and
+// sum_p f_s,p (u_s, u_s u_s), the inputs of the volumetric step.
+template <class C>
+struct PSums {
+  C S0, S1x, S1y, S2xx, S2yy, S2xy;
+};
+
+// The lattice update of the 256 cells of one tile: pull streaming with the
+// wall rules, the volumetric no-slip step with the particle sums `part`
+// supplies, the coupled macroscopic solve and both collisions.  Every thread
+// of the block calls gather() right after issuing its population loads (so
+// that the particle bookkeeping overlaps them) and then
+// part(act, x, y, rho, jx*, jy*, S); both may hold barriers.
+template <int PREC, bool OUT, class GatherFn, class PartFn>
+__device__ __forceinline__ void lattice_tile(
+    const Params& P, const Hot<typename Prec<PREC>::C>& H,
+    const typename Prec<PREC>::S* __restrict__ fin,
+    typename Prec<PREC>::S* __restrict__ fout,
+    const typename Prec<PREC>::S* __restrict__ gin,
+    typename Prec<PREC>::S* __restrict__ gout,
+    const typename Prec<PREC>::H* __restrict__ hin,
+    typename Prec<PREC>::H* __restrict__ hout, size_t plane, int tile,
+    double* __restrict__ macro, int* flags, GatherFn gather, PartFn part) {
+  typedef Prec<PREC> T;
+  typedef typename T::C C;
+  typedef typename T::H HT;
+
+  const int c = tile * kBlock + threadIdx.x;
+  const bool act = c < P.N;
+  const int cc = act ? c : P.N - 1;   // inactive lanes read a valid cell
+  const int y = cc / P.nx;
+  const int x = cc - y * P.nx;
+
+  // ---- pull streaming with the wall rules (eq. lbe.rho.str, lbe.e.str)
+  int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+  const bool oxm = xm < 0 && !P.perx, oxp = xp >= P.nx && !P.perx;
+  const bool oym = ym < 0 && !P.pery, oyp = yp >= P.ny && !P.pery;
+  xm = xm < 0 ? xm + P.nx : xm;
+  xp = xp >= P.nx ? xp - P.nx : xp;
+  ym = ym < 0 ? ym + P.ny : ym;
+  yp = yp >= P.ny ? yp - P.ny : yp;
+  const int r0 = y * P.nx, rm = ym * P.nx, rp = yp * P.nx;
+  C f[9], g[9];
+  f[0] = T::ld(fin, cc);
+  g[0] = T::ld(gin, cc);
+  constexpr int XLO = VLB_FACE_XLO, XHI = VLB_FACE_XHI;
+  constexpr int YLO = VLB_FACE_YLO, YHI = VLB_FACE_YHI;
+  pull<1, 3, XLO, -1, T>(fin, gin, plane, cc, r0 + xm, oxm, false, H, f[1], g[1]);
+  pull<2, 4, -1, YLO, T>(fin, gin, plane, cc, rm + x, false, oym, H, f[2], g[2]);
+  pull<3, 1, XHI, -1, T>(fin, gin, plane, cc, r0 + xp, oxp, false, H, f[3], g[3]);
+  pull<4, 2, -1, YHI, T>(fin, gin, plane, cc, rp + x, false, oyp, H, f[4], g[4]);
+  pull<5, 7, XLO, YLO, T>(fin, gin, plane, cc, rm + xm, oxm, oym, H, f[5], g[5]);
+  pull<6, 8, XHI, YLO, T>(fin, gin, plane, cc, rm + xp, oxp, oym, H, f[6], g[6]);
+  pull<7, 5, XHI, YHI, T>(fin, gin, plane, cc, rp + xp, oxp, oyp, H, f[7], g[7]);
+  pull<8, 6, XLO, YHI, T>(fin, gin, plane, cc, rp + xm, oxm, oyp, H, f[8], g[8]);
+  const HT hn = hin[cc];
+  gather();
+
+  // ---- moments of the deviations f* - w rho_0; the reference adds
+  // rho_0 (1, -2, 1, 0, ..., 0) to M f*
+  C m[9];
+  moments(f, m);
+  const C drho = m[0];                 // rho - rho_0
+  const C rho = H.rho0s + drho;        // rho = sum f*_i, kept by eq. fi
+  const C jxs = m[3], jys = m[5];
+
+  // ---- particles: solid fraction, u_s, momentum exchange (Sec. 2.3)
+  PSums<C> S;
+  S.S0 = S.S1x = S.S1y = S.S2xx = S.S2yy = S.S2xy = (C)0;
+  part(act, x, y, rho, jxs, jys, S);
+
+  // ---- volumetric no-slip step in moment space (eq. fi):
+  // M f = (1 - f_s) M f* + rho sum_p f_s,p m^eq(1, u_s,p), written for the
+  // deviations (the reference moments cancel against rho_0 S0)
+  const C S0 = S.S0, S1x = S.S1x, S1y = S.S1y;
+  const C S2xx = S.S2xx, S2yy = S.S2yy, S2xy = S.S2xy;
+  const C fs = S0;
+  const C wf = (C)1 - fs;
+  {
+    const C tr = S2xx + S2yy;
+    m[0] = wf * m[0] + S0 * drho;
+    m[1] = wf * m[1] + (-2 * S0 * drho + 3 * rho * tr);
+    m[2] = wf * m[2] + (S0 * drho - 3 * rho * tr);
+    m[3] = wf * m[3] + rho * S1x;
+    m[4] = wf * m[4] - rho * S1x;
+    m[5] = wf * m[5] + rho * S1y;
+    m[6] = wf * m[6] - rho * S1y;
+    m[7] = wf * m[7] + rho * (S2xx - S2yy);
+    m[8] = wf * m[8] + rho * S2xy;
+  }
+
+  // ---- [df_s/dt] by eq. dfs_dt through the carrier h = 2 f_s + d:
+  // d^{n+1} = 2 f_s^{n+1} - h^n,  h^{n+1} = 2 f_s^{n+1} + d^{n+1}
+  const C dfs = 2 * fs - (C)hn;
+  const HT hnew = (HT)(2 * fs + dfs);
+
+  // ---- per-cell properties (Sec. 2.2) and relaxation rates (Sec. 3)
+  const C cv = H.cvf + H.dcv * fs;
+  const C lam = H.lamf + H.dlam * fs;
+  const C tau_g = (C)0.5 + H.taug_coef * lam;
+  const C sig_j = (C)1 / tau_g;
+  // (1/sig_j - 1/2)(1/sig_e - 1/2) = 1/4 is sig_e = 2 - sig_j
+  const C sig_e = H.sigma_rule == 0 ? (C)2 - sig_j : (C)1;
+
+  // ---- energy moments (the reference w c_ref T_0 adds c_ref T_0 (1, -2,
+  // 1, 0, ..., 0)) and the local temperature gradient (Sec. 2.2)
+  C n[9];
+  moments(g, n);
+  const C cT0 = H.cT0s;
+  const C G = n[0] + cT0;                          // sum g_i
+  const C gcoef = H.grad_coef * sig_j;             // -3 / (c_ref tau_g)
+  const C gTx = gcoef * n[3], gTy = gcoef * n[5];
+
+  // ---- coupled macroscopic solve: u from eq. rho.rhou with F = a + b T,
+  // T from the implicit relation of Sec. 2.2 (linear in T)
+  const C ax = wf * H.A0x, ay = wf * H.A0y;
+  const C bx = wf * H.B0x, by = wf * H.B0y;
+  const C irho = (C)1 / rho;
+  const C jx = m[3], jy = m[5];
+  const C num = G - (C)0.5 * cv * ((jx + (C)0.5 * ax) * gTx + (jy + (C)0.5 * ay) * gTy) * irho;
+  const C den = cv - (C)0.5 * H.dcv * dfs + (C)0.25 * cv * (bx * gTx + by * gTy) * irho;
+  const C Tc = num / den;
+  const C Fx = ax + bx * Tc, Fy = ay + by * Tc;
+  const C ux = (jx + (C)0.5 * Fx) * irho, uy = (jy + (C)0.5 * Fy) * irho;
+  const C eps = cv * Tc;
+  const C qc = -cv * (ux * gTx + uy * gTy) + H.dcv * Tc * dfs;
+
+  if (act && !(rho > (C)0 && isfinite(Tc) && isfinite(ux) && isfinite(uy)))
+    atomicOr(flags, kFlagUnstable);
+
+  // ---- flow collision with the discrete force term (eq. lbe.rho.col);
+  // m^eq minus the reference moments is (drho, -2 drho + 3 rho u^2,
+  // drho - 3 rho u^2, rho ux, -rho ux, rho uy, -rho uy, rho (ux^2 - uy^2),
+  // rho ux uy); s_0 = s_j = 1
+  {
+    const C ru2 = rho * (ux * ux + uy * uy);
+    const C se = H.s_e, sq = H.s_q, sp = H.s_p;
+    const C he = (C)1 - (C)0.5 * se, hq = (C)1 - (C)0.5 * sq,
+            hp = (C)1 - (C)0.5 * sp;
+    const C Fu = Fx * ux + Fy * uy;
+    C mb[9];
+    mb[0] = drho;
+    mb[1] = m[1] - se * (m[1] - (-2 * drho + 3 * ru2)) + he * (6 * Fu);
+    mb[2] = m[2] - se * (m[2] - (drho - 3 * ru2)) - he * (6 * Fu);
+    mb[3] = rho * ux + (C)0.5 * Fx;
+    mb[4] = m[4] - sq * (m[4] + rho * ux) - hq * Fx;
+    mb[5] = rho * uy + (C)0.5 * Fy;
+    mb[6] = m[6] - sq * (m[6] + rho * uy) - hq * Fy;
+    mb[7] = m[7] - sp * (m[7] - rho * (ux * ux - uy * uy)) + hp * (2 * (Fx * ux - Fy * uy));
+    mb[8] = m[8] - sp * (m[8] - rho * ux * uy) + hp * (Fx * uy + Fy * ux);
+    C o[9];
+    inverse(mb, o);
+    if (act) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) T::st(fout, (size_t)q * plane + cc, o[q]);
+    }
+  }
+
+  // ---- energy collision with the discrete source term (eq. lbe.e.col):
+  // n^eq = [eps, -4 eps + 2 c_ref T, 4 eps - 3 c_ref T, 0...] (alpha1 = -2,
+  // alpha2 = 1), q_m = [q, -4 q, 4 q, 0...] (beta1 = -4, beta2 = 4),
+  // R = diag(1, se, se, sj, sj, sj, sj, se, se); moments minus reference
+  {
+    const C cT = H.cref * Tc;
+    const C he = (C)1 - (C)0.5 * sig_e;
+    C nb[9];
+    nb[0] = (eps - cT0) + (C)0.5 * qc;
+    nb[1] = n[1] - sig_e * (n[1] - (-4 * eps + 2 * cT + 2 * cT0)) - he * (4 * qc);
+    nb[2] = n[2] - sig_e * (n[2] - (4 * eps - 3 * cT - cT0)) + he * (4 * qc);
+    const C rj = (C)1 - sig_j, re = (C)1 - sig_e;
+    nb[3] = rj * n[3];
+    nb[4] = rj * n[4];
+    nb[5] = rj * n[5];
+    nb[6] = rj * n[6];
+    nb[7] = re * n[7];
+    nb[8] = re * n[8];
+    C o[9];
+    inverse(nb, o);
+    if (act) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) T::st(gout, (size_t)q * plane + cc, o[q]);
+      hout[cc] = hnew;
+    }
+  }
+
+  if (OUT && act) {
+    const size_t N = (size_t)P.N;
+    macro[cc] = (double)rho;
+    macro[N + cc] = (double)ux;
+    macro[2 * N + cc] = (double)uy;
+    macro[3 * N + cc] = (double)Tc;
+    macro[4 * N + cc] = (double)fs;
+    macro[5 * N + cc] = (double)dfs;
+  }
+}
+
+// The fluid lattice over every cell, without particles.  Cells of the tiles
+// particles reach are redone by k_lattice_particles, which runs next from
+// the same step-n inputs and overwrites them.
+template <int PREC, bool OUT>
+__global__ __launch_bounds__(kBlock) void k_lattice(
+    const Params P, const Hot<typename Prec<PREC>::C> H,
+    const typename Prec<PREC>::S* __restrict__ fin,
+    typename Prec<PREC>::S* __restrict__ fout,
+    const typename Prec<PREC>::S* __restrict__ gin,
+    typename Prec<PREC>::S* __restrict__ gout,
+    const typename Prec<PREC>::H* __restrict__ hin,
+    typename Prec<PREC>::H* __restrict__ hout, size_t plane,
+    double* __restrict__ macro, int* flags) {
+  typedef typename Prec<PREC>::C C;
+  lattice_tile<PREC, OUT>(P, H, fin, fout, gin, gout, hin, hout, plane,
+                          blockIdx.x, macro, flags, [] {},
+                          [](bool, int, int, C, C, C, PSums<C>&) {});
+}
+
+// Tile of particle-tile block k in the scan form: block k serves the
+// (k / maxr)-th particle's (k % maxr)-th tile, unless a particle of lower
+// index also reaches that tile (its block serves it).  -1: nothing to do.
+__device__ __forceinline__ int scan_task_tile(const Params& P, PState cur,
+                                              PConst pc, int k) {
+  const int p = k / P.maxr, j = k - p * P.maxr;
+  if (p >= P.np) return -1;
+  double X = cur.X[p], Y = cur.Y[p];
+  advance_position(P, X, Y, cur.Ux[p], cur.Uy[p]);
+  const BlockRanges r = block_ranges(P, X, Y, pc.R[p], kBlock);
+  if (j >= r.count()) return -1;
+  const int tile = r.at(j);
+  for (int q = 0; q < p; ++q) {
+    double Xq = cur.X[q], Yq = cur.Y[q];
+    advance_position(P, Xq, Yq, cur.Ux[q], cur.Uy[q]);
+    if (block_ranges(P, Xq, Yq, pc.R[q], kBlock).contains(tile)) return -1;
+  }
+  return tile;
+}
+
+// The tiles particles reach: the particles of the tile (scan form: found
+// and advanced here, with their new velocities rebuilt from the previous
+// step's partials; list form: the block list k_particles filled), the
+// exact-area solid fractions, and the per-block momentum-exchange partials.
+template <int PREC, bool OUT, bool SCAN>
+__global__ __launch_bounds__(kBlock) void k_lattice_particles(
+    const Params P, const Hot<typename Prec<PREC>::C> H,
+    const typename Prec<PREC>::S* __restrict__ fin,
+    typename Prec<PREC>::S* __restrict__ fout,
+    const typename Prec<PREC>::S* __restrict__ gin,
+    typename Prec<PREC>::S* __restrict__ gout,
+    const typename Prec<PREC>::H* __restrict__ hin,
+    typename Prec<PREC>::H* __restrict__ hout, size_t plane, PState cur,
+    PState nxt, PConst pc, Lists L, const double* __restrict__ partial_in,
+    double* __restrict__ partial, int have, double* __restrict__ macro,
+    int* flags) {
+  typedef typename Prec<PREC>::C C;
+  __shared__ BlockParticles bp;
+  __shared__ int tmp[kListCap];
+  __shared__ double red[4][3];
+  int tile;
+  if (SCAN) {
+    tile = scan_task_tile(P, cur, pc, blockIdx.x);   // uniform in the block
+    if (tile < 0) return;
+  } else {
+    tile = blockIdx.x;
+    if (L.cnt[tile] == 0) return;                    // uniform in the block
+  }
+  auto gather = [&] {
+    if (SCAN)
+      scan_block(bp, P, tile, cur, nxt, pc, partial_in, have, true, flags);
+    else
+      load_block_list(bp, tmp, L, tile, nxt, pc, flags);
+  };
+  int nin = 0;
+  auto part = [&](bool act, int x, int y, C rho, C jxs, C jys, PSums<C>& S) {
+    const int cnt = bp.cnt;
+    // each particle reaching the cell adds f_s,p to f_s and f_s,p (u_s,
+    // u_s u_s) to the sums; its share of sum_i (f_i - f*_i) e_i is
+    // f_s,p (rho u_s - j*)
+    for (int pass = 0; pass < 2; ++pass) {
+      // pass 1: overlapping disks' shares are scaled to sum to one (rare)
+      if (pass == 1 && !__syncthreads_or(act && S.S0 > (C)1)) break;
+      const bool over = S.S0 > (C)1;
+      const C inv = over ? (C)1 / S.S0 : (C)1;
+      for (int s = 0; s < cnt; ++s) {
+        double cfx = 0.0, cfy = 0.0, ctz = 0.0;
+        SlotGeom sg;
+        if (act && (pass == 0 || over) &&
+            particle_geometry(P, bp.X[s], bp.Y[s], bp.R[s], bp.Ux[s],
+                              bp.Uy[s], bp.Om[s], x, y, sg)) {
+          const C a = (C)sg.fs, ux = (C)sg.usx, uy = (C)sg.usy;
+          if (pass == 0) {
+            ++nin;
+            S.S0 += a;
+            S.S1x += a * ux;
+            S.S1y += a * uy;
+            S.S2xx += a * ux * ux;
+            S.S2yy += a * uy * uy;
+            S.S2xy += a * ux * uy;
+          }
+          const double k = pass == 0 ? 1.0 : (double)(inv - (C)1);
+          const double dpx = (double)(a * (rho * ux - jxs));
+          const double dpy = (double)(a * (rho * uy - jys));
+          cfx = -dpx * k;
+          cfy = -dpy * k;
+          ctz = -(sg.rx * dpy - sg.ry * dpx) * k;
+        }
+        block_sum3(cfx, cfy, ctz, red);
+        if (threadIdx.x == 0) {
+          double* o = partial + (size_t)bp.slot[s] * kRedVals;
+          if (pass == 0) {
+            o[0] = cfx; o[1] = cfy; o[2] = ctz;
+          } else {
+            o[0] += cfx; o[1] += cfy; o[2] += ctz;
+          }
+        }
+      }
+      if (pass == 1 && over) {
+        S.S1x *= inv; S.S1y *= inv; S.S2xx *= inv; S.S2yy *= inv;
+        S.S2xy *= inv;
+        S.S0 = (C)1;
+      }
+    }
+    if (act && nin > P.kmax) atomicOr(flags, kFlagOverlap);
+  };
+  lattice_tile<PREC, OUT>(P, H, fin, fout, gin, gout, hin, hout, plane, tile,
+                          macro, flags, gather, part);
+}
+
+// -------------------------------------------------------------------------
+// Initial state: equilibria of the mixed fluid/particle state per cell.
+
+template <int PREC, bool SCAN>
+__global__ __launch_bounds__(kBlock) void k_init(
+    const Params P, typename Prec<PREC>::S* __restrict__ fo,
+    typename Prec<PREC>::S* __restrict__ go,
+    typename Prec<PREC>::H* __restrict__ hcar, size_t plane, PState ps,
+    PConst pc, Lists L, double* __restrict__ macro, int* flags) {
+  typedef Prec<PREC> T;
+  typedef typename T::C C;
+  __shared__ BlockParticles bp;
+  __shared__ int tmp[kListCap];
+  gather_particles<SCAN>(bp, tmp, P, ps, ps, pc, L, nullptr, 0, false, flags);
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= P.N) return;
+  const int y = c / P.nx, x = c - y * P.nx;
+  double S0 = 0, Sx = 0, Sy = 0, Se = 0;
+  int nin = 0;
+  for (int s = 0; s < bp.cnt; ++s) {
+    SlotGeom sg;
+    if (slot_geometry(bp, s, P, x, y, sg)) {
+      ++nin;
+      S0 += sg.fs;
+      Sx += sg.fs * sg.usx;
+      Sy += sg.fs * sg.usy;
+      Se += sg.fs * P.cvs * bp.Tp[s];
+    }
+  }
+  if (nin > P.kmax) atomicOr(flags, kFlagOverlap);
+  if (S0 > 1.0) {
+    const double inv = 1.0 / S0;
+    Sx *= inv;
+    Sy *= inv;
+    Se *= inv;
+    S0 = 1.0;
+  }
+  const double fs = S0;
+  const double ux = (1.0 - fs) * P.init_ux + Sx;
+  const double uy = (1.0 - fs) * P.init_uy + Sy;
+  const double eps = (1.0 - fs) * P.cvf * P.init_T + Se;
+  const double cv = P.cvf + P.dcv * fs;
+  const double Tt = eps / cv;
+  const double rho = P.init_rho;
+  // f^eq = w_i rho [1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u^2] (= M^{-1} m^eq);
+  // g^eq_i = w_i c_ref T (i >= 1), g^eq_0 = eps - 5/9 c_ref T (= M^{-1} n^eq)
+  const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                       1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  const double u2 = ux * ux + uy * uy;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const double eu = ex[q] * ux + ey[q] * uy;
+    const double feq = w[q] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * u2);
+    const double geq = q == 0 ? eps - (5.0 / 9.0) * P.cref * Tt : w[q] * P.cref * Tt;
+    T::st(fo, (size_t)q * plane + c, (C)(feq - P.fshift[q]));
+    T::st(go, (size_t)q * plane + c, (C)(geq - P.gshift[q]));
+  }
+  hcar[c] = (typename T::H)(2.0 * fs);
+  const size_t N = (size_t)P.N;
+  macro[c] = rho;
+  macro[N + c] = ux;
+  macro[2 * N + c] = uy;
+  macro[3 * N + c] = Tt;
+  macro[4 * N + c] = fs;
+  macro[5 * N + c] = 0.0;
+}
+
+// -------------------------------------------------------------------------
+// Particle pass (list form, and the force read-out of both forms): one wave
+// (64 lanes) per particle.  Modes: update (Newton-Euler step, then the block
+// lists of the new band box), reduce only (store the momentum-exchange
+// force of the last pass), bin only (block lists of the stored positions).
+
+__global__ __launch_bounds__(256) void k_particles(
+    const Params P, PState cur, PState next, PConst pc, Lists L,
+    const double* __restrict__ partial, int have_partials, int mode,
+    int* flags) {
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= P.np) return;  // whole wave
+
+  if (mode == kModeReduceOnly) {
+    double fx, fy, tz;
+    reduce_partials(P, cur, pc, partial, have_partials, p, lane, fx, fy, tz);
     if (lane == 0) {
       cur.Fx[p] = fx;
       cur.Fy[p] = fy;
       cur.Tz[p] = tz;
     }
-    if (mode == kModeReduceOnly) return;
-
-    // ---- repulsion (short range, from the positions at step n)
-    double cx = 0.0, cy = 0.0;
-    const double zeta = P.coll_range;
-    const double Xp = cur.X[p], Yp = cur.Y[p], Rp = pc.R[p];
-    if (zeta > 0.0) {
-      for (int q = lane; q < P.np; q += 64) {
-        if (q == p) continue;
-        const double dx = Xp - near_copy(cur.X[q], Xp, (double)P.nx, P.perx);
-        const double dy = Yp - near_copy(cur.Y[q], Yp, (double)P.ny, P.pery);
-        const double d = sqrt(dx * dx + dy * dy);
-        const double reach = Rp + pc.R[q] + zeta;
-        if (d < reach && d > 0.0) {
-          const double s = (reach - d) / zeta;
-          const double mag = P.coll_pp * s * s / d;
-          cx += mag * dx;
-          cy += mag * dy;
-        }
-      }
-      cx = wave_sum(cx);
-      cy = wave_sum(cy);
-      if (lane == 0) {
-        // walls: the particle's mirror image across each wall face
-        const double dist[4] = {Xp, (double)P.nx - Xp, Yp, (double)P.ny - Yp};
-        const double nrmx[4] = {1.0, -1.0, 0.0, 0.0};
-        const double nrmy[4] = {0.0, 0.0, 1.0, -1.0};
-        for (int w = 0; w < 4; ++w) {
-          if (!P.wall_face[w]) continue;
-          const double d = 2.0 * dist[w], reach = 2.0 * Rp + zeta;
-          if (d < reach) {
-            const double s = (reach - d) / zeta;
-            cx += P.coll_pw * s * s * nrmx[w];
-            cy += P.coll_pw * s * s * nrmy[w];
-          }
-        }
-      }
-    }
-
-    // ---- Newton-Euler with the inside-fluid correction, forward Euler
-    if (lane == 0) {
-      const double R = Rp, rs = pc.rhos[p];
-      const double V = M_PI * R * R;
-      const double M = rs * V, I = 0.5 * M * R * R;
-      const double Min = P.rho_f * M / rs, Iin = P.rho_f * I / rs;
-      const double Ux = cur.Ux[p], Uy = cur.Uy[p], Om = cur.Om[p];
-      double nUx = Ux, nUy = Uy, nOm = Om;
-      if (!pc.fixed[p]) {
-        const double Finx = -Min * (Ux - cur.Uxp[p]);
-        const double Finy = -Min * (Uy - cur.Uyp[p]);
-        const double Tin = -Iin * (Om - cur.Omp[p]);
-        const double Fcx = (fx - Finx) + (rs - P.rho_f) * V * P.grav_x + cx;
-        const double Fcy = (fy - Finy) + (rs - P.rho_f) * V * P.grav_y + cy;
-        nUx = Ux + Fcx / M;
-        nUy = Uy + Fcy / M;
-        nOm = Om + (tz - Tin) / I;
-      }
-      nX = Xp + Ux;
-      nY = Yp + Uy;
-      if (P.perx) {
-        if (nX >= (double)P.nx) nX -= (double)P.nx;
-        if (nX < 0.0) nX += (double)P.nx;
-      }
-      if (P.pery) {
-        if (nY >= (double)P.ny) nY -= (double)P.ny;
-        if (nY < 0.0) nY += (double)P.ny;
-      }
-      next.X[p] = nX;
-      next.Y[p] = nY;
-      next.th[p] = cur.th[p] + Om;
-      next.Ux[p] = nUx;
-      next.Uy[p] = nUy;
-      next.Om[p] = nOm;
-      next.Uxp[p] = Ux;
-      next.Uyp[p] = Uy;
-      next.Omp[p] = Om;
-      next.Fx[p] = fx;
-      next.Fy[p] = fy;
-      next.Tz[p] = tz;
-    }
-    nX = __shfl(nX, 0, 64);
-    nY = __shfl(nY, 0, 64);
+    return;
+  }
+  double nX = cur.X[p], nY = cur.Y[p];
+  if (mode == kModeUpdate) {
+    const PUpd u = particle_update(P, cur, pc, partial, have_partials, p, lane);
+    if (lane == 0) store_particle(next, p, u);
+    nX = u.X;
+    nY = u.Y;
   }
 
   // ---- block lists for the band box at the new position
@@ -941,12 +1281,13 @@ __global__ __launch_bounds__(256) void k_particle_sums(
 // Cell ownership for inspection: the same block lists and predicates as the
 // lattice pass.
 
+template <bool SCAN>
 __global__ __launch_bounds__(kBlock) void k_ownership(
     const Params P, PState ps, PConst pc, Lists L, int* count, int* ids,
     int* full, int* flags) {
   __shared__ BlockParticles bp;
   __shared__ int tmp[kListCap];
-  load_block_list(bp, tmp, L, ps, pc, flags);
+  gather_particles<SCAN>(bp, tmp, P, ps, ps, pc, L, nullptr, 0, false, flags);
   const int c = blockIdx.x * kBlock + threadIdx.x;
   if (c >= P.N) return;
   const int y = c / P.nx, x = c - y * P.nx;
@@ -981,7 +1322,7 @@ __global__ void k_unpack(const Params P, const typename Prec<PREC>::S* pop,
   const int q = (int)(k / N);
   const size_t c = k - (size_t)q * N;
   const double sh = which_g ? P.gshift[q] : P.fshift[q];
-  out[k] = (double)T::ld(pop, (size_t)q * plane + c, (typename T::C)sh);
+  out[k] = (double)T::ld(pop, (size_t)q * plane + c) + sh;
 }
 
 // -------------------------------------------------------------------------
@@ -992,7 +1333,7 @@ static inline unsigned blocks_for(long n, int per) {
 }
 
 hipError_t launch_particles(const Params& P, PState cur, PState next,
-                            PConst pc, Lists L, double* partial,
+                            PConst pc, Lists L, const double* partial,
                             int have_partials, int mode, int* flags,
                             hipStream_t s) {
   if (P.np == 0) return hipSuccess;
@@ -1001,55 +1342,89 @@ hipError_t launch_particles(const Params& P, PState cur, PState next,
   return hipGetLastError();
 }
 
-template <int PREC>
-static hipError_t lattice_t(bool out, const Params& P, const void* fi,
-                            void* fo, const void* gi, void* go, void* h,
-                            size_t plane, PState pn, PConst pc, Lists L,
-                            double* partial, double* macro, int* flags,
-                            hipStream_t s) {
+template <int PREC, bool OUT>
+static hipError_t lattice_t(const LatticeLaunch& a, hipStream_t s) {
   typedef typename Prec<PREC>::S S;
-  typedef typename Prec<PREC>::H H;
-  if (out)
-    hipLaunchKernelGGL((k_lattice<PREC, true>), dim3(P.nblocks), dim3(kBlock),
-                       0, s, P, (const S*)fi, (S*)fo, (const S*)gi, (S*)go,
-                       (H*)h, plane, pn, pc, L, partial, macro, flags);
-  else
-    hipLaunchKernelGGL((k_lattice<PREC, false>), dim3(P.nblocks), dim3(kBlock),
-                       0, s, P, (const S*)fi, (S*)fo, (const S*)gi, (S*)go,
-                       (H*)h, plane, pn, pc, L, partial, macro, flags);
+  typedef typename Prec<PREC>::H HT;
+  const Hot<typename Prec<PREC>::C> H = make_hot<typename Prec<PREC>::C>(*a.P);
+  hipExtLaunchKernelGGL((k_lattice<PREC, OUT>), dim3(a.P->nblocks),
+                        dim3(kBlock), 0, s, a.ev_start, a.ev_stop, 0, *a.P, H,
+                        (const S*)a.fi, (S*)a.fo, (const S*)a.gi, (S*)a.go,
+                        (const HT*)a.hin, (HT*)a.hout, a.plane, a.macro,
+                        a.flags);
   return hipGetLastError();
 }
 
-hipError_t launch_lattice(int prec, bool out, const Params& P,
-                          const void* fi, void* fo, const void* gi, void* go,
-                          void* h, size_t plane, PState pn, PConst pc,
-                          Lists L, double* partial, double* macro, int* flags,
-                          hipStream_t s) {
+template <int PREC, bool OUT, bool SCAN>
+static hipError_t particles_t(const LatticeLaunch& a, hipStream_t s) {
+  typedef typename Prec<PREC>::S S;
+  typedef typename Prec<PREC>::H HT;
+  const Params& P = *a.P;
+  const Hot<typename Prec<PREC>::C> H = make_hot<typename Prec<PREC>::C>(P);
+  const unsigned grid = SCAN ? (unsigned)(P.np * P.maxr) : (unsigned)P.nblocks;
+  hipLaunchKernelGGL((k_lattice_particles<PREC, OUT, SCAN>), dim3(grid),
+                     dim3(kBlock), 0, s, P, H, (const S*)a.fi, (S*)a.fo,
+                     (const S*)a.gi, (S*)a.go, (const HT*)a.hin, (HT*)a.hout,
+                     a.plane, a.cur, a.nxt, a.pc, a.L, a.partial_in,
+                     a.partial_out, a.have, a.macro, a.flags);
+  return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t lattice_p(const LatticeLaunch& a, hipStream_t s) {
+  return a.out ? lattice_t<PREC, true>(a, s) : lattice_t<PREC, false>(a, s);
+}
+
+template <int PREC>
+static hipError_t particles_p(const LatticeLaunch& a, hipStream_t s) {
+  if (a.P->scan)
+    return a.out ? particles_t<PREC, true, true>(a, s)
+                 : particles_t<PREC, false, true>(a, s);
+  return a.out ? particles_t<PREC, true, false>(a, s)
+               : particles_t<PREC, false, false>(a, s);
+}
+
+hipError_t launch_lattice(int prec, const LatticeLaunch& a, hipStream_t s) {
   switch (prec) {
-    case VLB_FP64:
-      return lattice_t<VLB_FP64>(out, P, fi, fo, gi, go, h, plane, pn, pc, L,
-                                 partial, macro, flags, s);
-    case VLB_FP32:
-      return lattice_t<VLB_FP32>(out, P, fi, fo, gi, go, h, plane, pn, pc, L,
-                                 partial, macro, flags, s);
-    case VLB_FP16_SHIFT:
-      return lattice_t<VLB_FP16_SHIFT>(out, P, fi, fo, gi, go, h, plane, pn,
-                                       pc, L, partial, macro, flags, s);
-    case VLB_BF16_SHIFT:
-      return lattice_t<VLB_BF16_SHIFT>(out, P, fi, fo, gi, go, h, plane, pn,
-                                       pc, L, partial, macro, flags, s);
+    case VLB_FP64: return lattice_p<VLB_FP64>(a, s);
+    case VLB_FP32: return lattice_p<VLB_FP32>(a, s);
+    case VLB_FP16_SHIFT: return lattice_p<VLB_FP16_SHIFT>(a, s);
+    case VLB_BF16_SHIFT: return lattice_p<VLB_BF16_SHIFT>(a, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_init(int prec, const Params& P, void* f, void* g, void* h,
-                       size_t plane, PState pn, PConst pc, Lists L,
-                       double* macro, int* flags, hipStream_t s) {
-#define VLB_INIT(PR)                                                         \
-  hipLaunchKernelGGL(k_init<PR>, dim3(P.nblocks), dim3(kBlock), 0, s, P,      \
-                     (Prec<PR>::S*)f, (Prec<PR>::S*)g, (Prec<PR>::H*)h, plane, \
-                     pn, pc, L, macro, flags);                                 \
+hipError_t launch_lattice_particles(int prec, const LatticeLaunch& a,
+                                    hipStream_t s) {
+  if (a.P->np == 0) return hipSuccess;
+  switch (prec) {
+    case VLB_FP64: return particles_p<VLB_FP64>(a, s);
+    case VLB_FP32: return particles_p<VLB_FP32>(a, s);
+    case VLB_FP16_SHIFT: return particles_p<VLB_FP16_SHIFT>(a, s);
+    case VLB_BF16_SHIFT: return particles_p<VLB_BF16_SHIFT>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int PREC, bool SCAN>
+static hipError_t init_t(const Params& P, void* f, void* g, void* h,
+                         size_t plane, PState ps, PConst pc, Lists L,
+                         double* macro, int* flags, hipStream_t s) {
+  hipLaunchKernelGGL((k_init<PREC, SCAN>), dim3(P.nblocks), dim3(kBlock), 0,
+                     s, P, (typename Prec<PREC>::S*)f,
+                     (typename Prec<PREC>::S*)g, (typename Prec<PREC>::H*)h,
+                     plane, ps, pc, L, macro, flags);
   return hipGetLastError();
+}
+
+hipError_t launch_init(int prec, const Params& P, void* f, void* g, void* h,
+                       size_t plane, PState ps, PConst pc, Lists L,
+                       double* macro, int* flags, hipStream_t s) {
+#define VLB_INIT(PR)                                                        \
+  return P.scan ? init_t<PR, true>(P, f, g, h, plane, ps, pc, L, macro,     \
+                                   flags, s)                                \
+                : init_t<PR, false>(P, f, g, h, plane, ps, pc, L, macro,    \
+                                    flags, s);
   switch (prec) {
     case VLB_FP64: VLB_INIT(VLB_FP64)
     case VLB_FP32: VLB_INIT(VLB_FP32)
@@ -1072,8 +1447,12 @@ hipError_t launch_particle_sums(const Params& P, PState ps, PConst pc,
 hipError_t launch_ownership(const Params& P, PState ps, PConst pc, Lists L,
                             int* count, int* ids, int* full, int* flags,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_ownership, dim3(P.nblocks), dim3(kBlock), 0, s, P, ps,
-                     pc, L, count, ids, full, flags);
+  if (P.scan)
+    hipLaunchKernelGGL(k_ownership<true>, dim3(P.nblocks), dim3(kBlock), 0, s,
+                       P, ps, pc, L, count, ids, full, flags);
+  else
+    hipLaunchKernelGGL(k_ownership<false>, dim3(P.nblocks), dim3(kBlock), 0, s,
+                       P, ps, pc, L, count, ids, full, flags);
   return hipGetLastError();
 }
 
