@@ -1,7 +1,8 @@
 """Throughput of the coupled flow + thermal lattice update on one MI355X.
 
-One step = the whole per-time-step update (particle pass + fused lattice
-pass) over the workload, driven through the C ABI.  The headline workload is
+One step = the whole per-time-step update (one launch of the fused step
+kernel: particle update, solid fractions, both lattices, momentum exchange)
+over the workload, driven through the C ABI.  The headline workload is
 the 200 x 4000 channel with one cold sedimenting disk; the headline value is
 its FP64 throughput in MLUPS (every cell counts).  The same line reports the
 FP32 / FP16-shifted / BF16-shifted forms, the lattice kernel's achieved HBM
@@ -57,17 +58,22 @@ def measured_traffic(workload: str, precision: str):
 
 
 def run_gpu(vlb, d, ps, precision, steps, warmup):
+    """K steps with nothing else on the stream give the throughput; then K
+    more steps with every launch of the step kernel bracketed by HIP events
+    (recorded by the dispatch, on the context stream) give its average
+    duration for the roofline."""
     import torch
     dom = vlb.Domain(d, ps, precision).init()
     if warmup:
         dom.step(warmup)
-    dom.timing(True)
-    dom.timing_read()                      # reset the event pairs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dom.step(steps)                        # returns after the stream drained
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    dom.timing(True)
+    dom.timing_read()                      # reset the event pairs
+    dom.step(steps)
     ker_ms, nker = dom.timing_read()
     dom.timing(False)
     p = dom.particles()
@@ -175,7 +181,7 @@ def main():
             "unit": "GB/s",
             "frac": round(head["frac"], 4),
             "traffic": traffic,
-            "kernel": "k_lattice",
+            "kernel": "k_step",
             "bytes_per_cell": BYTES_PER_CELL[precs[0]],
             "cells_per_launch": cells,
             "avg_launch_us": round(head["lattice_ms"] * 1e3, 2),

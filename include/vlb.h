@@ -184,10 +184,10 @@ vlb_status vlb_load(vlb_ctx* ctx, const void* buf, size_t len);
 /* Steps taken since vlb_init. */
 int64_t vlb_step_count(const vlb_ctx* ctx);
 
-/* Kernel timing: while enabled, every launch of the lattice kernel is
- * bracketed by HIP events on the context stream; vlb_timing_read returns
- * the summed duration (ms) and the number of launches timed since the last
- * read, then resets. */
+/* Kernel timing: while enabled, every launch of the lattice step kernel
+ * (all cells, particle tiles included) is bracketed by HIP events on the
+ * context stream; vlb_timing_read returns the summed duration (ms) and the
+ * number of launches timed since the last read, then resets. */
 vlb_status vlb_timing_enable(vlb_ctx* ctx, int32_t on);
 vlb_status vlb_timing_read(vlb_ctx* ctx, double* total_ms, int64_t* count);
 

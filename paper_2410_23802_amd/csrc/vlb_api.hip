@@ -25,7 +25,8 @@ struct vlb_ctx {
   void* h[2] = {nullptr, nullptr};   // [df_s/dt] carrier, alternating
   int cur = 0;                       // f[cur], g[cur], h[cur]: step n
   double* macro = nullptr;
-  int* blk_cnt = nullptr;
+  int* blk_cnt[2] = {nullptr, nullptr};  // block counts, double buffered
+  int lpar = 0;                          // blk_cnt[lpar]: the current lists
   int2* blk_ent = nullptr;
   // particles
   int np = 0;
@@ -105,6 +106,16 @@ static void free_particles(vlb_ctx* c) {
   c->pconst = nullptr;
   c->pfixed = nullptr;
   c->thermal4 = nullptr;
+}
+
+static hipError_t clear_lists(vlb_ctx* c) {
+  c->lpar = 0;
+  for (int k = 0; k < 2; ++k) {
+    hipError_t e = hipMemsetAsync(c->blk_cnt[k], 0,
+                                  c->P.nblocks * sizeof(int), c->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 static vlb_status validate(const vlb_domain_desc* d, std::string& why) {
@@ -230,7 +241,8 @@ vlb_status vlb_create(const vlb_domain_desc* desc, void* hip_stream,
   ok = ok && dalloc(c, &c->h[0], N * c->h_elem);
   ok = ok && dalloc(c, &c->h[1], N * c->h_elem);
   ok = ok && dalloc(c, (void**)&c->macro, 6 * N * sizeof(double));
-  ok = ok && dalloc(c, (void**)&c->blk_cnt, c->P.nblocks * sizeof(int));
+  for (int k = 0; k < 2; ++k)
+    ok = ok && dalloc(c, (void**)&c->blk_cnt[k], c->P.nblocks * sizeof(int));
   ok = ok && dalloc(c, (void**)&c->blk_ent,
                     (size_t)c->P.nblocks * kListCap * sizeof(int2));
   ok = ok && dalloc(c, (void**)&c->flags, 4 * sizeof(int));
@@ -241,8 +253,7 @@ vlb_status vlb_create(const vlb_domain_desc* desc, void* hip_stream,
     vlb_destroy(c);
     return fail(nullptr, VLB_ENOMEM, "device allocation failed");
   }
-  if (hipMemsetAsync(c->blk_cnt, 0, c->P.nblocks * sizeof(int), c->stream) !=
-          hipSuccess ||
+  if (clear_lists(c) != hipSuccess ||
       hipMemsetAsync(c->flags, 0, 4 * sizeof(int), c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     vlb_destroy(c);
@@ -321,10 +332,23 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
   return VLB_OK;
 }
 
+// The current block lists (read by the lattice, init and ownership kernels).
 static Lists lists(vlb_ctx* c) {
   Lists L;
-  L.cnt = c->blk_cnt;
+  L.cnt = c->blk_cnt[c->lpar];
   L.ent = c->blk_ent;
+  L.clr = nullptr;
+  return L;
+}
+
+// Lists for a particle pass that bins: it fills the zeroed buffer and clears
+// the current one; the filled buffer becomes current.
+static Lists bin_lists(vlb_ctx* c) {
+  Lists L;
+  L.cnt = c->blk_cnt[1 - c->lpar];
+  L.ent = c->blk_ent;
+  L.clr = c->blk_cnt[c->lpar];
+  c->lpar ^= 1;
   return L;
 }
 
@@ -379,11 +403,11 @@ vlb_status vlb_init(vlb_ctx* c) {
     // the copies read pageable host vectors: finish before they go away
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
-  HIP_TRY(c, hipMemsetAsync(c->blk_cnt, 0, c->P.nblocks * sizeof(int), c->stream));
+  HIP_TRY(c, clear_lists(c));
   HIP_TRY(c, hipMemsetAsync(c->flags, 0, 4 * sizeof(int), c->stream));
   c->pp = 0;
   if (!c->P.scan)
-    HIP_TRY(c, launch_particles(c->P, c->ps[0], c->ps[1], c->pc, lists(c),
+    HIP_TRY(c, launch_particles(c->P, c->ps[0], c->ps[1], c->pc, bin_lists(c),
                                 c->partial[0], 0, kModeBinOnly, c->flags,
                                 c->stream));
   HIP_TRY(c, launch_init(c->prec, c->P, c->f[0], c->g[0], c->h[0], c->plane,
@@ -394,15 +418,17 @@ vlb_status vlb_init(vlb_ctx* c) {
   return st;
 }
 
+// One time step: (list form) the particle pass, which advances the
+// particles and fills the block lists, then the lattice step.
 static vlb_status one_step(vlb_ctx* c, bool last) {
   PState cur = c->ps[c->pcur], nxt = c->ps[1 - c->pcur];
   const double* pin = c->partial[c->pp];
   double* pout = c->partial[1 - c->pp];
   if (c->np > 0 && !c->P.scan)
-    HIP_TRY(c, launch_particles(c->P, cur, nxt, c->pc, lists(c), pin,
+    HIP_TRY(c, launch_particles(c->P, cur, nxt, c->pc, bin_lists(c), pin,
                                 c->have_partials, kModeUpdate, c->flags,
                                 c->stream));
-  LatticeLaunch a;
+  StepLaunch a;
   a.P = &c->P;
   a.out = last;
   a.fi = c->f[c->cur];
@@ -434,8 +460,7 @@ static vlb_status one_step(vlb_ctx* c, bool last) {
     a.ev_stop = c->ev[c->ev_used + 1];
     c->ev_used += 2;
   }
-  HIP_TRY(c, launch_lattice(c->prec, a, c->stream));
-  HIP_TRY(c, launch_lattice_particles(c->prec, a, c->stream));
+  HIP_TRY(c, launch_step(c->prec, a, c->stream));
   if (c->np > 0) {
     c->have_partials = 1;
     c->pcur ^= 1;
@@ -539,8 +564,9 @@ vlb_status vlb_read_ownership(vlb_ctx* c, int32_t* count, int32_t* ids,
   if (e == hipSuccess) e = hipMalloc((void**)&df, N * K * sizeof(int));
   PState cur = c->ps[c->pcur];
   if (e == hipSuccess && !c->P.scan)
-    e = launch_particles(c->P, cur, cur, c->pc, lists(c), c->partial[c->pp],
-                         0, kModeBinOnly, c->flags, c->stream);
+    e = launch_particles(c->P, cur, cur, c->pc, bin_lists(c),
+                         c->partial[c->pp], 0, kModeBinOnly, c->flags,
+                         c->stream);
   if (e == hipSuccess)
     e = launch_ownership(c->P, cur, c->pc, lists(c), dc, di, df, c->flags,
                          c->stream);
@@ -652,7 +678,7 @@ vlb_status vlb_load(vlb_ctx* c, const void* buf, size_t len) {
     HIP_TRY(c, hipMemcpyAsync(c->pconst, cst.data(), cst.size() * 8, H2D, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->pfixed, fx.data(), fx.size() * 4, H2D, c->stream));
   }
-  HIP_TRY(c, hipMemsetAsync(c->blk_cnt, 0, c->P.nblocks * sizeof(int), c->stream));
+  HIP_TRY(c, clear_lists(c));
   HIP_TRY(c, hipMemsetAsync(c->flags, 0, 4 * sizeof(int), c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->have_partials = hd.have_partials;
@@ -702,7 +728,8 @@ void vlb_destroy(vlb_ctx* c) {
   for (int k = 0; k < 2; ++k)
     if (c->h[k]) (void)hipFree(c->h[k]);
   if (c->macro) (void)hipFree(c->macro);
-  if (c->blk_cnt) (void)hipFree(c->blk_cnt);
+  for (int k = 0; k < 2; ++k)
+    if (c->blk_cnt[k]) (void)hipFree(c->blk_cnt[k]);
   if (c->blk_ent) (void)hipFree(c->blk_ent);
   if (c->flags) (void)hipFree(c->flags);
   if (c->flags_host) (void)hipHostFree(c->flags_host);

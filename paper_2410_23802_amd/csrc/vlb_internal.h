@@ -97,17 +97,22 @@ struct PConst {
   const int* fixed;
 };
 
+// Per-tile particle lists of the list form.  The counts are double
+// buffered: the particle pass fills `cnt` (all zero on entry) and clears
+// `clr`, the counts of the previous step, which both lattice kernels of
+// that step have finished reading.
 struct Lists {
   int* cnt;     // [nblocks]
   int2* ent;    // [nblocks][kListCap] (particle id, partial slot)
+  int* clr;     // [nblocks] or null: counts to reset to zero
 };
 
-// Arguments of one lattice launch.  `cur` is the particle state of step n;
+// Arguments of one lattice step.  `cur` is the particle state of step n;
 // `nxt` receives step n+1 (scan form) or already holds it (list form).
 // Partials of step n are read from `partial_in`, those of step n+1 written
 // to `partial_out`.  ev_start/ev_stop (may be null) are recorded by the
 // dispatch itself.
-struct LatticeLaunch {
+struct StepLaunch {
   const Params* P;
   bool out;                  // also store the macroscopic fields
   const void* fi; void* fo;
@@ -130,11 +135,8 @@ hipError_t launch_particles(const Params& P, PState cur, PState next,
                             PConst pc, Lists L, const double* partial,
                             int have_partials, int mode, int* flags,
                             hipStream_t s);
-// k_lattice over every cell (events, if given, bracket this launch)
-hipError_t launch_lattice(int prec, const LatticeLaunch& a, hipStream_t s);
-// k_lattice_particles over the tiles particles reach (after launch_lattice)
-hipError_t launch_lattice_particles(int prec, const LatticeLaunch& a,
-                                    hipStream_t s);
+// k_step: the lattice step over every cell (events, if given, bracket it)
+hipError_t launch_step(int prec, const StepLaunch& a, hipStream_t s);
 hipError_t launch_init(int prec, const Params& P, void* f, void* g, void* h,
                        size_t plane, PState pn, PConst pc, Lists L,
                        double* macro, int* flags, hipStream_t s);

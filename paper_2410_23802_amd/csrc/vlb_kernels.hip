@@ -505,8 +505,8 @@ __device__ __forceinline__ void store_particle(PState& s, int p,
 }
 
 // -------------------------------------------------------------------------
-// Block particle list: load, sort by particle id, stage the particle data in
-// LDS, and reset the global count for the next particle pass.
+// Block particle list: load, sort by particle id and stage the particle
+// data in LDS.
 
 struct BlockParticles {
   int cnt;
@@ -527,7 +527,6 @@ __device__ __forceinline__ void load_block_list(BlockParticles& bp, int* tmp,
       n = kListCap;
     }
     bp.cnt = n;
-    L.cnt[b] = 0;  // consumed
   }
   __syncthreads();
   const int n = bp.cnt;
@@ -765,11 +764,12 @@ struct PSums {
 // The lattice update of the 256 cells of one tile: pull streaming with the
 // wall rules, the volumetric no-slip step with the particle sums `part`
 // supplies, the coupled macroscopic solve and both collisions.  Every thread
-// of the block calls gather() right after issuing its population loads (so
-// that the particle bookkeeping overlaps them) and then
-// part(act, x, y, rho, jx*, jy*, S); both may hold barriers.
-template <int PREC, bool OUT, class GatherFn, class PartFn>
-__device__ __forceinline__ void lattice_tile(
+// of the block calls pre() before it issues its population loads, gather()
+// right after (so that its work overlaps them; a true result, which must be
+// uniform over the wave, abandons the tile: the return value is then false)
+// and then part(act, x, y, rho, jx*, jy*, S).
+template <int PREC, bool OUT, class PreFn, class GatherFn, class PartFn>
+__device__ __forceinline__ bool lattice_tile(
     const Params& P, const Hot<typename Prec<PREC>::C>& H,
     const typename Prec<PREC>::S* __restrict__ fin,
     typename Prec<PREC>::S* __restrict__ fout,
@@ -777,7 +777,8 @@ __device__ __forceinline__ void lattice_tile(
     typename Prec<PREC>::S* __restrict__ gout,
     const typename Prec<PREC>::H* __restrict__ hin,
     typename Prec<PREC>::H* __restrict__ hout, size_t plane, int tile,
-    double* __restrict__ macro, int* flags, GatherFn gather, PartFn part) {
+    double* __restrict__ macro, int* flags, PreFn pre, GatherFn gather,
+    PartFn part) {
   typedef Prec<PREC> T;
   typedef typename T::C C;
   typedef typename T::H HT;
@@ -797,6 +798,7 @@ __device__ __forceinline__ void lattice_tile(
   ym = ym < 0 ? ym + P.ny : ym;
   yp = yp >= P.ny ? yp - P.ny : yp;
   const int r0 = y * P.nx, rm = ym * P.nx, rp = yp * P.nx;
+  pre();
   C f[9], g[9];
   f[0] = T::ld(fin, cc);
   g[0] = T::ld(gin, cc);
@@ -811,7 +813,7 @@ __device__ __forceinline__ void lattice_tile(
   pull<7, 5, XHI, YHI, T>(fin, gin, plane, cc, rp + xp, oxp, oyp, H, f[7], g[7]);
   pull<8, 6, XLO, YHI, T>(fin, gin, plane, cc, rp + xm, oxm, oyp, H, f[8], g[8]);
   const HT hn = hin[cc];
-  gather();
+  if (gather()) return false;
 
   // ---- moments of the deviations f* - w rho_0; the reference adds
   // rho_0 (1, -2, 1, 0, ..., 0) to M f*
@@ -949,25 +951,7 @@ __device__ __forceinline__ void lattice_tile(
     macro[4 * N + cc] = (double)fs;
     macro[5 * N + cc] = (double)dfs;
   }
-}
-
-// The fluid lattice over every cell, without particles.  Cells of the tiles
-// particles reach are redone by k_lattice_particles, which runs next from
-// the same step-n inputs and overwrites them.
-template <int PREC, bool OUT>
-__global__ __launch_bounds__(kBlock) void k_lattice(
-    const Params P, const Hot<typename Prec<PREC>::C> H,
-    const typename Prec<PREC>::S* __restrict__ fin,
-    typename Prec<PREC>::S* __restrict__ fout,
-    const typename Prec<PREC>::S* __restrict__ gin,
-    typename Prec<PREC>::S* __restrict__ gout,
-    const typename Prec<PREC>::H* __restrict__ hin,
-    typename Prec<PREC>::H* __restrict__ hout, size_t plane,
-    double* __restrict__ macro, int* flags) {
-  typedef typename Prec<PREC>::C C;
-  lattice_tile<PREC, OUT>(P, H, fin, fout, gin, gout, hin, hout, plane,
-                          blockIdx.x, macro, flags, [] {},
-                          [](bool, int, int, C, C, C, PSums<C>&) {});
+  return true;
 }
 
 // Tile of particle-tile block k in the scan form: block k serves the
@@ -990,12 +974,43 @@ __device__ __forceinline__ int scan_task_tile(const Params& P, PState cur,
   return tile;
 }
 
-// The tiles particles reach: the particles of the tile (scan form: found
-// and advanced here, with their new velocities rebuilt from the previous
-// step's partials; list form: the block list k_particles filled), the
-// exact-area solid fractions, and the per-block momentum-exchange partials.
+// LDS of a particle tile: the staged particles, the per-cell particle sums
+// (written before the lattice update, read by it) and the per-cell rho, j*
+// (written by the lattice update, read by the momentum exchange).
+template <class C>
+struct TileShared {
+  BlockParticles bp;
+  int tmp[kListCap];
+  double red[4][3];
+  C S[6][kBlock];      // f_s and sum_p f_s,p (u_s, u_s u_s), shares scaled
+  C S0raw[kBlock];     // sum_p f_s,p before scaling
+  C M[3][kBlock];      // rho, jx*, jy* after streaming
+};
+
+// One time step of the whole lattice, one launch.  Two block roles:
+//
+//  * particle tiles (the tiles particles reach): the particles of the tile
+//    (scan form: found and advanced here, velocities rebuilt from the
+//    previous step's partials; list form: the block list k_particles
+//    filled), then three phases that keep the register peak at that of the
+//    plain update -- (1) exact-area solid fractions and the particle sums
+//    of each cell into LDS, (2) the lattice update reading them, (3) the
+//    per-block momentum-exchange partials of every particle of the tile;
+//  * plain tiles: the lattice update without particles.
+//
+// Scan form: the first np * maxr blocks take the particle tiles (so their
+// longer dependency chain starts first and overlaps the streaming of the
+// rest); the following nblocks blocks take every tile and leave those some
+// particle reaches (same advanced positions and band boxes; one particle
+// per lane) to the first group.  List form: block b takes tile b in the
+// role its block count gives.
+// FP64 is held to 128 VGPRs (4 waves per SIMD, the occupancy of the plain
+// update; the geometry of the particle role spills a little).  The 32-bit
+// forms are left unconstrained: at 8 waves the particle role spills heavily
+// and the step is slower than at 4.
 template <int PREC, bool OUT, bool SCAN>
-__global__ __launch_bounds__(kBlock) void k_lattice_particles(
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 1))) void k_step(
     const Params P, const Hot<typename Prec<PREC>::C> H,
     const typename Prec<PREC>::S* __restrict__ fin,
     typename Prec<PREC>::S* __restrict__ fout,
@@ -1007,77 +1022,144 @@ __global__ __launch_bounds__(kBlock) void k_lattice_particles(
     double* __restrict__ partial, int have, double* __restrict__ macro,
     int* flags) {
   typedef typename Prec<PREC>::C C;
-  __shared__ BlockParticles bp;
-  __shared__ int tmp[kListCap];
-  __shared__ double red[4][3];
+  __shared__ TileShared<C> sh;
+  const int t = threadIdx.x, lane = t & 63;
+
   int tile;
+  bool ptile;
   if (SCAN) {
-    tile = scan_task_tile(P, cur, pc, blockIdx.x);   // uniform in the block
-    if (tile < 0) return;
+    const int nfirst = P.np * P.maxr;
+    if ((int)blockIdx.x < nfirst) {
+      tile = scan_task_tile(P, cur, pc, blockIdx.x);   // uniform in the block
+      if (tile < 0) return;
+      ptile = true;
+    } else {
+      tile = blockIdx.x - nfirst;
+      ptile = false;
+    }
   } else {
     tile = blockIdx.x;
-    if (L.cnt[tile] == 0) return;                    // uniform in the block
+    ptile = P.np > 0 && L.cnt[tile] != 0;              // uniform in the block
   }
-  auto gather = [&] {
+  const int c0 = tile * kBlock + t;
+  const bool act0 = c0 < P.N;
+  const int cy = (act0 ? c0 : P.N - 1) / P.nx;
+  const int cx = (act0 ? c0 : P.N - 1) - cy * P.nx;
+
+  // ---- phase 1 (particle tiles): particles of the tile, and per cell the
+  // solid fraction f_s = sum_p f_s,p and sum_p f_s,p (u_s, u_s u_s); where
+  // overlapping disks cover more than the cell the shares are scaled to
+  // sum to one
+  if (ptile) {
     if (SCAN)
-      scan_block(bp, P, tile, cur, nxt, pc, partial_in, have, true, flags);
+      scan_block(sh.bp, P, tile, cur, nxt, pc, partial_in, have, true, flags);
     else
-      load_block_list(bp, tmp, L, tile, nxt, pc, flags);
-  };
-  int nin = 0;
-  auto part = [&](bool act, int x, int y, C rho, C jxs, C jys, PSums<C>& S) {
-    const int cnt = bp.cnt;
-    // each particle reaching the cell adds f_s,p to f_s and f_s,p (u_s,
-    // u_s u_s) to the sums; its share of sum_i (f_i - f*_i) e_i is
-    // f_s,p (rho u_s - j*)
-    for (int pass = 0; pass < 2; ++pass) {
-      // pass 1: overlapping disks' shares are scaled to sum to one (rare)
-      if (pass == 1 && !__syncthreads_or(act && S.S0 > (C)1)) break;
-      const bool over = S.S0 > (C)1;
-      const C inv = over ? (C)1 / S.S0 : (C)1;
-      for (int s = 0; s < cnt; ++s) {
-        double cfx = 0.0, cfy = 0.0, ctz = 0.0;
-        SlotGeom sg;
-        if (act && (pass == 0 || over) &&
-            particle_geometry(P, bp.X[s], bp.Y[s], bp.R[s], bp.Ux[s],
-                              bp.Uy[s], bp.Om[s], x, y, sg)) {
-          const C a = (C)sg.fs, ux = (C)sg.usx, uy = (C)sg.usy;
-          if (pass == 0) {
-            ++nin;
-            S.S0 += a;
-            S.S1x += a * ux;
-            S.S1y += a * uy;
-            S.S2xx += a * ux * ux;
-            S.S2yy += a * uy * uy;
-            S.S2xy += a * ux * uy;
-          }
-          const double k = pass == 0 ? 1.0 : (double)(inv - (C)1);
-          const double dpx = (double)(a * (rho * ux - jxs));
-          const double dpy = (double)(a * (rho * uy - jys));
-          cfx = -dpx * k;
-          cfy = -dpy * k;
-          ctz = -(sg.rx * dpy - sg.ry * dpx) * k;
-        }
-        block_sum3(cfx, cfy, ctz, red);
-        if (threadIdx.x == 0) {
-          double* o = partial + (size_t)bp.slot[s] * kRedVals;
-          if (pass == 0) {
-            o[0] = cfx; o[1] = cfy; o[2] = ctz;
-          } else {
-            o[0] += cfx; o[1] += cfy; o[2] += ctz;
-          }
-        }
-      }
-      if (pass == 1 && over) {
-        S.S1x *= inv; S.S1y *= inv; S.S2xx *= inv; S.S2yy *= inv;
-        S.S2xy *= inv;
-        S.S0 = (C)1;
+      load_block_list(sh.bp, sh.tmp, L, tile, nxt, pc, flags);
+    PSums<C> S;
+    S.S0 = S.S1x = S.S1y = S.S2xx = S.S2yy = S.S2xy = (C)0;
+    int nin = 0;
+    const int cnt = sh.bp.cnt;
+    for (int k = 0; k < cnt; ++k) {
+      SlotGeom sg;
+      if (act0 && particle_geometry(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.R[k],
+                                    sh.bp.Ux[k], sh.bp.Uy[k], sh.bp.Om[k],
+                                    cx, cy, sg)) {
+        const C a = (C)sg.fs, ux = (C)sg.usx, uy = (C)sg.usy;
+        ++nin;
+        S.S0 += a;
+        S.S1x += a * ux;
+        S.S1y += a * uy;
+        S.S2xx += a * ux * ux;
+        S.S2yy += a * uy * uy;
+        S.S2xy += a * ux * uy;
       }
     }
-    if (act && nin > P.kmax) atomicOr(flags, kFlagOverlap);
+    if (act0 && nin > P.kmax) atomicOr(flags, kFlagOverlap);
+    sh.S0raw[t] = S.S0;
+    if (S.S0 > (C)1) {
+      const C inv = (C)1 / S.S0;
+      S.S1x *= inv; S.S1y *= inv; S.S2xx *= inv; S.S2yy *= inv;
+      S.S2xy *= inv;
+      S.S0 = (C)1;
+    }
+    sh.S[0][t] = S.S0; sh.S[1][t] = S.S1x; sh.S[2][t] = S.S1y;
+    sh.S[3][t] = S.S2xx; sh.S[4][t] = S.S2yy; sh.S[5][t] = S.S2xy;
+  }
+
+  // ---- phase 2: the lattice update
+  const bool probe = SCAN && !ptile && lane < P.np;
+  double X = 0.0, Y = 0.0, Ux = 0.0, Uy = 0.0, R = 0.0;
+  auto pre = [&] {
+    if (probe) {
+      X = cur.X[lane];
+      Y = cur.Y[lane];
+      Ux = cur.Ux[lane];
+      Uy = cur.Uy[lane];
+      R = pc.R[lane];
+    }
   };
-  lattice_tile<PREC, OUT>(P, H, fin, fout, gin, gout, hin, hout, plane, tile,
-                          macro, flags, gather, part);
+  auto gather = [&]() -> bool {
+    if (!SCAN || ptile) return false;
+    bool hit = false;
+    if (probe) {
+      advance_position(P, X, Y, Ux, Uy);
+      const BlockRanges r = block_ranges(P, X, Y, R, kBlock);
+      hit = r.contains(tile);
+      // a centre the band-box logic cannot place: no tile serves it
+      if (r.n == 0 && tile == 0) atomicOr(flags, kFlagUnstable);
+    }
+    return __ballot(hit) != 0ull;   // a particle tile: the first group's
+  };
+  auto part = [&](bool, int, int, C rho, C jxs, C jys, PSums<C>& S) {
+    if (ptile) {
+      S.S0 = sh.S[0][t]; S.S1x = sh.S[1][t]; S.S1y = sh.S[2][t];
+      S.S2xx = sh.S[3][t]; S.S2yy = sh.S[4][t]; S.S2xy = sh.S[5][t];
+      sh.M[0][t] = rho; sh.M[1][t] = jxs; sh.M[2][t] = jys;
+    }
+  };
+  if (!lattice_tile<PREC, OUT>(P, H, fin, fout, gin, gout, hin, hout, plane,
+                               tile, macro, flags, pre, gather, part))
+    return;
+  if (!ptile) return;
+
+  // ---- phase 3 (particle tiles): momentum exchange.  Each particle's share
+  // of sum_i (f_i - f*_i) e_i in a cell is f_s,p (rho u_s - j*); the block
+  // sums of minus that (force) and of its moment about the centre (torque)
+  // go to the particle's partial slot of this tile.  Pass 2 adds the
+  // correction of the scaled shares (cells covered more than once; rare).
+  const C rho = sh.M[0][t], jxs = sh.M[1][t], jys = sh.M[2][t];
+  const C S0raw = sh.S0raw[t];
+  const int cnt = sh.bp.cnt;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1 && !__syncthreads_or(act0 && S0raw > (C)1)) break;
+    const bool over = pass == 1 && S0raw > (C)1;
+    const C inv = over ? (C)1 / S0raw : (C)1;
+    for (int k = 0; k < cnt; ++k) {
+      double cfx = 0.0, cfy = 0.0, ctz = 0.0;
+      SlotGeom sg;
+      if (act0 && (pass == 0 || over) &&
+          particle_geometry(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.R[k],
+                            sh.bp.Ux[k], sh.bp.Uy[k], sh.bp.Om[k], cx, cy,
+                            sg)) {
+        const C a = (C)sg.fs, ux = (C)sg.usx, uy = (C)sg.usy;
+        const double kk = pass == 0 ? 1.0 : (double)(inv - (C)1);
+        const double dpx = (double)(a * (rho * ux - jxs));
+        const double dpy = (double)(a * (rho * uy - jys));
+        cfx = -dpx * kk;
+        cfy = -dpy * kk;
+        ctz = -(sg.rx * dpy - sg.ry * dpx) * kk;
+      }
+      block_sum3(cfx, cfy, ctz, sh.red);
+      if (t == 0) {
+        double* o = partial + (size_t)sh.bp.slot[k] * kRedVals;
+        if (pass == 0) {
+          o[0] = cfx; o[1] = cfy; o[2] = ctz;
+        } else {
+          o[0] += cfx; o[1] += cfy; o[2] += ctz;
+        }
+      }
+    }
+  }
 }
 
 // -------------------------------------------------------------------------
@@ -1159,6 +1241,11 @@ __global__ __launch_bounds__(256) void k_particles(
     const Params P, PState cur, PState next, PConst pc, Lists L,
     const double* __restrict__ partial, int have_partials, int mode,
     int* flags) {
+  if (L.clr) {   // the previous step's block counts (the next fill's zeros)
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < P.nblocks;
+         k += gridDim.x * blockDim.x)
+      L.clr[k] = 0;
+  }
   const int lane = threadIdx.x & 63;
   const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (p >= P.np) return;  // whole wave
@@ -1342,66 +1429,38 @@ hipError_t launch_particles(const Params& P, PState cur, PState next,
   return hipGetLastError();
 }
 
-template <int PREC, bool OUT>
-static hipError_t lattice_t(const LatticeLaunch& a, hipStream_t s) {
-  typedef typename Prec<PREC>::S S;
-  typedef typename Prec<PREC>::H HT;
-  const Hot<typename Prec<PREC>::C> H = make_hot<typename Prec<PREC>::C>(*a.P);
-  hipExtLaunchKernelGGL((k_lattice<PREC, OUT>), dim3(a.P->nblocks),
-                        dim3(kBlock), 0, s, a.ev_start, a.ev_stop, 0, *a.P, H,
-                        (const S*)a.fi, (S*)a.fo, (const S*)a.gi, (S*)a.go,
-                        (const HT*)a.hin, (HT*)a.hout, a.plane, a.macro,
-                        a.flags);
-  return hipGetLastError();
-}
-
 template <int PREC, bool OUT, bool SCAN>
-static hipError_t particles_t(const LatticeLaunch& a, hipStream_t s) {
+static hipError_t step_t(const StepLaunch& a, hipStream_t s) {
   typedef typename Prec<PREC>::S S;
   typedef typename Prec<PREC>::H HT;
   const Params& P = *a.P;
   const Hot<typename Prec<PREC>::C> H = make_hot<typename Prec<PREC>::C>(P);
-  const unsigned grid = SCAN ? (unsigned)(P.np * P.maxr) : (unsigned)P.nblocks;
-  hipLaunchKernelGGL((k_lattice_particles<PREC, OUT, SCAN>), dim3(grid),
-                     dim3(kBlock), 0, s, P, H, (const S*)a.fi, (S*)a.fo,
-                     (const S*)a.gi, (S*)a.go, (const HT*)a.hin, (HT*)a.hout,
-                     a.plane, a.cur, a.nxt, a.pc, a.L, a.partial_in,
-                     a.partial_out, a.have, a.macro, a.flags);
+  const unsigned grid =
+      (unsigned)(SCAN ? P.np * P.maxr + P.nblocks : P.nblocks);
+  hipExtLaunchKernelGGL((k_step<PREC, OUT, SCAN>), dim3(grid), dim3(kBlock),
+                        0, s, a.ev_start, a.ev_stop, 0, P, H, (const S*)a.fi,
+                        (S*)a.fo, (const S*)a.gi, (S*)a.go, (const HT*)a.hin,
+                        (HT*)a.hout, a.plane, a.cur, a.nxt, a.pc, a.L,
+                        a.partial_in, a.partial_out, a.have, a.macro,
+                        a.flags);
   return hipGetLastError();
 }
 
 template <int PREC>
-static hipError_t lattice_p(const LatticeLaunch& a, hipStream_t s) {
-  return a.out ? lattice_t<PREC, true>(a, s) : lattice_t<PREC, false>(a, s);
-}
-
-template <int PREC>
-static hipError_t particles_p(const LatticeLaunch& a, hipStream_t s) {
+static hipError_t step_p(const StepLaunch& a, hipStream_t s) {
   if (a.P->scan)
-    return a.out ? particles_t<PREC, true, true>(a, s)
-                 : particles_t<PREC, false, true>(a, s);
-  return a.out ? particles_t<PREC, true, false>(a, s)
-               : particles_t<PREC, false, false>(a, s);
+    return a.out ? step_t<PREC, true, true>(a, s)
+                 : step_t<PREC, false, true>(a, s);
+  return a.out ? step_t<PREC, true, false>(a, s)
+               : step_t<PREC, false, false>(a, s);
 }
 
-hipError_t launch_lattice(int prec, const LatticeLaunch& a, hipStream_t s) {
+hipError_t launch_step(int prec, const StepLaunch& a, hipStream_t s) {
   switch (prec) {
-    case VLB_FP64: return lattice_p<VLB_FP64>(a, s);
-    case VLB_FP32: return lattice_p<VLB_FP32>(a, s);
-    case VLB_FP16_SHIFT: return lattice_p<VLB_FP16_SHIFT>(a, s);
-    case VLB_BF16_SHIFT: return lattice_p<VLB_BF16_SHIFT>(a, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_lattice_particles(int prec, const LatticeLaunch& a,
-                                    hipStream_t s) {
-  if (a.P->np == 0) return hipSuccess;
-  switch (prec) {
-    case VLB_FP64: return particles_p<VLB_FP64>(a, s);
-    case VLB_FP32: return particles_p<VLB_FP32>(a, s);
-    case VLB_FP16_SHIFT: return particles_p<VLB_FP16_SHIFT>(a, s);
-    case VLB_BF16_SHIFT: return particles_p<VLB_BF16_SHIFT>(a, s);
+    case VLB_FP64: return step_p<VLB_FP64>(a, s);
+    case VLB_FP32: return step_p<VLB_FP32>(a, s);
+    case VLB_FP16_SHIFT: return step_p<VLB_FP16_SHIFT>(a, s);
+    case VLB_BF16_SHIFT: return step_p<VLB_BF16_SHIFT>(a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -251,6 +251,8 @@ def vlb_timing_enable(h, on: bool) -> None:
 
 
 def vlb_timing_read(h):
+    """(summed ms, launches) of the timed lattice-step launches since the
+    last read."""
     ms, n = ctypes.c_double(), ctypes.c_int64()
     _check(lib().vlb_timing_read(h, ctypes.byref(ms), ctypes.byref(n)),
            "vlb_timing_read", h)
