@@ -31,8 +31,10 @@ BYTES_PER_CELL = {"fp64": 2 * 18 * 8 + 2 * 8, "fp32": 2 * 18 * 4 + 2 * 4,
                   "fp16s": 2 * 18 * 2 + 2 * 4, "bf16s": 2 * 18 * 2 + 2 * 4}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16 storage, f32 arithmetic",
          "bf16s": "bf16 storage, f32 arithmetic"}
+# the step kernel and its launch shape (tile mapping, grid) come from these
 KERNEL_SOURCES = ["paper_2410_23802_amd/csrc/vlb_kernels.hip",
-                  "paper_2410_23802_amd/csrc/vlb_internal.h"]
+                  "paper_2410_23802_amd/csrc/vlb_internal.h",
+                  "paper_2410_23802_amd/csrc/vlb_api.hip"]
 
 
 def kernel_hash() -> str:
@@ -44,9 +46,11 @@ def kernel_hash() -> str:
 
 
 def measured_traffic(workload: str, precision: str):
-    """HBM bytes per lattice launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_lattice_{workload}.json")
+    """HBM bytes per step-kernel launch (FETCH_SIZE + WRITE_SIZE, each
+    scaled by what it reads for a copy of known size) from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source;
+    else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_k_step_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -89,7 +93,7 @@ def run_gpu(vlb, d, ps, precision, steps, warmup):
     }
 
 
-def cpu_baseline(d, ps, target_s=15.0):
+def cpu_baseline(d, ps, target_s=20.0):
     """The FP64 oracle as it stands, on a bounded sample of the same
     workload: as many steps as take about `target_s` seconds."""
     from oracle import oracle as O
@@ -113,6 +117,21 @@ def cpu_baseline(d, ps, target_s=15.0):
                       f"{threads} OpenMP threads, {dt:.1f} s"}
 
 
+def copy_probe(torch, nbytes):
+    """Five plain copies of nbytes between two device buffers: each reads
+    and writes exactly nbytes, which calibrates the FETCH_SIZE / WRITE_SIZE
+    counters against the bytes a kernel is known to move."""
+    n = max(1, nbytes // 4)
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(f"# copy probe: 5 x {4 * n} bytes", file=sys.stderr, flush=True)
+    del x, y
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +140,9 @@ def main():
     ap.add_argument("--precisions", default="fp64,fp32,fp16s,bf16s")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the oracle CPU baseline")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="first run 5 device-to-device copies of BYTES bytes "
+                         "(the known-size reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -138,6 +160,8 @@ def main():
         from paper_2410_23802_amd import build as hb
         hb.build()
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(torch, args.copy_probe)
 
     workload = "c2_channel"
     d, ps = W.c2_channel()

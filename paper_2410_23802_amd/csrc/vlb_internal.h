@@ -50,6 +50,10 @@ struct Params {
   int np, maxb;
   int scan;           // 1: scan form (few particles, one launch per step)
   int maxr;           // scan form: bound on the tiles one particle reaches
+  int nfirst;         // step kernel: blocks of the particle-tile group
+                      // (scan form: np * maxr rounded up to 8; else 0)
+  int xcd_group;      // step kernel: consecutive tiles per XCD group
+  int stream_blocks;  // step kernel: blocks of the streaming group
 };
 
 // The constants the per-cell arithmetic uses, in the compute precision C

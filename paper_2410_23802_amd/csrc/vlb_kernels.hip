@@ -974,6 +974,18 @@ __device__ __forceinline__ int scan_task_tile(const Params& P, PState cur,
   return tile;
 }
 
+// Tile of the k-th block of the streaming group.  Workgroups are dealt to
+// the 8 XCDs in turn, so block k runs on XCD x = k % 8.  Tiles come in
+// groups of G consecutive tiles, dealt to the XCDs in turn, and each XCD
+// walks its groups' tiles in order: the rows a tile pulls from its
+// neighbours are then mostly in the XCD's own L2 already.  (The group
+// starts at a multiple of 8 blocks.)  Tiles >= nblocks: none.
+__device__ __forceinline__ int stream_tile(const Params& P, int k) {
+  const int x = k & 7, j = k >> 3;
+  const int gi = j / P.xcd_group, o = j - gi * P.xcd_group;
+  return (gi * 8 + x) * P.xcd_group + o;
+}
+
 // LDS of a particle tile: the staged particles, the per-cell particle sums
 // (written before the lattice update, read by it) and the per-cell rho, j*
 // (written by the lattice update, read by the momentum exchange).
@@ -1027,19 +1039,14 @@ __attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 1))) void k_step(
 
   int tile;
   bool ptile;
-  if (SCAN) {
-    const int nfirst = P.np * P.maxr;
-    if ((int)blockIdx.x < nfirst) {
-      tile = scan_task_tile(P, cur, pc, blockIdx.x);   // uniform in the block
-      if (tile < 0) return;
-      ptile = true;
-    } else {
-      tile = blockIdx.x - nfirst;
-      ptile = false;
-    }
+  if (SCAN && (int)blockIdx.x < P.nfirst) {
+    tile = scan_task_tile(P, cur, pc, blockIdx.x);     // uniform in the block
+    if (tile < 0) return;
+    ptile = true;
   } else {
-    tile = blockIdx.x;
-    ptile = P.np > 0 && L.cnt[tile] != 0;              // uniform in the block
+    tile = stream_tile(P, blockIdx.x - P.nfirst);
+    if (tile >= P.nblocks) return;
+    ptile = !SCAN && P.np > 0 && L.cnt[tile] != 0;     // uniform in the block
   }
   const int c0 = tile * kBlock + t;
   const bool act0 = c0 < P.N;
@@ -1435,8 +1442,7 @@ static hipError_t step_t(const StepLaunch& a, hipStream_t s) {
   typedef typename Prec<PREC>::H HT;
   const Params& P = *a.P;
   const Hot<typename Prec<PREC>::C> H = make_hot<typename Prec<PREC>::C>(P);
-  const unsigned grid =
-      (unsigned)(SCAN ? P.np * P.maxr + P.nblocks : P.nblocks);
+  const unsigned grid = (unsigned)(P.nfirst + P.stream_blocks);
   hipExtLaunchKernelGGL((k_step<PREC, OUT, SCAN>), dim3(grid), dim3(kBlock),
                         0, s, a.ev_start, a.ev_stop, 0, P, H, (const S*)a.fi,
                         (S*)a.fo, (const S*)a.gi, (S*)a.go, (const HT*)a.hin,
