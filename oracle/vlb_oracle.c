@@ -13,6 +13,12 @@
  * Where the paper leaves a choice open, the reading taken is stated at the
  * point of use (tagged "Reading:").
  *
+ * Parity unpinned: the particle repulsion (or_collision_force).  The paper
+ * adopts a collision model without giving its law or constants, so only
+ * invariants pin it here (force at contact equals the stiffness, zero at
+ * and beyond the range, equal and opposite pair forces, a wall acting as a
+ * mirror-image particle); the quadratic law itself is a reading.
+ *
  * One step n -> n+1 (stage numbers are used in comments below):
  *   1  particle update from the force and torque of step n   (Sec. 2.3)
  *   2  cell ownership and solid fraction at n+1               (Sec. 2, Fig. 1)
@@ -408,7 +414,8 @@ int or_overlap_count(const or_state* s) { return s->overlaps; }
 /* ------------------------------------------------------------------ */
 /* stage 1: particle dynamics (Sec. 2.3)                                */
 
-/* Reading of the collision model the paper adopts without giving it:
+/* Parity unpinned (law and constants).  Reading of the collision model
+ * the paper adopts without giving it:
  * a short-range repulsion of range zeta,
  *   F_ij = k_pp ((R_i + R_j + zeta - d_ij) / zeta)^2 (X_i - X_j) / d_ij
  * for d_ij < R_i + R_j + zeta, and against each wall the same law applied

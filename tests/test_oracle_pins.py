@@ -312,3 +312,77 @@ def test_couette_exact_linear_profile(oracle_mod):
     assert run(1e-4) < 1e-13
     e1, e2 = run(0.02), run(0.01)
     assert 7.0 < e1 / e2 < 9.0
+
+
+# --------------------------------------------------------------------------
+# Collision model (reading of the cited model): invariants that hold for any
+# short-range central repulsion with the descriptor's meaning of its
+# constants -- the law's shape and constants themselves are a reading the
+# paper does not fix (parity unpinned).
+
+
+def _pair(O, X1, Y1, R1, X2, Y2, R2, nx=200, ny=200, periodic=True, kpp=3e-3,
+          kpw=5e-3, zeta=2.0):
+    d = W.domain(nx, ny, coll_range=zeta, coll_stiff_pp=kpp,
+                 coll_stiff_pw=kpw)
+    if not periodic:
+        d = W.walls(d)
+    ps = [W.particle(X1, Y1, R1), W.particle(X2, Y2, R2)]
+    o = O.Oracle(d, ps)
+    return o.collision_force(0), o.collision_force(1)
+
+
+def test_collision_equal_and_opposite_along_centre_line(oracle_mod):
+    """F_ij = -F_ji, directed from j to i, also across a periodic face
+    (minimum image)."""
+    O = oracle_mod
+    for (X1, Y1, X2, Y2) in ((100.0, 100.0, 112.5, 104.0),
+                             (3.0, 50.0, 190.0, 53.0),       # wraps in x
+                             (70.0, 198.5, 66.0, 9.0)):      # wraps in y
+        (f1x, f1y), (f2x, f2y) = _pair(O, X1, Y1, 7.0, X2, Y2, 6.0)
+        assert math.hypot(f1x, f1y) > 0
+        assert f1x == -f2x and f1y == -f2y
+        dx = X1 - X2
+        dy = Y1 - Y2
+        dx -= 200.0 * round(dx / 200.0)
+        dy -= 200.0 * round(dy / 200.0)
+        # parallel to the centre line, pointing away from the other disk
+        assert abs(f1x * dy - f1y * dx) < 1e-15 * math.hypot(f1x, f1y) * 20
+        assert f1x * dx + f1y * dy > 0
+
+
+def test_collision_contact_value_and_range(oracle_mod):
+    """At contact (gap 0) the force equals the stiffness constant; at and
+    beyond the range zeta it is zero; inside it the force decreases
+    monotonically with the gap and vanishes continuously at the range."""
+    O = oracle_mod
+    R1, R2, zeta, k = 7.0, 6.0, 2.0, 3e-3
+    (fx, fy), _ = _pair(O, 100.0, 100.0, R1, 100.0 + R1 + R2, 100.0, R2,
+                        kpp=k, zeta=zeta)
+    assert abs(math.hypot(fx, fy) - k) < 1e-15 and fx < 0
+    for gap in (zeta, zeta + 0.5, 10.0):
+        (fx, fy), _ = _pair(O, 100.0, 100.0, R1, 100.0 + R1 + R2 + gap,
+                            100.0, R2, kpp=k, zeta=zeta)
+        assert fx == 0.0 and fy == 0.0
+    mags = []
+    for gap in np.linspace(0.0, zeta * (1 - 1e-9), 9):
+        (fx, fy), _ = _pair(O, 100.0, 100.0, R1, 100.0 + R1 + R2 + gap,
+                            100.0, R2, kpp=k, zeta=zeta)
+        mags.append(math.hypot(fx, fy))
+    assert all(a > b for a, b in zip(mags, mags[1:]))
+    assert mags[-1] < 1e-15 * k
+
+
+def test_collision_wall_is_mirror_pair(oracle_mod):
+    """Against a wall a particle feels what it would feel from its mirror
+    image (same radius, stiffness k_pw) across the wall."""
+    O = oracle_mod
+    R, kpw, delta = 6.0, 5e-3, 6.5          # centre 6.5 from the y- wall
+    d = W.walls(W.domain(200, 200, coll_range=2.0, coll_stiff_pp=1e-3,
+                         coll_stiff_pw=kpw))
+    o = O.Oracle(d, [W.particle(100.0, delta, R)])
+    wx, wy = o.collision_force(0)
+    (px, py), _ = _pair(O, 100.0, 100.0, R, 100.0, 100.0 - 2 * delta, R,
+                        kpp=kpw)
+    assert wy > 0 and wx == 0.0
+    assert abs(wy - py) <= 1e-15 * abs(py) and px == 0.0
