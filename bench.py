@@ -93,6 +93,47 @@ def run_gpu(vlb, d, ps, precision, steps, warmup):
     }
 
 
+def run_batch(vlb, steps, warmup):
+    """The 256 uneven single-particle domains in FP32: one autotuned batch
+    (one launch per step, graph replay) against the same domains run one at
+    a time, each for the same steps.  Aggregate MLUPS = all cells x steps /
+    wall time."""
+    import torch
+    import workloads as W
+    cases = W.c5_batch()
+    b = vlb.Batch(cases, "fp32").init()
+    tune = b.autotune(3)
+    cells = b.cells
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    batch_s = time.perf_counter() - t0
+    b.close()
+    batched = cells * steps / batch_s / 1e6
+    seq = 0.0
+    for d, ps in cases:
+        dom = vlb.Domain(d, ps, "fp32").init()
+        dom.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dom.step(steps)
+        seq += time.perf_counter() - t0
+        dom.close()
+    single = cells * steps / seq / 1e6
+    print(f"# batch: {len(cases)} domains, {cells} cells: {batched:.0f} MLUPS "
+          f"batched vs {single:.0f} one at a time ({batched / single:.2f}x); "
+          f"tuning {tune}", file=sys.stderr, flush=True)
+    return {"workload": "c5_batch", "domains": len(cases), "cells": cells,
+            "precision": "fp32 storage and arithmetic, fp64 particle sums",
+            "steps": steps, "mlups_batched": round(batched, 1),
+            "ms_per_step_batched": round(batch_s * 1e3 / steps, 4),
+            "mlups_one_at_a_time": round(single, 1),
+            "speedup": round(batched / single, 3),
+            "tuning": {k: (round(v, 2) if isinstance(v, float) else v)
+                       for k, v in tune.items()}}
+
+
 def cpu_baseline(d, ps, target_s=20.0):
     """The FP64 oracle as it stands, on a bounded sample of the same
     workload: as many steps as take about `target_s` seconds."""
@@ -140,6 +181,8 @@ def main():
     ap.add_argument("--precisions", default="fp64,fp32,fp16s,bf16s")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the oracle CPU baseline")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-domains measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="first run 5 device-to-device copies of BYTES bytes "
                          "(the known-size reference for HBM counters)")
@@ -220,6 +263,8 @@ def main():
                 "bytes_per_cell": BYTES_PER_CELL[p],
             } for p in precs},
     }
+    if not args.no_batch:
+        line["batch"] = run_batch(vlb, min(args.steps, 100), 4)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(d, ps)
     print(json.dumps(line), flush=True)

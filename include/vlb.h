@@ -200,6 +200,76 @@ const char* vlb_last_error(const vlb_ctx* ctx);
 /* Free the context and its device memory (NULL is ignored). */
 void vlb_destroy(vlb_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent domains (each the problem of Sec. 2 on its own
+ * grid, with its own parameters and up to 64 particles) advanced together.
+ * One launch of one kernel advances every domain by a step; a fixed set of
+ * persistent blocks walks a table of tiles that lists every domain's
+ * particle tiles first.  Results of a domain are those the single-domain
+ * calls give for it, bit for bit, whatever the batch and the tuning.
+ * All domains share one precision and step in lockstep.  The batch owns a
+ * HIP stream of default priority; every call is complete on return. */
+
+typedef struct vlb_batch vlb_batch;
+
+/* Launch shape of the batch step kernel.  grid_blocks: persistent blocks, a
+ * multiple of 8 (0: one block per task).  order 0: tiles listed domain by
+ * domain; 1: tiles dealt to the 8 XCDs in contiguous bands.  use_graph:
+ * replay steady-state steps from a captured two-step hipGraph.
+ * us_per_step: the time vlb_batch_autotune measured for the choice. */
+typedef struct {
+  int32_t grid_blocks;
+  int32_t order;
+  int32_t use_graph;
+  double  us_per_step;
+} vlb_batch_tuning;
+
+/* Create ncases domains: descs[ncases] (copied), nparticles[ncases] in
+ * 0..64 and the particles of all domains back to back in `particles`
+ * (host memory, copied; may be NULL when every count is 0).  VLB_EINVAL for
+ * a bad descriptor (the message names the domain) or mixed precisions,
+ * VLB_ENOMEM when the device memory does not suffice. */
+vlb_status vlb_batch_create(int32_t ncases, const vlb_domain_desc* descs,
+                            const int32_t* nparticles,
+                            const vlb_particle_desc* particles,
+                            vlb_batch** out);
+
+/* Initial state of every domain (as vlb_init). */
+vlb_status vlb_batch_init(vlb_batch* b);
+
+/* Advance every domain by nsteps >= 0 steps.  VLB_EUNSTABLE / VLB_EOVERLAP
+ * name the first failing domain in vlb_batch_last_error; the batch must
+ * then be initialised again. */
+vlb_status vlb_batch_step(vlb_batch* b, int64_t nsteps);
+
+/* Time every candidate launch shape (grid_blocks 4, 8 and 16 per compute
+ * unit and one block per task, both orders) over `steps` steps, keep the
+ * fastest (with use_graph = 1) and initialise the batch again.  Only on a
+ * freshly initialised batch (VLB_ESTATE otherwise).  chosen may be NULL. */
+vlb_status vlb_batch_autotune(vlb_batch* b, int32_t steps,
+                              vlb_batch_tuning* chosen);
+vlb_status vlb_batch_set_tuning(vlb_batch* b, const vlb_batch_tuning* t);
+vlb_status vlb_batch_get_tuning(const vlb_batch* b, vlb_batch_tuning* t);
+
+/* Reads of domain i, as vlb_read_field and vlb_read_particles. */
+vlb_status vlb_batch_read_field(vlb_batch* b, int32_t i, int32_t field,
+                                double* dst, int32_t dst_is_device);
+vlb_status vlb_batch_read_particles(vlb_batch* b, int32_t i, int32_t n,
+                                    vlb_particle_state* dst);
+
+/* Number of domains; total cells; steps since vlb_batch_init; device
+ * bytes held. */
+int32_t vlb_batch_size(const vlb_batch* b);
+int64_t vlb_batch_cells(const vlb_batch* b);
+int64_t vlb_batch_step_count(const vlb_batch* b);
+size_t vlb_batch_device_bytes(const vlb_batch* b);
+
+/* Message for the last failing call on b (or on creation when b is NULL). */
+const char* vlb_batch_last_error(const vlb_batch* b);
+
+/* Free the batch, its domains and its stream (NULL is ignored). */
+void vlb_batch_destroy(vlb_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,52 +9,9 @@
 #include <string>
 #include <vector>
 
-#include "vlb_internal.h"
+#include "vlb_context.h"
 
 using namespace vlb;
-
-struct vlb_ctx {
-  vlb_domain_desc d;
-  hipStream_t stream = nullptr;
-  int device = 0;
-  Params P;
-  int prec = 0;
-  size_t plane = 0, pop_elem = 0, h_elem = 0;
-  void* f[2] = {nullptr, nullptr};
-  void* g[2] = {nullptr, nullptr};
-  void* h[2] = {nullptr, nullptr};   // [df_s/dt] carrier, alternating
-  int cur = 0;                       // f[cur], g[cur], h[cur]: step n
-  double* macro = nullptr;
-  int* blk_cnt[2] = {nullptr, nullptr};  // block counts, double buffered
-  int lpar = 0;                          // blk_cnt[lpar]: the current lists
-  int2* blk_ent = nullptr;
-  // particles
-  int np = 0;
-  int maxb = 0;
-  double* pmem[2] = {nullptr, nullptr};
-  int* pslot[2] = {nullptr, nullptr};
-  PState ps[2];
-  int pcur = 0;
-  double* pconst = nullptr;
-  int* pfixed = nullptr;
-  PConst pc;
-  double* partial[2] = {nullptr, nullptr};  // step n / step n+1, alternating
-  int pp = 0;                                // partial[pp]: the latest pass
-  double* thermal4 = nullptr;
-  std::vector<vlb_particle_desc> parts;
-  // status
-  int* flags = nullptr;
-  int* flags_host = nullptr;
-  int have_partials = 0;
-  int64_t step = 0;
-  bool initialized = false;
-  size_t dev_bytes = 0;
-  // timing
-  bool timing = false;
-  std::vector<hipEvent_t> ev;
-  size_t ev_used = 0;
-  std::string err;
-};
 
 static std::string g_create_error;
 
@@ -232,6 +189,60 @@ static void derive_params(vlb_ctx* c) {
   P.maxb = 0;
 }
 
+// The current block lists (read by the lattice, init and ownership kernels).
+static Lists lists(vlb_ctx* c) {
+  Lists L;
+  L.cnt = c->blk_cnt[c->lpar];
+  L.ent = c->blk_ent;
+  L.clr = nullptr;
+  return L;
+}
+
+// Lists for a particle pass that bins: it fills the zeroed buffer and clears
+// the current one; the filled buffer becomes current.
+static Lists bin_lists(vlb_ctx* c) {
+  Lists L;
+  L.cnt = c->blk_cnt[1 - c->lpar];
+  L.ent = c->blk_ent;
+  L.clr = c->blk_cnt[c->lpar];
+  c->lpar ^= 1;
+  return L;
+}
+
+// The buffers of the next step of context c.
+StepBufs vlb::context_step_bufs(vlb_ctx* c) {
+  StepBufs B;
+  B.fi = c->f[c->cur];
+  B.fo = c->f[1 - c->cur];
+  B.gi = c->g[c->cur];
+  B.go = c->g[1 - c->cur];
+  B.hin = c->h[c->cur];
+  B.hout = c->h[1 - c->cur];
+  B.plane = c->plane;
+  B.cur = c->ps[c->pcur];
+  B.nxt = c->ps[1 - c->pcur];
+  B.pc = c->pc;
+  B.L = lists(c);
+  B.partial_in = c->partial[c->pp];
+  B.partial_out = c->partial[1 - c->pp];
+  B.macro = c->macro;
+  B.flags = c->flags;
+  return B;
+}
+
+// Bookkeeping of n steps taken (by one_step or by a batch launch).
+void vlb::context_advance(vlb_ctx* c, int64_t n) {
+  if (n <= 0) return;
+  const int flip = (int)(n & 1);
+  if (c->np > 0) {
+    c->have_partials = 1;
+    c->pcur ^= flip;
+    c->pp ^= flip;
+  }
+  c->cur ^= flip;
+  c->step += n;
+}
+
 extern "C" {
 
 vlb_status vlb_create(const vlb_domain_desc* desc, void* hip_stream,
@@ -356,26 +367,6 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
   return VLB_OK;
 }
 
-// The current block lists (read by the lattice, init and ownership kernels).
-static Lists lists(vlb_ctx* c) {
-  Lists L;
-  L.cnt = c->blk_cnt[c->lpar];
-  L.ent = c->blk_ent;
-  L.clr = nullptr;
-  return L;
-}
-
-// Lists for a particle pass that bins: it fills the zeroed buffer and clears
-// the current one; the filled buffer becomes current.
-static Lists bin_lists(vlb_ctx* c) {
-  Lists L;
-  L.cnt = c->blk_cnt[1 - c->lpar];
-  L.ent = c->blk_ent;
-  L.clr = c->blk_cnt[c->lpar];
-  c->lpar ^= 1;
-  return L;
-}
-
 static vlb_status check_flags(vlb_ctx* c) {
   HIP_TRY(c, hipMemcpyAsync(c->flags_host, c->flags, sizeof(int),
                             hipMemcpyDeviceToHost, c->stream));
@@ -442,12 +433,12 @@ vlb_status vlb_init(vlb_ctx* c) {
   return st;
 }
 
+
 // One time step: (list form) the particle pass, which advances the
 // particles and fills the block lists, then the lattice step.
 static vlb_status one_step(vlb_ctx* c, bool last) {
   PState cur = c->ps[c->pcur], nxt = c->ps[1 - c->pcur];
   const double* pin = c->partial[c->pp];
-  double* pout = c->partial[1 - c->pp];
   if (c->np > 0 && !c->P.scan)
     HIP_TRY(c, launch_particles(c->P, cur, nxt, c->pc, bin_lists(c), pin,
                                 c->have_partials, kModeUpdate, c->flags,
@@ -455,22 +446,8 @@ static vlb_status one_step(vlb_ctx* c, bool last) {
   StepLaunch a;
   a.P = &c->P;
   a.out = last;
-  a.fi = c->f[c->cur];
-  a.fo = c->f[1 - c->cur];
-  a.gi = c->g[c->cur];
-  a.go = c->g[1 - c->cur];
-  a.hin = c->h[c->cur];
-  a.hout = c->h[1 - c->cur];
-  a.plane = c->plane;
-  a.cur = cur;
-  a.nxt = nxt;
-  a.pc = c->pc;
-  a.L = lists(c);
-  a.partial_in = pin;
-  a.partial_out = pout;
   a.have = c->have_partials;
-  a.macro = c->macro;
-  a.flags = c->flags;
+  a.B = context_step_bufs(c);
   a.ev_start = a.ev_stop = nullptr;
   if (c->timing) {
     if (c->ev_used + 2 > c->ev.size()) {
@@ -485,15 +462,10 @@ static vlb_status one_step(vlb_ctx* c, bool last) {
     c->ev_used += 2;
   }
   HIP_TRY(c, launch_step(c->prec, a, c->stream));
-  if (c->np > 0) {
-    c->have_partials = 1;
-    c->pcur ^= 1;
-    c->pp ^= 1;
-  }
-  c->cur ^= 1;
-  c->step++;
+  context_advance(c, 1);
   return VLB_OK;
 }
+
 
 vlb_status vlb_step(vlb_ctx* c, int64_t nsteps) {
   if (!c) return VLB_EINVAL;

@@ -1,0 +1,1168 @@
+// vlb_device.h -- device code shared by the kernels of the volumetric
+// lattice Boltzmann step for thermal particulate flow with conjugate heat
+// transfer (arXiv 2410.23802): storage forms, geometry, reductions, the
+// particle helpers and the per-tile step (private to the library).
+//
+// Data layout in HBM (one domain):
+//   populations  f, g : 9 planes each, plane stride `plane` >= N = nx*ny,
+//                       cell c = j*nx + i (x fastest); two copies (A/B),
+//                       pull streaming reads A and writes B.
+//   h                 : 1 value per cell, the carrier h = 2 f_s + [df_s/dt]
+//                       of the eq. dfs_dt recursion, two copies.
+//   macro             : rho, ux, uy, T, f_s, [df_s/dt] as FP64 planes,
+//                       written only by the last step of a vlb_step call.
+//   partials          : FP64 shares of the momentum-exchange force and
+//                       torque, one slot per (particle, 256-cell tile).
+//
+// A step is one launch over all tiles in two roles (see step_task): the
+// tiles particles reach run the volumetric step and the momentum exchange,
+// the others a plain update.  The particles are handled in one of two forms:
+//   scan (few particles): each particle tile finds the particles whose band
+//     box reaches it at the new position X + U (forward Euler needs no force
+//     for the position) and rebuilds their new velocities itself from the
+//     previous step's partials -- the same inputs in the same order in every
+//     tile, hence the same bits; the first tile a particle reaches stores its
+//     new state.  Partials [particle][tile].
+//   list (many particles): k_particles first updates every particle (one
+//     wave each) and fills per-tile particle lists.  Partials [particle][k-th
+//     tile reached].
+// No floating-point atomics anywhere: every sum runs in a fixed order, so a
+// run is bitwise reproducible.
+#pragma once
+
+#include <math.h>
+
+#include <hip/hip_ext.h>
+
+#include "vlb_internal.h"
+
+namespace vlb {
+
+// -------------------------------------------------------------------------
+// Storage forms.  Populations are stored as deviations from a fixed
+// per-direction reference (f_i - w_i rho_0, g_i - w_i c_ref T_0) and the
+// kernel computes on deviations, so the low-Mach momentum is never formed
+// by cancelling O(1) numbers.  FP64 uses a zero reference (literal values);
+// FP16/BF16 compute in FP32 and keep the [df_s/dt] carrier in FP32.
+
+template <int PREC>
+struct Prec;
+
+template <>
+struct Prec<VLB_FP64> {
+  typedef double S;
+  typedef double C;
+  typedef double H;
+  static __device__ __forceinline__ C ld(const S* p, size_t i) { return p[i]; }
+  static __device__ __forceinline__ void st(S* p, size_t i, C v) { p[i] = v; }
+};
+
+template <>
+struct Prec<VLB_FP32> {
+  typedef float S;
+  typedef float C;
+  typedef float H;
+  static __device__ __forceinline__ C ld(const S* p, size_t i) { return p[i]; }
+  static __device__ __forceinline__ void st(S* p, size_t i, C v) { p[i] = v; }
+};
+
+template <>
+struct Prec<VLB_FP16_SHIFT> {
+  typedef _Float16 S;
+  typedef float C;
+  typedef float H;
+  static __device__ __forceinline__ C ld(const S* p, size_t i) {
+    return (float)p[i];
+  }
+  static __device__ __forceinline__ void st(S* p, size_t i, C v) {
+    p[i] = (_Float16)v;
+  }
+};
+
+template <>
+struct Prec<VLB_BF16_SHIFT> {
+  typedef uint16_t S;
+  typedef float C;
+  typedef float H;
+  static __device__ __forceinline__ C ld(const S* p, size_t i) {
+    return __uint_as_float(((uint32_t)p[i]) << 16);
+  }
+  static __device__ __forceinline__ void st(S* p, size_t i, C v) {
+    // round to nearest even on the upper 16 bits
+    uint32_t b = __float_as_uint(v);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    p[i] = (uint16_t)(b >> 16);
+  }
+};
+
+// -------------------------------------------------------------------------
+// Geometry (FP64 in every storage form).
+
+// Nearest periodic copy of a particle coordinate seen from a node.
+__device__ __forceinline__ double near_copy(double Xp, double node, double L,
+                                            int periodic) {
+  if (periodic) {
+    double half = 0.5 * L;
+    if (node - Xp > half) return Xp + L;
+    if (Xp - node > half) return Xp - L;
+  }
+  return Xp;
+}
+
+// Integer ownership: the point of cell (i, j) nearest to the centre lies
+// strictly inside the circle.  Evaluated without fused multiply-adds so the
+// decision is the same on every IEEE machine.
+__device__ __noinline__ bool owns_cell(double X, double Y, double R, int i,
+                                       int j) {
+#pragma clang fp contract(off)
+  double lo = (double)i, hi = (double)(i + 1);
+  double nx_ = X < lo ? lo : (X > hi ? hi : X);
+  double ddx = X - nx_;
+  lo = (double)j;
+  hi = (double)(j + 1);
+  double ny_ = Y < lo ? lo : (Y > hi ? hi : Y);
+  double ddy = Y - ny_;
+  double q = ddx * ddx;
+  q = q + ddy * ddy;
+  return q < R * R;
+}
+
+// The cell lies in the closed disk: its corner farthest from the centre does.
+__device__ __noinline__ bool cell_within(double X, double Y, double R, int i,
+                                         int j) {
+#pragma clang fp contract(off)
+  double ex = (X < (double)i + 0.5) ? (double)(i + 1) - X : X - (double)i;
+  double ey = (Y < (double)j + 0.5) ? (double)(j + 1) - Y : Y - (double)j;
+  double q = ex * ex;
+  q = q + ey * ey;
+  return q <= R * R;
+}
+
+// Signed area of (disk of radius R at the origin) intersected with the
+// triangle (origin, P, Q): the chord part of PQ inside the circle gives a
+// triangle, the parts outside give circular sectors.
+__device__ double tri_disk_area(double px, double py, double qx, double qy,
+                                double R) {
+  const double half_r2 = 0.5 * R * R;
+  double dx = qx - px, dy = qy - py;
+  double a = dx * dx + dy * dy;
+  double b = px * dx + py * dy;
+  double c = (px * px + py * py) - R * R;
+  double disc = b * b - a * c;
+  double s1 = 1.0, s2 = 0.0;
+  if (disc > 0.0) {
+    double r = sqrt(disc);
+    s1 = fmin(fmax((-b - r) / a, 0.0), 1.0);
+    s2 = fmin(fmax((-b + r) / a, 0.0), 1.0);
+  }
+  if (!(s1 < s2)) return half_r2 * atan2(px * qy - py * qx, px * qx + py * qy);
+  double ax = px + s1 * dx, ay = py + s1 * dy;
+  double bx = px + s2 * dx, by = py + s2 * dy;
+  double area = 0.5 * (ax * by - ay * bx);
+  if (s1 > 0.0) area += half_r2 * atan2(px * ay - py * ax, px * ax + py * ay);
+  if (s2 < 1.0) area += half_r2 * atan2(bx * qy - by * qx, bx * qx + by * qy);
+  return area;
+}
+
+// Exact share of cell (i, j) covered by the disk (centre X, Y, radius R),
+// by Green's theorem over the four edges of the square taken
+// counter-clockwise.
+__device__ double covered_share(double X, double Y, double R, int i, int j) {
+  double x0 = (double)i - X, x1 = (double)(i + 1) - X;
+  double y0 = (double)j - Y, y1 = (double)(j + 1) - Y;
+  double A = tri_disk_area(x0, y0, x1, y0, R) + tri_disk_area(x1, y0, x1, y1, R) +
+             tri_disk_area(x1, y1, x0, y1, R) + tri_disk_area(x0, y1, x0, y0, R);
+  return fmin(fmax(A, 0.0), 1.0);
+}
+
+// -------------------------------------------------------------------------
+// Reductions (fixed order: xor butterfly inside a wave, waves in index order).
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sum of three values over the 256 threads of a block, result in thread 0.
+// `red` holds 4 waves x 3 values of LDS.  Contains two barriers.
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c,
+                                           double (*red)[3]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  if (lane == 0) {
+    red[w][0] = a;
+    red[w][1] = b;
+    red[w][2] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
+    b = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
+    c = ((red[0][2] + red[1][2]) + red[2][2]) + red[3][2];
+  }
+  __syncthreads();
+}
+
+// -------------------------------------------------------------------------
+// Band boxes and block bookkeeping.
+
+__device__ __forceinline__ int wave_excl_scan(int v, int lane) {
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  return incl - v;
+}
+
+// Actual row handled by lane r when the band rows [j0, j1] (unwrapped) are
+// visited in ascending order of their index in the domain.
+__device__ __forceinline__ int sorted_row(int r, int j0, int j1, int ny) {
+  if (j1 >= ny) {  // rows 0..j1-ny, then j0..ny-1
+    const int w = j1 - ny + 1;
+    return r < w ? r : j0 + (r - w);
+  }
+  if (j0 < 0) {    // rows 0..j1, then j0+ny..ny-1
+    return r <= j1 ? r : (j0 + ny) + (r - j1 - 1);
+  }
+  return j0 + r;
+}
+
+// Column segments of the band box in ascending order (two when the box
+// wraps around a periodic x axis).
+struct ColSegs {
+  int n, lo[2], hi[2];
+};
+
+__device__ __forceinline__ ColSegs col_segments(int i0, int i1, int nx) {
+  ColSegs cs;
+  if (i0 < 0) {
+    cs.n = 2; cs.lo[0] = 0; cs.hi[0] = i1; cs.lo[1] = i0 + nx; cs.hi[1] = nx - 1;
+  } else if (i1 >= nx) {
+    cs.n = 2; cs.lo[0] = 0; cs.hi[0] = i1 - nx; cs.lo[1] = i0; cs.hi[1] = nx - 1;
+  } else {
+    cs.n = 1; cs.lo[0] = i0; cs.hi[0] = i1; cs.lo[1] = 0; cs.hi[1] = -1;
+  }
+  return cs;
+}
+
+// Band box of a particle: cells [i0, i1] x [j0, j1] (unwrapped on periodic
+// axes, clipped on walled ones).
+__device__ __forceinline__ void band_box(const Params& P, double X, double Y,
+                                         double R, int& i0, int& i1, int& j0,
+                                         int& j1) {
+  i0 = (int)floor(X - R) - 1;
+  i1 = (int)floor(X + R) + 1;
+  j0 = (int)floor(Y - R) - 1;
+  j1 = (int)floor(Y + R) + 1;
+  if (!P.perx) { i0 = max(i0, 0); i1 = min(i1, P.nx - 1); }
+  if (!P.pery) { j0 = max(j0, 0); j1 = min(j1, P.ny - 1); }
+}
+
+// A particle centre the band-box logic can handle: finite, inside [0, L) on
+// a periodic axis (positions are wrapped after every update) and within one
+// domain length of a walled axis (boxes are clipped there).
+__device__ __forceinline__ bool centre_ok(const Params& P, double X,
+                                          double Y) {
+  if (!isfinite(X) || !isfinite(Y)) return false;
+  const double Lx = (double)P.nx, Ly = (double)P.ny;
+  const bool okx = P.perx ? (X >= 0.0 && X < Lx) : (X >= -Lx && X <= 2.0 * Lx);
+  const bool oky = P.pery ? (Y >= 0.0 && Y < Ly) : (Y >= -Ly && Y <= 2.0 * Ly);
+  return okx && oky;
+}
+
+// The 256-cell blocks that row `row` of the band box touches, ascending, at
+// most four.  Returns their number.
+__device__ __forceinline__ int row_blocks(int row, const ColSegs& cs, int nx,
+                                          int* b) {
+  int n = 0;
+  for (int k = 0; k < cs.n; ++k) {
+    if (cs.hi[k] < cs.lo[k]) continue;
+    const int first = (row * nx + cs.lo[k]) / kBlock;
+    const int last = (row * nx + cs.hi[k]) / kBlock;
+    for (int q = first; q <= last; ++q)
+      if (n == 0 || b[n - 1] != q) b[n++] = q;
+  }
+  return n;
+}
+
+
+// -------------------------------------------------------------------------
+// Particle helpers shared by both forms.
+
+// Forward Euler of the position (Sec. 2.3): X^{n+1} = X^n + U^n, wrapped
+// into [0, L) on periodic axes.
+__device__ __forceinline__ void advance_position(const Params& P, double& X,
+                                                 double& Y, double Ux,
+                                                 double Uy) {
+  X = X + Ux;
+  Y = Y + Uy;
+  if (P.perx) {
+    if (X >= (double)P.nx) X -= (double)P.nx;
+    if (X < 0.0) X += (double)P.nx;
+  }
+  if (P.pery) {
+    if (Y >= (double)P.ny) Y -= (double)P.ny;
+    if (Y < 0.0) Y += (double)P.ny;
+  }
+}
+
+// The units of `unit` consecutive cells (64: a wave, 256: a block) a
+// particle's band box reaches: at most two ascending, disjoint ranges (two
+// when the box wraps around a periodic y axis).  Every cell of the box lies
+// in a listed unit.
+struct BlockRanges {
+  int n;
+  int lo[2], hi[2];
+  __device__ __forceinline__ int count() const {
+    return n == 0 ? 0
+                  : (hi[0] - lo[0] + 1) + (n > 1 ? hi[1] - lo[1] + 1 : 0);
+  }
+  __device__ __forceinline__ int at(int k) const {
+    const int l0 = hi[0] - lo[0] + 1;
+    return k < l0 ? lo[0] + k : lo[1] + (k - l0);
+  }
+  __device__ __forceinline__ bool contains(int b) const {
+    return (n > 0 && b >= lo[0] && b <= hi[0]) ||
+           (n > 1 && b >= lo[1] && b <= hi[1]);
+  }
+};
+
+__device__ BlockRanges block_ranges(const Params& P, double X, double Y,
+                                    double R, int unit) {
+  BlockRanges r;
+  r.n = 0;
+  r.lo[0] = r.lo[1] = 0;
+  r.hi[0] = r.hi[1] = -1;
+  if (!centre_ok(P, X, Y)) return r;
+  int i0, i1, j0, j1;
+  band_box(P, X, Y, R, i0, i1, j0, j1);
+  if (i1 < i0 || j1 < j0) return r;
+  int a0[2] = {j0, 0}, a1[2] = {j1, -1}, na = 1;
+  if (P.pery && j0 < 0) {          // rows 0..j1 and j0+ny..ny-1
+    na = 2; a0[0] = 0; a1[0] = j1; a0[1] = j0 + P.ny; a1[1] = P.ny - 1;
+  } else if (P.pery && j1 >= P.ny) {  // rows 0..j1-ny and j0..ny-1
+    na = 2; a0[0] = 0; a1[0] = j1 - P.ny; a0[1] = j0; a1[1] = P.ny - 1;
+  }
+  const bool xfull = P.perx && (i0 < 0 || i1 >= P.nx);
+  const int ca = xfull ? 0 : i0, cb = xfull ? P.nx - 1 : i1;
+  for (int k = 0; k < na; ++k) {
+    r.lo[k] = (a0[k] * P.nx + ca) / unit;
+    r.hi[k] = (a1[k] * P.nx + cb) / unit;
+  }
+  r.n = na;
+  if (na == 2 && r.hi[0] >= r.lo[1]) {  // the two ranges touch: merge
+    r.hi[0] = max(r.hi[0], r.hi[1]);
+    r.n = 1;
+  }
+  return r;
+}
+
+// Momentum-exchange force and torque of particle p: the sum of the partials
+// the last lattice pass wrote, lanes striding the slots, then an xor
+// butterfly (every lane ends with the same bits).
+__device__ __forceinline__ void reduce_partials(const Params& P,
+                                                const PState& cur,
+                                                const PConst& pc,
+                                                const double* partial,
+                                                int have, int p, int lane,
+                                                double& fx, double& fy,
+                                                double& tz) {
+  fx = fy = tz = 0.0;
+  if (have) {
+    if (P.scan) {
+      // scan form: one slot per (particle, 256-cell tile)
+      const BlockRanges r =
+          block_ranges(P, cur.X[p], cur.Y[p], pc.R[p], kBlock);
+      const int nb = r.count();
+      const double* src = partial + (size_t)p * P.nblocks * kRedVals;
+      for (int k = lane; k < nb; k += 64) {
+        const double* o = src + (size_t)r.at(k) * kRedVals;
+        fx += o[0];
+        fy += o[1];
+        tz += o[2];
+      }
+    } else {
+      const int ns = cur.nslot[p];
+      const double* src = partial + (size_t)p * P.maxb * kRedVals;
+      for (int k = lane; k < ns; k += 64) {
+        fx += src[k * kRedVals + 0];
+        fy += src[k * kRedVals + 1];
+        tz += src[k * kRedVals + 2];
+      }
+    }
+  }
+  fx = wave_sum(fx);
+  fy = wave_sum(fy);
+  tz = wave_sum(tz);
+}
+
+// Repulsion on particle p (the collision model the paper adopts): a
+// short-range force of range zeta, k ((R_p + R_q + zeta - d)/zeta)^2 along
+// the centre line, and against each wall the same law applied to the
+// particle's mirror image.  Positions of step n.  Every lane returns the
+// same bits.
+__device__ __forceinline__ void repulsion(const Params& P, const PState& cur,
+                                          const PConst& pc, int p, int lane,
+                                          double& cx, double& cy) {
+  cx = cy = 0.0;
+  const double zeta = P.coll_range;
+  if (!(zeta > 0.0)) return;
+  const double Xp = cur.X[p], Yp = cur.Y[p], Rp = pc.R[p];
+  for (int q = lane; q < P.np; q += 64) {
+    if (q == p) continue;
+    const double dx = Xp - near_copy(cur.X[q], Xp, (double)P.nx, P.perx);
+    const double dy = Yp - near_copy(cur.Y[q], Yp, (double)P.ny, P.pery);
+    const double d = sqrt(dx * dx + dy * dy);
+    const double reach = Rp + pc.R[q] + zeta;
+    if (d < reach && d > 0.0) {
+      const double s = (reach - d) / zeta;
+      const double mag = P.coll_pp * s * s / d;
+      cx += mag * dx;
+      cy += mag * dy;
+    }
+  }
+  cx = wave_sum(cx);
+  cy = wave_sum(cy);
+  const double dist[4] = {Xp, (double)P.nx - Xp, Yp, (double)P.ny - Yp};
+  const double nrmx[4] = {1.0, -1.0, 0.0, 0.0};
+  const double nrmy[4] = {0.0, 0.0, 1.0, -1.0};
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    if (!P.wall_face[w]) continue;
+    const double d = 2.0 * dist[w], reach = 2.0 * Rp + zeta;
+    if (d < reach) {
+      const double s = (reach - d) / zeta;
+      cx += P.coll_pw * s * s * nrmx[w];
+      cy += P.coll_pw * s * s * nrmy[w];
+    }
+  }
+}
+
+struct PUpd {
+  double X, Y, th, Ux, Uy, Om, Uxp, Uyp, Omp, Fx, Fy, Tz;
+};
+
+// One step of particle p, wave-level (every lane returns the same bits):
+// Newton-Euler (eq. particle; the gyroscopic term vanishes in 2-D) with the
+// inside-fluid correction of eq. inside.fluid by backward differences,
+// total force = hydrodynamic + (rho_s - rho_f) V g + repulsion, forward
+// Euler (Sec. 2.3 end).
+__device__ PUpd particle_update(const Params& P, const PState& cur,
+                                const PConst& pc, const double* partial,
+                                int have, int p, int lane) {
+  double fx, fy, tz, cx, cy;
+  reduce_partials(P, cur, pc, partial, have, p, lane, fx, fy, tz);
+  repulsion(P, cur, pc, p, lane, cx, cy);
+  PUpd u;
+  const double R = pc.R[p], rs = pc.rhos[p];
+  const double V = M_PI * R * R;
+  const double M = rs * V, I = 0.5 * M * R * R;
+  const double Min = P.rho_f * M / rs, Iin = P.rho_f * I / rs;
+  const double Ux = cur.Ux[p], Uy = cur.Uy[p], Om = cur.Om[p];
+  u.Ux = Ux;
+  u.Uy = Uy;
+  u.Om = Om;
+  if (!pc.fixed[p]) {
+    const double Finx = -Min * (Ux - cur.Uxp[p]);
+    const double Finy = -Min * (Uy - cur.Uyp[p]);
+    const double Tin = -Iin * (Om - cur.Omp[p]);
+    const double Fcx = (fx - Finx) + (rs - P.rho_f) * V * P.grav_x + cx;
+    const double Fcy = (fy - Finy) + (rs - P.rho_f) * V * P.grav_y + cy;
+    u.Ux = Ux + Fcx / M;
+    u.Uy = Uy + Fcy / M;
+    u.Om = Om + (tz - Tin) / I;
+  }
+  u.X = cur.X[p];
+  u.Y = cur.Y[p];
+  advance_position(P, u.X, u.Y, Ux, Uy);
+  u.th = cur.th[p] + Om;
+  u.Uxp = Ux;
+  u.Uyp = Uy;
+  u.Omp = Om;
+  u.Fx = fx;
+  u.Fy = fy;
+  u.Tz = tz;
+  return u;
+}
+
+__device__ __forceinline__ void store_particle(PState& s, int p,
+                                               const PUpd& u) {
+  s.X[p] = u.X; s.Y[p] = u.Y; s.th[p] = u.th;
+  s.Ux[p] = u.Ux; s.Uy[p] = u.Uy; s.Om[p] = u.Om;
+  s.Uxp[p] = u.Uxp; s.Uyp[p] = u.Uyp; s.Omp[p] = u.Omp;
+  s.Fx[p] = u.Fx; s.Fy[p] = u.Fy; s.Tz[p] = u.Tz;
+}
+
+// -------------------------------------------------------------------------
+// Block particle list: load, sort by particle id and stage the particle
+// data in LDS.
+
+struct BlockParticles {
+  int cnt;
+  int pid[kListCap];
+  int slot[kListCap];
+  double X[kListCap], Y[kListCap], R[kListCap];
+  double Ux[kListCap], Uy[kListCap], Om[kListCap], Tp[kListCap];
+};
+
+__device__ __forceinline__ void load_block_list(BlockParticles& bp, int* tmp,
+                                                Lists L, int b, PState pn,
+                                                PConst pc, int* flags) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    int n = L.cnt[b];
+    if (n > kListCap) {
+      atomicOr(flags, kFlagListFull);
+      n = kListCap;
+    }
+    bp.cnt = n;
+  }
+  __syncthreads();
+  const int n = bp.cnt;
+  if (n == 0) return;
+  int2 e = make_int2(0, 0);
+  if (t < n) {
+    e = L.ent[(size_t)b * kListCap + t];
+    tmp[t] = e.x;
+  }
+  __syncthreads();
+  if (t < n) {
+    int rank = 0;
+    for (int k = 0; k < n; ++k) rank += tmp[k] < e.x;
+    bp.pid[rank] = e.x;
+    bp.slot[rank] = e.y;
+    bp.X[rank] = pn.X[e.x];
+    bp.Y[rank] = pn.Y[e.x];
+    bp.R[rank] = pc.R[e.x];
+    bp.Ux[rank] = pn.Ux[e.x];
+    bp.Uy[rank] = pn.Uy[e.x];
+    bp.Om[rank] = pn.Om[e.x];
+    bp.Tp[rank] = pc.Tinit[e.x];
+  }
+  __syncthreads();
+}
+
+// Geometry of slot s for the cell (i, j): covered share and solid velocity
+// u_s = U + Omega x (x - X) at the node (eq. us).  Returns false when the
+// particle does not reach the cell.
+struct SlotGeom {
+  double fs, usx, usy, rx, ry;
+  bool full;
+};
+
+__device__ __forceinline__ bool slot_geometry(const BlockParticles& bp, int s,
+                                              const Params& P, int i, int j,
+                                              SlotGeom& g) {
+  double xn = (double)i + 0.5, yn = (double)j + 0.5;
+  double X = near_copy(bp.X[s], xn, (double)P.nx, P.perx);
+  double Y = near_copy(bp.Y[s], yn, (double)P.ny, P.pery);
+  double R = bp.R[s];
+  if (!owns_cell(X, Y, R, i, j)) return false;
+  g.full = cell_within(X, Y, R, i, j);
+  g.fs = g.full ? 1.0 : covered_share(X, Y, R, i, j);
+  g.rx = xn - X;
+  g.ry = yn - Y;
+  g.usx = bp.Ux[s] - bp.Om[s] * g.ry;
+  g.usy = bp.Uy[s] + bp.Om[s] * g.rx;
+  return true;
+}
+
+
+// Scan form: gather the particles that reach tile b.  With `advance` (a
+// lattice step) their positions are X + U and their velocities are rebuilt
+// from the previous step's partials, and the first tile a particle reaches
+// stores its new state in `next`; without it (init, ownership) the stored
+// state is used.  Needs P.np <= 64.
+__device__ void scan_block(BlockParticles& bp, const Params& P, int b,
+                           PState cur, PState next, PConst pc,
+                           const double* partial, int have, bool advance,
+                           int* flags) {
+  __shared__ int s_nwork;
+  __shared__ int s_work_pid[64], s_work_rank[64], s_work_store[64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if (wave == 0) {
+    bool cand = false, store = false;
+    double X = 0.0, Y = 0.0;
+    if (lane < P.np) {
+      X = cur.X[lane];
+      Y = cur.Y[lane];
+      if (advance) advance_position(P, X, Y, cur.Ux[lane], cur.Uy[lane]);
+      const BlockRanges r = block_ranges(P, X, Y, pc.R[lane], kBlock);
+      cand = r.contains(b);
+      if (r.n == 0 && b == 0) atomicOr(flags, kFlagUnstable);
+      store = advance && (r.n > 0 ? b == r.lo[0] : b == 0);
+    }
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const unsigned long long mc = __ballot(cand);
+    const int rank = __popcll(mc & below);
+    if (cand) {
+      bp.pid[rank] = lane;
+      bp.slot[rank] = lane * P.nblocks + b;
+      bp.X[rank] = X;
+      bp.Y[rank] = Y;
+      bp.R[rank] = pc.R[lane];
+      bp.Tp[rank] = pc.Tinit[lane];
+    }
+    const unsigned long long mw = __ballot(cand || store);
+    const int wrank = __popcll(mw & below);
+    if (cand || store) {
+      s_work_pid[wrank] = lane;
+      s_work_rank[wrank] = cand ? rank : -1;
+      s_work_store[wrank] = store ? 1 : 0;
+    }
+    if (lane == 0) {
+      bp.cnt = __popcll(mc);
+      s_nwork = __popcll(mw);
+    }
+  }
+  __syncthreads();
+  const int nwork = s_nwork;
+  for (int k = wave; k < nwork; k += 4) {
+    const int p = s_work_pid[k], r = s_work_rank[k];
+    if (advance) {
+      const PUpd u = particle_update(P, cur, pc, partial, have, p, lane);
+      if (lane == 0) {
+        if (r >= 0) {
+          bp.Ux[r] = u.Ux;
+          bp.Uy[r] = u.Uy;
+          bp.Om[r] = u.Om;
+        }
+        if (s_work_store[k]) store_particle(next, p, u);
+      }
+    } else if (lane == 0 && r >= 0) {
+      bp.Ux[r] = cur.Ux[p];
+      bp.Uy[r] = cur.Uy[p];
+      bp.Om[r] = cur.Om[p];
+    }
+  }
+  __syncthreads();
+}
+
+// Geometry of a particle (centre X, Y, radius R, velocity U, Omega) for the
+// cell (i, j): covered share and solid velocity u_s = U + Omega x (x - X) at
+// the node (eq. us).  False when the particle does not reach the cell.
+__device__ __forceinline__ bool particle_geometry(const Params& P, double Xp,
+                                                  double Yp, double R,
+                                                  double Ux, double Uy,
+                                                  double Om, int i, int j,
+                                                  SlotGeom& g) {
+  const double xn = (double)i + 0.5, yn = (double)j + 0.5;
+  const double X = near_copy(Xp, xn, (double)P.nx, P.perx);
+  const double Y = near_copy(Yp, yn, (double)P.ny, P.pery);
+  if (!owns_cell(X, Y, R, i, j)) return false;
+  g.full = cell_within(X, Y, R, i, j);
+  g.fs = g.full ? 1.0 : covered_share(X, Y, R, i, j);
+  g.rx = xn - X;
+  g.ry = yn - Y;
+  g.usx = Ux - Om * g.ry;
+  g.usy = Uy + Om * g.rx;
+  return true;
+}
+
+template <bool SCAN>
+__device__ __forceinline__ void gather_particles(
+    BlockParticles& bp, int* tmp, const Params& P, PState cur, PState next,
+    PConst pc, Lists L, const double* partial, int have, bool advance,
+    int* flags) {
+  if (SCAN)
+    scan_block(bp, P, blockIdx.x, cur, next, pc, partial, have, advance,
+               flags);
+  else
+    load_block_list(bp, tmp, L, blockIdx.x, advance ? next : cur, pc, flags);
+}
+
+// -------------------------------------------------------------------------
+// The fused lattice pass.
+
+// Pull of direction Q for the cell: the upstream value, or -- when the
+// upstream cell lies beyond a wall -- the rule of that wall applied to the
+// opposite population of the cell itself.  XS/YS name the wall met across
+// the x / y side (-1: none); when both apply (a corner) the y wall decides.
+// Branch-free: one load from a selected address, then selects of
+// compile-time-indexed wall constants.
+template <int Q, int OPP, int XS, int YS, class T>
+__device__ __forceinline__ void pull(const typename T::S* __restrict__ fin,
+                                     const typename T::S* __restrict__ gin,
+                                     size_t plane, int cc, int src, bool ox,
+                                     bool oy, const Hot<typename T::C>& H,
+                                     typename T::C& fv, typename T::C& gv) {
+  typedef typename T::C C;
+  const bool out = (XS >= 0 && ox) || (YS >= 0 && oy);
+  const size_t idx = out ? (size_t)OPP * plane + cc : (size_t)Q * plane + src;
+  C f = T::ld(fin, idx), g = T::ld(gin, idx);
+  if (XS >= 0 || YS >= 0) {
+    constexpr int WX = XS >= 0 ? XS : YS, WY = YS >= 0 ? YS : XS;
+    const bool useY = YS >= 0 && oy;
+    const C fa = useY ? H.fadd[WY][Q] : H.fadd[WX][Q];
+    const C ga = useY ? H.gadd[WY][Q] : H.gadd[WX][Q];
+    const C gs = useY ? H.gsign[WY] : H.gsign[WX];
+    f = out ? f + fa : f;
+    g = out ? gs * g + ga : g;
+  }
+  fv = f;
+  gv = g;
+}
+
+// M f for D2Q9 (rows of M, Sec. 2.1).
+template <class C>
+__device__ __forceinline__ void moments(const C* f, C* m) {
+  const C a14 = f[1] + f[2] + f[3] + f[4];
+  const C a58 = f[5] + f[6] + f[7] + f[8];
+  m[0] = f[0] + a14 + a58;
+  m[1] = -4 * f[0] - a14 + 2 * a58;
+  m[2] = 4 * f[0] - 2 * a14 + a58;
+  const C b57 = f[5] - f[7], b68 = f[6] - f[8];
+  m[3] = f[1] - f[3] + b57 - b68;
+  m[4] = -2 * (f[1] - f[3]) + b57 - b68;
+  m[5] = f[2] - f[4] + b57 + b68;
+  m[6] = -2 * (f[2] - f[4]) + b57 + b68;
+  m[7] = f[1] - f[2] + f[3] - f[4];
+  m[8] = f[5] - f[6] + f[7] - f[8];
+}
+
+// M^{-1} m = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m
+// (the rows of M are orthogonal with those squared norms).
+template <class C>
+__device__ __forceinline__ void inverse(const C* m, C* o) {
+  const C k0 = m[0] * (C)(1.0 / 9.0), k1 = m[1] * (C)(1.0 / 36.0),
+          k2 = m[2] * (C)(1.0 / 36.0), k3 = m[3] * (C)(1.0 / 6.0),
+          k4 = m[4] * (C)(1.0 / 12.0), k5 = m[5] * (C)(1.0 / 6.0),
+          k6 = m[6] * (C)(1.0 / 12.0), k7 = m[7] * (C)0.25,
+          k8 = m[8] * (C)0.25;
+  o[0] = k0 - 4 * k1 + 4 * k2;
+  const C ax = k0 - k1 - 2 * k2;
+  o[1] = ax + k3 - 2 * k4 + k7;
+  o[2] = ax + k5 - 2 * k6 - k7;
+  o[3] = ax - k3 + 2 * k4 + k7;
+  o[4] = ax - k5 + 2 * k6 - k7;
+  const C dg = k0 + 2 * k1 + k2;
+  const C p34 = k3 + k4, p56 = k5 + k6;
+  o[5] = dg + p34 + p56 + k8;
+  o[6] = dg - p34 + p56 - k8;
+  o[7] = dg - p34 - p56 + k8;
+  o[8] = dg + p34 - p56 - k8;
+}
+
+// Particle sums of one cell: total solid fraction f_s = sum_p f_s,p and
+// sum_p f_s,p (u_s, u_s u_s), the inputs of the volumetric step.
+template <class C>
+struct PSums {
+  C S0, S1x, S1y, S2xx, S2yy, S2xy;
+};
+
+// The lattice update of the 256 cells of one tile: pull streaming with the
+// wall rules, the volumetric no-slip step with the particle sums `part`
+// supplies, the coupled macroscopic solve and both collisions.  Every thread
+// of the block calls pre() before it issues its population loads, gather()
+// right after (so that its work overlaps them; a true result, which must be
+// uniform over the wave, abandons the tile: the return value is then false)
+// and then part(act, x, y, rho, jx*, jy*, S).
+template <int PREC, bool OUT, class PreFn, class GatherFn, class PartFn>
+__device__ __forceinline__ bool lattice_tile(
+    const Params& P, const Hot<typename Prec<PREC>::C>& H,
+    const typename Prec<PREC>::S* __restrict__ fin,
+    typename Prec<PREC>::S* __restrict__ fout,
+    const typename Prec<PREC>::S* __restrict__ gin,
+    typename Prec<PREC>::S* __restrict__ gout,
+    const typename Prec<PREC>::H* __restrict__ hin,
+    typename Prec<PREC>::H* __restrict__ hout, size_t plane, int tile,
+    double* __restrict__ macro, int* flags, PreFn pre, GatherFn gather,
+    PartFn part) {
+  typedef Prec<PREC> T;
+  typedef typename T::C C;
+  typedef typename T::H HT;
+
+  const int c = tile * kBlock + threadIdx.x;
+  const bool act = c < P.N;
+  const int cc = act ? c : P.N - 1;   // inactive lanes read a valid cell
+  const int y = cc / P.nx;
+  const int x = cc - y * P.nx;
+
+  // ---- pull streaming with the wall rules (eq. lbe.rho.str, lbe.e.str)
+  int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+  const bool oxm = xm < 0 && !P.perx, oxp = xp >= P.nx && !P.perx;
+  const bool oym = ym < 0 && !P.pery, oyp = yp >= P.ny && !P.pery;
+  xm = xm < 0 ? xm + P.nx : xm;
+  xp = xp >= P.nx ? xp - P.nx : xp;
+  ym = ym < 0 ? ym + P.ny : ym;
+  yp = yp >= P.ny ? yp - P.ny : yp;
+  const int r0 = y * P.nx, rm = ym * P.nx, rp = yp * P.nx;
+  pre();
+  C f[9], g[9];
+  f[0] = T::ld(fin, cc);
+  g[0] = T::ld(gin, cc);
+  constexpr int XLO = VLB_FACE_XLO, XHI = VLB_FACE_XHI;
+  constexpr int YLO = VLB_FACE_YLO, YHI = VLB_FACE_YHI;
+  pull<1, 3, XLO, -1, T>(fin, gin, plane, cc, r0 + xm, oxm, false, H, f[1], g[1]);
+  pull<2, 4, -1, YLO, T>(fin, gin, plane, cc, rm + x, false, oym, H, f[2], g[2]);
+  pull<3, 1, XHI, -1, T>(fin, gin, plane, cc, r0 + xp, oxp, false, H, f[3], g[3]);
+  pull<4, 2, -1, YHI, T>(fin, gin, plane, cc, rp + x, false, oyp, H, f[4], g[4]);
+  pull<5, 7, XLO, YLO, T>(fin, gin, plane, cc, rm + xm, oxm, oym, H, f[5], g[5]);
+  pull<6, 8, XHI, YLO, T>(fin, gin, plane, cc, rm + xp, oxp, oym, H, f[6], g[6]);
+  pull<7, 5, XHI, YHI, T>(fin, gin, plane, cc, rp + xp, oxp, oyp, H, f[7], g[7]);
+  pull<8, 6, XLO, YHI, T>(fin, gin, plane, cc, rp + xm, oxm, oyp, H, f[8], g[8]);
+  const HT hn = hin[cc];
+  if (gather()) return false;
+
+  // ---- moments of the deviations f* - w rho_0; the reference adds
+  // rho_0 (1, -2, 1, 0, ..., 0) to M f*
+  C m[9];
+  moments(f, m);
+  const C drho = m[0];                 // rho - rho_0
+  const C rho = H.rho0s + drho;        // rho = sum f*_i, kept by eq. fi
+  const C jxs = m[3], jys = m[5];
+
+  // ---- particles: solid fraction, u_s, momentum exchange (Sec. 2.3)
+  PSums<C> S;
+  S.S0 = S.S1x = S.S1y = S.S2xx = S.S2yy = S.S2xy = (C)0;
+  part(act, x, y, rho, jxs, jys, S);
+
+  // ---- volumetric no-slip step in moment space (eq. fi):
+  // M f = (1 - f_s) M f* + rho sum_p f_s,p m^eq(1, u_s,p), written for the
+  // deviations (the reference moments cancel against rho_0 S0)
+  const C S0 = S.S0, S1x = S.S1x, S1y = S.S1y;
+  const C S2xx = S.S2xx, S2yy = S.S2yy, S2xy = S.S2xy;
+  const C fs = S0;
+  const C wf = (C)1 - fs;
+  {
+    const C tr = S2xx + S2yy;
+    m[0] = wf * m[0] + S0 * drho;
+    m[1] = wf * m[1] + (-2 * S0 * drho + 3 * rho * tr);
+    m[2] = wf * m[2] + (S0 * drho - 3 * rho * tr);
+    m[3] = wf * m[3] + rho * S1x;
+    m[4] = wf * m[4] - rho * S1x;
+    m[5] = wf * m[5] + rho * S1y;
+    m[6] = wf * m[6] - rho * S1y;
+    m[7] = wf * m[7] + rho * (S2xx - S2yy);
+    m[8] = wf * m[8] + rho * S2xy;
+  }
+
+  // ---- [df_s/dt] by eq. dfs_dt through the carrier h = 2 f_s + d:
+  // d^{n+1} = 2 f_s^{n+1} - h^n,  h^{n+1} = 2 f_s^{n+1} + d^{n+1}
+  const C dfs = 2 * fs - (C)hn;
+  const HT hnew = (HT)(2 * fs + dfs);
+
+  // ---- per-cell properties (Sec. 2.2) and relaxation rates (Sec. 3)
+  const C cv = H.cvf + H.dcv * fs;
+  const C lam = H.lamf + H.dlam * fs;
+  const C tau_g = (C)0.5 + H.taug_coef * lam;
+  const C sig_j = (C)1 / tau_g;
+  // (1/sig_j - 1/2)(1/sig_e - 1/2) = 1/4 is sig_e = 2 - sig_j
+  const C sig_e = H.sigma_rule == 0 ? (C)2 - sig_j : (C)1;
+
+  // ---- energy moments (the reference w c_ref T_0 adds c_ref T_0 (1, -2,
+  // 1, 0, ..., 0)) and the local temperature gradient (Sec. 2.2)
+  C n[9];
+  moments(g, n);
+  const C cT0 = H.cT0s;
+  const C G = n[0] + cT0;                          // sum g_i
+  const C gcoef = H.grad_coef * sig_j;             // -3 / (c_ref tau_g)
+  const C gTx = gcoef * n[3], gTy = gcoef * n[5];
+
+  // ---- coupled macroscopic solve: u from eq. rho.rhou with F = a + b T,
+  // T from the implicit relation of Sec. 2.2 (linear in T)
+  const C ax = wf * H.A0x, ay = wf * H.A0y;
+  const C bx = wf * H.B0x, by = wf * H.B0y;
+  const C irho = (C)1 / rho;
+  const C jx = m[3], jy = m[5];
+  const C num = G - (C)0.5 * cv * ((jx + (C)0.5 * ax) * gTx + (jy + (C)0.5 * ay) * gTy) * irho;
+  const C den = cv - (C)0.5 * H.dcv * dfs + (C)0.25 * cv * (bx * gTx + by * gTy) * irho;
+  const C Tc = num / den;
+  const C Fx = ax + bx * Tc, Fy = ay + by * Tc;
+  const C ux = (jx + (C)0.5 * Fx) * irho, uy = (jy + (C)0.5 * Fy) * irho;
+  const C eps = cv * Tc;
+  const C qc = -cv * (ux * gTx + uy * gTy) + H.dcv * Tc * dfs;
+
+  if (act && !(rho > (C)0 && isfinite(Tc) && isfinite(ux) && isfinite(uy)))
+    atomicOr(flags, kFlagUnstable);
+
+  // ---- flow collision with the discrete force term (eq. lbe.rho.col);
+  // m^eq minus the reference moments is (drho, -2 drho + 3 rho u^2,
+  // drho - 3 rho u^2, rho ux, -rho ux, rho uy, -rho uy, rho (ux^2 - uy^2),
+  // rho ux uy); s_0 = s_j = 1
+  {
+    const C ru2 = rho * (ux * ux + uy * uy);
+    const C se = H.s_e, sq = H.s_q, sp = H.s_p;
+    const C he = (C)1 - (C)0.5 * se, hq = (C)1 - (C)0.5 * sq,
+            hp = (C)1 - (C)0.5 * sp;
+    const C Fu = Fx * ux + Fy * uy;
+    C mb[9];
+    mb[0] = drho;
+    mb[1] = m[1] - se * (m[1] - (-2 * drho + 3 * ru2)) + he * (6 * Fu);
+    mb[2] = m[2] - se * (m[2] - (drho - 3 * ru2)) - he * (6 * Fu);
+    mb[3] = rho * ux + (C)0.5 * Fx;
+    mb[4] = m[4] - sq * (m[4] + rho * ux) - hq * Fx;
+    mb[5] = rho * uy + (C)0.5 * Fy;
+    mb[6] = m[6] - sq * (m[6] + rho * uy) - hq * Fy;
+    mb[7] = m[7] - sp * (m[7] - rho * (ux * ux - uy * uy)) + hp * (2 * (Fx * ux - Fy * uy));
+    mb[8] = m[8] - sp * (m[8] - rho * ux * uy) + hp * (Fx * uy + Fy * ux);
+    C o[9];
+    inverse(mb, o);
+    if (act) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) T::st(fout, (size_t)q * plane + cc, o[q]);
+    }
+  }
+
+  // ---- energy collision with the discrete source term (eq. lbe.e.col):
+  // n^eq = [eps, -4 eps + 2 c_ref T, 4 eps - 3 c_ref T, 0...] (alpha1 = -2,
+  // alpha2 = 1), q_m = [q, -4 q, 4 q, 0...] (beta1 = -4, beta2 = 4),
+  // R = diag(1, se, se, sj, sj, sj, sj, se, se); moments minus reference
+  {
+    const C cT = H.cref * Tc;
+    const C he = (C)1 - (C)0.5 * sig_e;
+    C nb[9];
+    nb[0] = (eps - cT0) + (C)0.5 * qc;
+    nb[1] = n[1] - sig_e * (n[1] - (-4 * eps + 2 * cT + 2 * cT0)) - he * (4 * qc);
+    nb[2] = n[2] - sig_e * (n[2] - (4 * eps - 3 * cT - cT0)) + he * (4 * qc);
+    const C rj = (C)1 - sig_j, re = (C)1 - sig_e;
+    nb[3] = rj * n[3];
+    nb[4] = rj * n[4];
+    nb[5] = rj * n[5];
+    nb[6] = rj * n[6];
+    nb[7] = re * n[7];
+    nb[8] = re * n[8];
+    C o[9];
+    inverse(nb, o);
+    if (act) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) T::st(gout, (size_t)q * plane + cc, o[q]);
+      hout[cc] = hnew;
+    }
+  }
+
+  if (OUT && act) {
+    const size_t N = (size_t)P.N;
+    macro[cc] = (double)rho;
+    macro[N + cc] = (double)ux;
+    macro[2 * N + cc] = (double)uy;
+    macro[3 * N + cc] = (double)Tc;
+    macro[4 * N + cc] = (double)fs;
+    macro[5 * N + cc] = (double)dfs;
+  }
+  return true;
+}
+
+// Tile of particle-tile block k in the scan form: block k serves the
+// (k / maxr)-th particle's (k % maxr)-th tile, unless a particle of lower
+// index also reaches that tile (its block serves it).  -1: nothing to do.
+__device__ __forceinline__ int scan_task_tile(const Params& P, PState cur,
+                                              PConst pc, int k) {
+  const int p = k / P.maxr, j = k - p * P.maxr;
+  if (p >= P.np) return -1;
+  double X = cur.X[p], Y = cur.Y[p];
+  advance_position(P, X, Y, cur.Ux[p], cur.Uy[p]);
+  const BlockRanges r = block_ranges(P, X, Y, pc.R[p], kBlock);
+  if (j >= r.count()) return -1;
+  const int tile = r.at(j);
+  for (int q = 0; q < p; ++q) {
+    double Xq = cur.X[q], Yq = cur.Y[q];
+    advance_position(P, Xq, Yq, cur.Ux[q], cur.Uy[q]);
+    if (block_ranges(P, Xq, Yq, pc.R[q], kBlock).contains(tile)) return -1;
+  }
+  return tile;
+}
+
+// Tile of the k-th block of the streaming group.  Workgroups are dealt to
+// the 8 XCDs in turn, so block k runs on XCD x = k % 8.  Tiles come in
+// groups of G consecutive tiles, dealt to the XCDs in turn, and each XCD
+// walks its groups' tiles in order: the rows a tile pulls from its
+// neighbours are then mostly in the XCD's own L2 already.  (The group
+// starts at a multiple of 8 blocks.)  Tiles >= nblocks: none.
+__device__ __forceinline__ int stream_tile(const Params& P, int k) {
+  const int x = k & 7, j = k >> 3;
+  const int gi = j / P.xcd_group, o = j - gi * P.xcd_group;
+  return (gi * 8 + x) * P.xcd_group + o;
+}
+
+// LDS of a particle tile: the staged particles, the per-cell particle sums
+// (written before the lattice update, read by it) and the per-cell rho, j*
+// (written by the lattice update, read by the momentum exchange).
+template <class C>
+struct TileShared {
+  BlockParticles bp;
+  int tmp[kListCap];
+  double red[4][3];
+  C S[6][kBlock];      // f_s and sum_p f_s,p (u_s, u_s u_s), shares scaled
+  C S0raw[kBlock];     // sum_p f_s,p before scaling
+  C M[3][kBlock];      // rho, jx*, jy* after streaming
+};
+
+// One tile of one time step (a whole step is one launch of k_step, or of
+// k_batch_step for many domains).  Two roles:
+//
+//  * particle tiles (the tiles particles reach): the particles of the tile
+//    (scan form: found and advanced here, velocities rebuilt from the
+//    previous step's partials; list form: the block list k_particles
+//    filled), then three phases that keep the register peak at that of the
+//    plain update -- (1) exact-area solid fractions and the particle sums
+//    of each cell into LDS, (2) the lattice update reading them, (3) the
+//    per-block momentum-exchange partials of every particle of the tile;
+//  * plain tiles: the lattice update without particles.
+//
+// Scan form: the first np * maxr blocks (tasks) take the particle tiles (so
+// their longer dependency chain starts first and overlaps the streaming of
+// the rest); the following ones take every tile and leave those some
+// particle reaches (same advanced positions and band boxes; one particle
+// per lane) to the first group.  List form: each tile in the role its block
+// count gives.
+template <int PREC, bool OUT, bool SCAN>
+__device__ __forceinline__ void step_task(
+    const Params& P, const Hot<typename Prec<PREC>::C>& H, const StepBufs& B,
+    int have, int tile, bool ptile, TileShared<typename Prec<PREC>::C>& sh) {
+  typedef typename Prec<PREC>::C C;
+  typedef typename Prec<PREC>::S S;
+  typedef typename Prec<PREC>::H HT;
+  const S* __restrict__ fin = (const S*)B.fi;
+  S* __restrict__ fout = (S*)B.fo;
+  const S* __restrict__ gin = (const S*)B.gi;
+  S* __restrict__ gout = (S*)B.go;
+  const HT* __restrict__ hin = (const HT*)B.hin;
+  HT* __restrict__ hout = (HT*)B.hout;
+  const size_t plane = B.plane;
+  const PState cur = B.cur, nxt = B.nxt;
+  const PConst pc = B.pc;
+  const Lists L = B.L;
+  const double* __restrict__ partial_in = B.partial_in;
+  double* __restrict__ partial = B.partial_out;
+  double* __restrict__ macro = B.macro;
+  int* flags = B.flags;
+  const int t = threadIdx.x, lane = t & 63;
+
+  const int c0 = tile * kBlock + t;
+  const bool act0 = c0 < P.N;
+  const int cy = (act0 ? c0 : P.N - 1) / P.nx;
+  const int cx = (act0 ? c0 : P.N - 1) - cy * P.nx;
+
+  // ---- phase 1 (particle tiles): particles of the tile, and per cell the
+  // solid fraction f_s = sum_p f_s,p and sum_p f_s,p (u_s, u_s u_s); where
+  // overlapping disks cover more than the cell the shares are scaled to
+  // sum to one
+  if (ptile) {
+    if (SCAN)
+      scan_block(sh.bp, P, tile, cur, nxt, pc, partial_in, have, true, flags);
+    else
+      load_block_list(sh.bp, sh.tmp, L, tile, nxt, pc, flags);
+    PSums<C> S;
+    S.S0 = S.S1x = S.S1y = S.S2xx = S.S2yy = S.S2xy = (C)0;
+    int nin = 0;
+    const int cnt = sh.bp.cnt;
+    for (int k = 0; k < cnt; ++k) {
+      SlotGeom sg;
+      if (act0 && particle_geometry(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.R[k],
+                                    sh.bp.Ux[k], sh.bp.Uy[k], sh.bp.Om[k],
+                                    cx, cy, sg)) {
+        const C a = (C)sg.fs, ux = (C)sg.usx, uy = (C)sg.usy;
+        ++nin;
+        S.S0 += a;
+        S.S1x += a * ux;
+        S.S1y += a * uy;
+        S.S2xx += a * ux * ux;
+        S.S2yy += a * uy * uy;
+        S.S2xy += a * ux * uy;
+      }
+    }
+    if (act0 && nin > P.kmax) atomicOr(flags, kFlagOverlap);
+    sh.S0raw[t] = S.S0;
+    if (S.S0 > (C)1) {
+      const C inv = (C)1 / S.S0;
+      S.S1x *= inv; S.S1y *= inv; S.S2xx *= inv; S.S2yy *= inv;
+      S.S2xy *= inv;
+      S.S0 = (C)1;
+    }
+    sh.S[0][t] = S.S0; sh.S[1][t] = S.S1x; sh.S[2][t] = S.S1y;
+    sh.S[3][t] = S.S2xx; sh.S[4][t] = S.S2yy; sh.S[5][t] = S.S2xy;
+  }
+
+  // ---- phase 2: the lattice update
+  const bool probe = SCAN && !ptile && lane < P.np;
+  double X = 0.0, Y = 0.0, Ux = 0.0, Uy = 0.0, R = 0.0;
+  auto pre = [&] {
+    if (probe) {
+      X = cur.X[lane];
+      Y = cur.Y[lane];
+      Ux = cur.Ux[lane];
+      Uy = cur.Uy[lane];
+      R = pc.R[lane];
+    }
+  };
+  auto gather = [&]() -> bool {
+    if (!SCAN || ptile) return false;
+    bool hit = false;
+    if (probe) {
+      advance_position(P, X, Y, Ux, Uy);
+      const BlockRanges r = block_ranges(P, X, Y, R, kBlock);
+      hit = r.contains(tile);
+      // a centre the band-box logic cannot place: no tile serves it
+      if (r.n == 0 && tile == 0) atomicOr(flags, kFlagUnstable);
+    }
+    return __ballot(hit) != 0ull;   // a particle tile: the first group's
+  };
+  auto part = [&](bool, int, int, C rho, C jxs, C jys, PSums<C>& S) {
+    if (ptile) {
+      S.S0 = sh.S[0][t]; S.S1x = sh.S[1][t]; S.S1y = sh.S[2][t];
+      S.S2xx = sh.S[3][t]; S.S2yy = sh.S[4][t]; S.S2xy = sh.S[5][t];
+      sh.M[0][t] = rho; sh.M[1][t] = jxs; sh.M[2][t] = jys;
+    }
+  };
+  if (!lattice_tile<PREC, OUT>(P, H, fin, fout, gin, gout, hin, hout, plane,
+                               tile, macro, flags, pre, gather, part))
+    return;
+  if (!ptile) return;
+
+  // ---- phase 3 (particle tiles): momentum exchange.  Each particle's share
+  // of sum_i (f_i - f*_i) e_i in a cell is f_s,p (rho u_s - j*); the block
+  // sums of minus that (force) and of its moment about the centre (torque)
+  // go to the particle's partial slot of this tile.  Pass 2 adds the
+  // correction of the scaled shares (cells covered more than once; rare).
+  const C rho = sh.M[0][t], jxs = sh.M[1][t], jys = sh.M[2][t];
+  const C S0raw = sh.S0raw[t];
+  const int cnt = sh.bp.cnt;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1 && !__syncthreads_or(act0 && S0raw > (C)1)) break;
+    const bool over = pass == 1 && S0raw > (C)1;
+    const C inv = over ? (C)1 / S0raw : (C)1;
+    for (int k = 0; k < cnt; ++k) {
+      double cfx = 0.0, cfy = 0.0, ctz = 0.0;
+      SlotGeom sg;
+      if (act0 && (pass == 0 || over) &&
+          particle_geometry(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.R[k],
+                            sh.bp.Ux[k], sh.bp.Uy[k], sh.bp.Om[k], cx, cy,
+                            sg)) {
+        const C a = (C)sg.fs, ux = (C)sg.usx, uy = (C)sg.usy;
+        const double kk = pass == 0 ? 1.0 : (double)(inv - (C)1);
+        const double dpx = (double)(a * (rho * ux - jxs));
+        const double dpy = (double)(a * (rho * uy - jys));
+        cfx = -dpx * kk;
+        cfy = -dpy * kk;
+        ctz = -(sg.rx * dpy - sg.ry * dpx) * kk;
+      }
+      block_sum3(cfx, cfy, ctz, sh.red);
+      if (t == 0) {
+        double* o = partial + (size_t)sh.bp.slot[k] * kRedVals;
+        if (pass == 0) {
+          o[0] = cfx; o[1] = cfy; o[2] = ctz;
+        } else {
+          o[0] += cfx; o[1] += cfy; o[2] += ctz;
+        }
+      }
+    }
+  }
+}
+
+static inline unsigned blocks_for(long n, int per) {
+  return (unsigned)((n + per - 1) / per);
+}
+
+}  // namespace vlb

@@ -111,14 +111,13 @@ struct Lists {
   int* clr;     // [nblocks] or null: counts to reset to zero
 };
 
-// Arguments of one lattice step.  `cur` is the particle state of step n;
-// `nxt` receives step n+1 (scan form) or already holds it (list form).
-// Partials of step n are read from `partial_in`, those of step n+1 written
-// to `partial_out`.  ev_start/ev_stop (may be null) are recorded by the
-// dispatch itself.
-struct StepLaunch {
-  const Params* P;
-  bool out;                  // also store the macroscopic fields
+// The buffers one lattice step of one domain reads and writes (device
+// pointers; the population and carrier pointers are in the storage type of
+// the domain's precision).  `cur` is the particle state of step n; `nxt`
+// receives step n+1 (scan form) or already holds it (list form).  Partials
+// of step n are read from `partial_in`, those of step n+1 written to
+// `partial_out`.
+struct StepBufs {
   const void* fi; void* fo;
   const void* gi; void* go;
   const void* hin; void* hout;   // [df_s/dt] carrier, step n / step n+1
@@ -128,11 +127,36 @@ struct StepLaunch {
   Lists L;
   const double* partial_in;
   double* partial_out;
-  int have;                  // partial_in holds a previous step
   double* macro;
   int* flags;
+};
+
+// Arguments of one launch of the step kernel.  ev_start/ev_stop (may be
+// null) are recorded by the dispatch itself.
+struct StepLaunch {
+  const Params* P;
+  bool out;                  // also store the macroscopic fields
+  int have;                  // partial_in holds a previous step
+  StepBufs B;
   hipEvent_t ev_start, ev_stop;
 };
+
+// One domain of a batch as the batch step kernel sees it: its constants in
+// both compute precisions and the buffers of a step taken from each of the
+// two buffer parities.  All domains of a batch advance in lockstep.  In the
+// device copy of the table every pointer of B holds the byte offset of its
+// buffer from the batch's arena pointer (the kernel adds the arena back).
+struct BatchCase {
+  Params P;
+  Hot<double> Hd;
+  Hot<float> Hf;
+  StepBufs B[2];
+};
+
+// A task of the batch step kernel: (domain, k); k < P.nfirst is the k-th
+// particle-tile task of the domain, else tile k - P.nfirst.  Domain -1: no
+// work (padding).
+typedef int2 BatchTask;
 
 // Launchers (defined in vlb_kernels.hip).  All run on `s`.
 hipError_t launch_particles(const Params& P, PState cur, PState next,
@@ -141,6 +165,14 @@ hipError_t launch_particles(const Params& P, PState cur, PState next,
                             hipStream_t s);
 // k_step: the lattice step over every cell (events, if given, bracket it)
 hipError_t launch_step(int prec, const StepLaunch& a, hipStream_t s);
+// k_batch_step: one step of every domain of a batch; `grid` persistent
+// blocks walk the task table in steps of `grid`.
+hipError_t launch_batch_step(int prec, bool out, const BatchCase* cases,
+                             const BatchTask* tasks, char* arena, int ntasks,
+                             int grid, int parity, int have, hipStream_t s);
+// out[i] = the error flags of domain i
+hipError_t launch_gather_flags(const BatchCase* cases, char* arena, int n,
+                               int* out, hipStream_t s);
 hipError_t launch_init(int prec, const Params& P, void* f, void* g, void* h,
                        size_t plane, PState pn, PConst pc, Lists L,
                        double* macro, int* flags, hipStream_t s);

@@ -70,6 +70,11 @@ class vlb_particle_desc(ctypes.Structure):
                  "T_init")] + [("fixed", ctypes.c_int32)]
 
 
+class vlb_batch_tuning(ctypes.Structure):
+    _fields_ = [("grid_blocks", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("us_per_step", ctypes.c_double)]
+
+
 class vlb_particle_state(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("x", "y", "theta", "ux", "uy", "omega", "Fx", "Fy", "Tz",
@@ -109,6 +114,28 @@ def lib():
         "vlb_device_bytes": ([vp], ctypes.c_size_t),
         "vlb_last_error": ([vp], ctypes.c_char_p),
         "vlb_destroy": ([vp], None),
+        "vlb_batch_create": ([i32, ctypes.POINTER(vlb_domain_desc),
+                              ctypes.POINTER(i32),
+                              ctypes.POINTER(vlb_particle_desc),
+                              ctypes.POINTER(vp)], ctypes.c_int),
+        "vlb_batch_init": ([vp], ctypes.c_int),
+        "vlb_batch_step": ([vp, i64], ctypes.c_int),
+        "vlb_batch_autotune": ([vp, i32, ctypes.POINTER(vlb_batch_tuning)],
+                               ctypes.c_int),
+        "vlb_batch_set_tuning": ([vp, ctypes.POINTER(vlb_batch_tuning)],
+                                 ctypes.c_int),
+        "vlb_batch_get_tuning": ([vp, ctypes.POINTER(vlb_batch_tuning)],
+                                 ctypes.c_int),
+        "vlb_batch_read_field": ([vp, i32, i32, vp, i32], ctypes.c_int),
+        "vlb_batch_read_particles": ([vp, i32, i32,
+                                      ctypes.POINTER(vlb_particle_state)],
+                                     ctypes.c_int),
+        "vlb_batch_size": ([vp], i32),
+        "vlb_batch_cells": ([vp], i64),
+        "vlb_batch_step_count": ([vp], i64),
+        "vlb_batch_device_bytes": ([vp], ctypes.c_size_t),
+        "vlb_batch_last_error": ([vp], ctypes.c_char_p),
+        "vlb_batch_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -343,3 +370,100 @@ class Domain:
 
     def timing_read(self):
         return vlb_timing_read(self.h)
+
+
+# ---- batches ------------------------------------------------------------------
+
+
+def _bcheck(status: int, where: str, h=None) -> None:
+    if status != VLB_OK:
+        m = lib().vlb_batch_last_error(h)
+        raise VlbError(status, where, m.decode() if m else "")
+
+
+def _state_array(arr, n) -> np.ndarray:
+    names = [f[0] for f in vlb_particle_state._fields_]
+    out = np.zeros(n, dtype=[(k, np.float64) for k in names])
+    for i in range(n):
+        for k in names:
+            out[i][k] = getattr(arr[i], k)
+    return out
+
+
+class Batch:
+    """Independent domains advanced together: `cases` is a list of
+    (domain dict, particle list) pairs of the `workloads` module."""
+
+    def __init__(self, cases, precision="fp32", shift_T0=None):
+        n = len(cases)
+        self.cases = [(dict(d), list(ps)) for d, ps in cases]
+        descs = (vlb_domain_desc * n)()
+        counts = (ctypes.c_int32 * n)()
+        allp = []
+        for i, (d, ps) in enumerate(self.cases):
+            descs[i] = make_domain_desc(d, precision, None, shift_T0)
+            counts[i] = len(ps)
+            allp.extend(ps)
+        parts = make_particles(allp)
+        h = ctypes.c_void_p()
+        _bcheck(lib().vlb_batch_create(n, descs, counts, parts,
+                                       ctypes.byref(h)), "vlb_batch_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().vlb_batch_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def __len__(self):
+        return int(lib().vlb_batch_size(self.h))
+
+    @property
+    def cells(self) -> int:
+        return int(lib().vlb_batch_cells(self.h))
+
+    def init(self):
+        _bcheck(lib().vlb_batch_init(self.h), "vlb_batch_init", self.h)
+        return self
+
+    def step(self, n: int = 1):
+        _bcheck(lib().vlb_batch_step(self.h, int(n)), "vlb_batch_step", self.h)
+        return self
+
+    def autotune(self, steps: int = 5) -> dict:
+        t = vlb_batch_tuning()
+        _bcheck(lib().vlb_batch_autotune(self.h, int(steps), ctypes.byref(t)),
+                "vlb_batch_autotune", self.h)
+        return {k: getattr(t, k) for k, _ in vlb_batch_tuning._fields_}
+
+    def tuning(self) -> dict:
+        t = vlb_batch_tuning()
+        _bcheck(lib().vlb_batch_get_tuning(self.h, ctypes.byref(t)),
+                "vlb_batch_get_tuning", self.h)
+        return {k: getattr(t, k) for k, _ in vlb_batch_tuning._fields_}
+
+    def set_tuning(self, grid_blocks: int, order: int, use_graph: bool = True):
+        t = vlb_batch_tuning(int(grid_blocks), int(order), int(bool(use_graph)),
+                             0.0)
+        _bcheck(lib().vlb_batch_set_tuning(self.h, ctypes.byref(t)),
+                "vlb_batch_set_tuning", self.h)
+        return self
+
+    def field(self, i: int, name: str) -> np.ndarray:
+        d = self.cases[i][0]
+        shape = ((9, d["ny"], d["nx"]) if name in ("f", "g")
+                 else (d["ny"], d["nx"]))
+        out = np.empty(shape, np.float64)
+        _bcheck(lib().vlb_batch_read_field(self.h, int(i), FIELDS[name],
+                                           out.ctypes.data, 0),
+                "vlb_batch_read_field", self.h)
+        return out
+
+    def particles(self, i: int) -> np.ndarray:
+        n = len(self.cases[i][1])
+        arr = (vlb_particle_state * max(1, n))()
+        _bcheck(lib().vlb_batch_read_particles(self.h, int(i), n, arr),
+                "vlb_batch_read_particles", self.h)
+        return _state_array(arr, n)

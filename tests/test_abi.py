@@ -67,3 +67,24 @@ def test_null_arguments(vlb):
     assert L.vlb_init(None) == vlb.VLB_EINVAL
     assert L.vlb_step_count(None) == -1
     L.vlb_destroy(None)
+
+
+def test_batch_create_rejects_bad_arguments(vlb):
+    """Checked before any device work: mixed precisions, too many particles
+    in one domain, no domains."""
+    L = vlb.lib()
+    h = ctypes.c_void_p()
+    descs = (vlb.vlb_domain_desc * 2)(vlb.make_domain_desc(W.domain(16, 16), "fp32"),
+                                      vlb.make_domain_desc(W.domain(16, 16), "fp64"))
+    counts = (ctypes.c_int32 * 2)(0, 0)
+    assert L.vlb_batch_create(2, descs, counts, None, ctypes.byref(h)) == vlb.VLB_EINVAL
+    assert "precision" in L.vlb_batch_last_error(None).decode()
+    descs[1] = vlb.make_domain_desc(W.domain(16, 16), "fp32")
+    counts[1] = 65
+    parts = vlb.make_particles([W.particle(8, 8, 2)] * 65)
+    assert L.vlb_batch_create(2, descs, counts, parts, ctypes.byref(h)) == vlb.VLB_EINVAL
+    assert "0..64" in L.vlb_batch_last_error(None).decode()
+    assert L.vlb_batch_create(0, descs, counts, parts, ctypes.byref(h)) == vlb.VLB_EINVAL
+    assert h.value is None
+    assert L.vlb_batch_step(None, 1) == vlb.VLB_EINVAL
+    L.vlb_batch_destroy(None)
