@@ -32,9 +32,11 @@ BYTES_PER_CELL = {"fp64": 2 * 18 * 8 + 2 * 8, "fp32": 2 * 18 * 4 + 2 * 4,
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16 storage, f32 arithmetic",
          "bf16s": "bf16 storage, f32 arithmetic"}
 # the step kernel and its launch shape (tile mapping, grid) come from these
-KERNEL_SOURCES = ["paper_2410_23802_amd/csrc/vlb_kernels.hip",
+KERNEL_SOURCES = ["paper_2410_23802_amd/csrc/vlb_device.h",
+                  "paper_2410_23802_amd/csrc/vlb_kernels.hip",
                   "paper_2410_23802_amd/csrc/vlb_internal.h",
-                  "paper_2410_23802_amd/csrc/vlb_api.hip"]
+                  "paper_2410_23802_amd/csrc/vlb_api.hip",
+                  "paper_2410_23802_amd/build.py"]
 
 
 def kernel_hash() -> str:

@@ -670,6 +670,21 @@ __device__ __forceinline__ bool particle_geometry(const Params& P, double Xp,
   return true;
 }
 
+// The lever arm x - X and the solid velocity u_s of a particle at the node
+// of cell (i, j): the same arithmetic as particle_geometry, without the
+// area.
+__device__ __forceinline__ void particle_motion(const Params& P, double Xp,
+                                                double Yp, double Ux,
+                                                double Uy, double Om, int i,
+                                                int j, double& rx, double& ry,
+                                                double& usx, double& usy) {
+  const double xn = (double)i + 0.5, yn = (double)j + 0.5;
+  rx = xn - near_copy(Xp, xn, (double)P.nx, P.perx);
+  ry = yn - near_copy(Yp, yn, (double)P.ny, P.pery);
+  usx = Ux - Om * ry;
+  usy = Uy + Om * rx;
+}
+
 template <bool SCAN>
 __device__ __forceinline__ void gather_particles(
     BlockParticles& bp, int* tmp, const Params& P, PState cur, PState next,
@@ -989,14 +1004,21 @@ __device__ __forceinline__ int stream_tile(const Params& P, int k) {
 // LDS of a particle tile: the staged particles, the per-cell particle sums
 // (written before the lattice update, read by it) and the per-cell rho, j*
 // (written by the lattice update, read by the momentum exchange).
+constexpr int kShareCache = 4;   // shares per cell kept from phase 1
+
 template <class C>
 struct TileShared {
   BlockParticles bp;
   int tmp[kListCap];
-  double red[4][3];
+  double red[kListCap][4][3];  // per slot and wave: force x, y, torque
   C S[6][kBlock];      // f_s and sum_p f_s,p (u_s, u_s u_s), shares scaled
   C S0raw[kBlock];     // sum_p f_s,p before scaling
   C M[3][kBlock];      // rho, jx*, jy* after streaming
+  // the first kShareCache particles reaching each cell (slot order): slot
+  // and share, so the momentum exchange need not recompute the areas
+  C share[kShareCache][kBlock];
+  unsigned char slot[kShareCache][kBlock];
+  unsigned char nreach[kBlock];  // particles reaching the cell (saturated)
 };
 
 // One tile of one time step (a whole step is one launch of k_step, or of
@@ -1064,6 +1086,10 @@ __device__ __forceinline__ void step_task(
                                     sh.bp.Ux[k], sh.bp.Uy[k], sh.bp.Om[k],
                                     cx, cy, sg)) {
         const C a = (C)sg.fs, ux = (C)sg.usx, uy = (C)sg.usy;
+        if (nin < kShareCache) {
+          sh.slot[nin][t] = (unsigned char)k;
+          sh.share[nin][t] = a;
+        }
         ++nin;
         S.S0 += a;
         S.S1x += a * ux;
@@ -1074,6 +1100,7 @@ __device__ __forceinline__ void step_task(
       }
     }
     if (act0 && nin > P.kmax) atomicOr(flags, kFlagOverlap);
+    sh.nreach[t] = (unsigned char)(nin < 255 ? nin : 255);
     sh.S0raw[t] = S.S0;
     if (S.S0 > (C)1) {
       const C inv = (C)1 / S.S0;
@@ -1126,36 +1153,72 @@ __device__ __forceinline__ void step_task(
   // sums of minus that (force) and of its moment about the centre (torque)
   // go to the particle's partial slot of this tile.  Pass 2 adds the
   // correction of the scaled shares (cells covered more than once; rare).
+  // The shares come from phase 1 (recomputed only past kShareCache per
+  // cell); every slot's sums are reduced per wave into LDS, then the four
+  // waves in order by one thread per slot.
   const C rho = sh.M[0][t], jxs = sh.M[1][t], jys = sh.M[2][t];
   const C S0raw = sh.S0raw[t];
   const int cnt = sh.bp.cnt;
+  const int nreach = act0 ? sh.nreach[t] : 0;
+  const int ncached = nreach < kShareCache ? nreach : kShareCache;
+  const int wv = t >> 6;
   for (int pass = 0; pass < 2; ++pass) {
     if (pass == 1 && !__syncthreads_or(act0 && S0raw > (C)1)) break;
     const bool over = pass == 1 && S0raw > (C)1;
     const C inv = over ? (C)1 / S0raw : (C)1;
+    int e = 0;                       // next cached share of this cell
     for (int k = 0; k < cnt; ++k) {
+      bool has = false;
+      C a = (C)0;
+      if (e < ncached && sh.slot[e][t] == k) {
+        a = sh.share[e][t];
+        has = true;
+        ++e;
+      } else if (e == kShareCache && nreach > kShareCache) {
+        SlotGeom sg;                 // past the cache: recompute
+        if (particle_geometry(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.R[k],
+                              sh.bp.Ux[k], sh.bp.Uy[k], sh.bp.Om[k], cx, cy,
+                              sg)) {
+          a = (C)sg.fs;
+          has = true;
+        }
+      }
+      const bool add = has && (pass == 0 || over);
       double cfx = 0.0, cfy = 0.0, ctz = 0.0;
-      SlotGeom sg;
-      if (act0 && (pass == 0 || over) &&
-          particle_geometry(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.R[k],
-                            sh.bp.Ux[k], sh.bp.Uy[k], sh.bp.Om[k], cx, cy,
-                            sg)) {
-        const C a = (C)sg.fs, ux = (C)sg.usx, uy = (C)sg.usy;
+      if (add) {
+        double rx, ry, usx, usy;
+        particle_motion(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.Ux[k], sh.bp.Uy[k],
+                        sh.bp.Om[k], cx, cy, rx, ry, usx, usy);
+        const C ux = (C)usx, uy = (C)usy;
         const double kk = pass == 0 ? 1.0 : (double)(inv - (C)1);
         const double dpx = (double)(a * (rho * ux - jxs));
         const double dpy = (double)(a * (rho * uy - jys));
         cfx = -dpx * kk;
         cfy = -dpy * kk;
-        ctz = -(sg.rx * dpy - sg.ry * dpx) * kk;
+        ctz = -(rx * dpy - ry * dpx) * kk;
       }
-      block_sum3(cfx, cfy, ctz, sh.red);
-      if (t == 0) {
-        double* o = partial + (size_t)sh.bp.slot[k] * kRedVals;
-        if (pass == 0) {
-          o[0] = cfx; o[1] = cfy; o[2] = ctz;
-        } else {
-          o[0] += cfx; o[1] += cfy; o[2] += ctz;
-        }
+      if (__ballot(add) != 0ull) {   // uniform in the wave
+        cfx = wave_sum(cfx);
+        cfy = wave_sum(cfy);
+        ctz = wave_sum(ctz);
+      }
+      if (lane == 0) {
+        sh.red[k][wv][0] = cfx;
+        sh.red[k][wv][1] = cfy;
+        sh.red[k][wv][2] = ctz;
+      }
+    }
+    __syncthreads();
+    if (t < cnt) {
+      const double(*r)[3] = sh.red[t];
+      const double fx = ((r[0][0] + r[1][0]) + r[2][0]) + r[3][0];
+      const double fy = ((r[0][1] + r[1][1]) + r[2][1]) + r[3][1];
+      const double tz = ((r[0][2] + r[1][2]) + r[2][2]) + r[3][2];
+      double* o = partial + (size_t)sh.bp.slot[t] * kRedVals;
+      if (pass == 0) {
+        o[0] = fx; o[1] = fy; o[2] = tz;
+      } else {
+        o[0] += fx; o[1] += fy; o[2] += tz;
       }
     }
   }

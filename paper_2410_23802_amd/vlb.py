@@ -314,6 +314,9 @@ class Domain:
         self.np_ = len(particles)
         self.precision = precision
         self._desc = make_domain_desc(domain, precision, shift_rho0, shift_T0)
+        # kept on the object: at interpreter exit the module globals may
+        # already be gone when close() runs from __del__
+        self._destroy = lib().vlb_destroy
         self.h = vlb_create(self._desc, stream)
         try:
             vlb_set_particles(self.h, list(particles))
@@ -323,7 +326,7 @@ class Domain:
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
-            vlb_destroy(self.h)
+            self._destroy(self.h)
             self.h = None
 
     __del__ = close
@@ -405,6 +408,7 @@ class Batch:
             counts[i] = len(ps)
             allp.extend(ps)
         parts = make_particles(allp)
+        self._destroy = lib().vlb_batch_destroy   # see Domain.__init__
         h = ctypes.c_void_p()
         _bcheck(lib().vlb_batch_create(n, descs, counts, parts,
                                        ctypes.byref(h)), "vlb_batch_create")
@@ -412,7 +416,7 @@ class Batch:
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
-            lib().vlb_batch_destroy(self.h)
+            self._destroy(self.h)
             self.h = None
 
     __del__ = close
