@@ -164,14 +164,73 @@ __device__ double tri_disk_area(double px, double py, double qx, double qy,
   return area;
 }
 
+// The same area as tri_disk_area, in two parts: the triangle part is added
+// to `tri`, and each circular sector, of angle arg(conj(u) v) between the
+// vectors u and v that bound it, is multiplied into the complex number
+// (zr, zi) as u.v + i u x v -- the angles add as the factors multiply.
+// The product is rescaled by a power of two after each factor (exactly),
+// and vanishing factors (a degenerate sector) are left out.
+__device__ __forceinline__ void sector_factor(double ux, double uy, double vx,
+                                              double vy, double& zr,
+                                              double& zi) {
+  const double cr = ux * vx + uy * vy, ci = ux * vy - uy * vx;
+  if (cr == 0.0 && ci == 0.0) return;
+  const double r = zr * cr - zi * ci, im = zr * ci + zi * cr;
+  int e;
+  (void)frexp(fmax(fabs(r), fabs(im)), &e);
+  zr = ldexp(r, -e);
+  zi = ldexp(im, -e);
+}
+
+__device__ __forceinline__ void tri_disk_parts(double px, double py,
+                                               double qx, double qy, double R,
+                                               double& tri, double& zr,
+                                               double& zi) {
+  const double dx = qx - px, dy = qy - py;
+  const double a = dx * dx + dy * dy;
+  const double b = px * dx + py * dy;
+  const double c = (px * px + py * py) - R * R;
+  const double disc = b * b - a * c;
+  double s1 = 1.0, s2 = 0.0;
+  if (disc > 0.0) {
+    const double r = sqrt(disc);
+    s1 = fmin(fmax((-b - r) / a, 0.0), 1.0);
+    s2 = fmin(fmax((-b + r) / a, 0.0), 1.0);
+  }
+  if (!(s1 < s2)) {
+    sector_factor(px, py, qx, qy, zr, zi);
+    return;
+  }
+  const double ax = px + s1 * dx, ay = py + s1 * dy;
+  const double bx = px + s2 * dx, by = py + s2 * dy;
+  tri += 0.5 * (ax * by - ay * bx);
+  if (s1 > 0.0) sector_factor(px, py, ax, ay, zr, zi);
+  if (s2 < 1.0) sector_factor(bx, by, qx, qy, zr, zi);
+}
+
 // Exact share of cell (i, j) covered by the disk (centre X, Y, radius R),
 // by Green's theorem over the four edges of the square taken
-// counter-clockwise.
+// counter-clockwise: triangles from the centre to the parts of the edges
+// inside the circle, circular sectors for the parts outside.  When the
+// centre lies outside the closed cell the cell subtends less than pi from
+// it, so the sectors' net angle is in (-pi, pi) and one atan2 of the
+// product of their complex factors gives it; otherwise (a disk narrower
+// than the cell's diagonal) each sector is evaluated on its own.
 __device__ double covered_share(double X, double Y, double R, int i, int j) {
-  double x0 = (double)i - X, x1 = (double)(i + 1) - X;
-  double y0 = (double)j - Y, y1 = (double)(j + 1) - Y;
-  double A = tri_disk_area(x0, y0, x1, y0, R) + tri_disk_area(x1, y0, x1, y1, R) +
-             tri_disk_area(x1, y1, x0, y1, R) + tri_disk_area(x0, y1, x0, y0, R);
+  const double x0 = (double)i - X, x1 = (double)(i + 1) - X;
+  const double y0 = (double)j - Y, y1 = (double)(j + 1) - Y;
+  double A;
+  if (x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0) {
+    A = tri_disk_area(x0, y0, x1, y0, R) + tri_disk_area(x1, y0, x1, y1, R) +
+        tri_disk_area(x1, y1, x0, y1, R) + tri_disk_area(x0, y1, x0, y0, R);
+  } else {
+    double tri = 0.0, zr = 1.0, zi = 0.0;
+    tri_disk_parts(x0, y0, x1, y0, R, tri, zr, zi);
+    tri_disk_parts(x1, y0, x1, y1, R, tri, zr, zi);
+    tri_disk_parts(x1, y1, x0, y1, R, tri, zr, zi);
+    tri_disk_parts(x0, y1, x0, y0, R, tri, zr, zi);
+    A = tri + 0.5 * R * R * atan2(zi, zr);
+  }
   return fmin(fmax(A, 0.0), 1.0);
 }
 
