@@ -95,6 +95,30 @@ def run_gpu(vlb, d, ps, precision, steps, warmup):
     }
 
 
+def run_dense(vlb, steps, warmup):
+    """The 1536^2 cavity with 2048 settling disks (list form: a particle
+    pass, then the step kernel), FP64 and FP32: whole-step MLUPS, and the
+    step kernel's event-timed duration against its algorithmic bytes."""
+    import torch
+    import workloads as W
+    d, ps = W.c3_dense()
+    cells = d["nx"] * d["ny"]
+    out = {"workload": "c3_dense", "nx": d["nx"], "ny": d["ny"],
+           "particles": len(ps)}
+    for prec in ("fp64", "fp32"):
+        r = run_gpu(vlb, d, ps, prec, steps, warmup)
+        gbs = BYTES_PER_CELL[prec] * cells / (r["lattice_ms"] * 1e-3) / 1e9
+        out[prec] = {"mlups": round(r["mlups"], 1),
+                     "ms_per_step": round(r["ms_per_step"], 4),
+                     "k_step_us": round(r["lattice_ms"] * 1e3, 1),
+                     "k_step_achieved_GBs": round(gbs, 1),
+                     "k_step_frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+        print(f"# dense {prec}: {r['mlups']:.0f} MLUPS, "
+              f"{r['ms_per_step']:.4f} ms/step, k_step {r['lattice_ms'] * 1e3:.1f} us "
+              f"-> {gbs:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+    return out
+
+
 def run_batch(vlb, steps, warmup):
     """The 256 uneven single-particle domains in FP32: one autotuned batch
     (one launch per step, graph replay) against the same domains run one at
@@ -185,6 +209,8 @@ def main():
                     help="skip the oracle CPU baseline")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-domains measurement")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the dense-cavity measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="first run 5 device-to-device copies of BYTES bytes "
                          "(the known-size reference for HBM counters)")
@@ -265,6 +291,8 @@ def main():
                 "bytes_per_cell": BYTES_PER_CELL[p],
             } for p in precs},
     }
+    if not args.no_dense:
+        line["dense"] = run_dense(vlb, min(args.steps, 100), 4)
     if not args.no_batch:
         line["batch"] = run_batch(vlb, min(args.steps, 100), 4)
     if not args.no_cpu:

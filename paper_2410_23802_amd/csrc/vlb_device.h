@@ -471,28 +471,30 @@ __device__ __forceinline__ void reduce_partials(const Params& P,
 // the centre line, and against each wall the same law applied to the
 // particle's mirror image.  Positions of step n.  Every lane returns the
 // same bits.
-__device__ __forceinline__ void repulsion(const Params& P, const PState& cur,
-                                          const PConst& pc, int p, int lane,
-                                          double& cx, double& cy) {
-  cx = cy = 0.0;
+__device__ __forceinline__ void repulsion_pair(const Params& P, double Xp,
+                                               double Yp, double Rp,
+                                               double Xq, double Yq,
+                                               double Rq, double& cx,
+                                               double& cy) {
   const double zeta = P.coll_range;
-  if (!(zeta > 0.0)) return;
-  const double Xp = cur.X[p], Yp = cur.Y[p], Rp = pc.R[p];
-  for (int q = lane; q < P.np; q += 64) {
-    if (q == p) continue;
-    const double dx = Xp - near_copy(cur.X[q], Xp, (double)P.nx, P.perx);
-    const double dy = Yp - near_copy(cur.Y[q], Yp, (double)P.ny, P.pery);
-    const double d = sqrt(dx * dx + dy * dy);
-    const double reach = Rp + pc.R[q] + zeta;
-    if (d < reach && d > 0.0) {
-      const double s = (reach - d) / zeta;
-      const double mag = P.coll_pp * s * s / d;
-      cx += mag * dx;
-      cy += mag * dy;
-    }
+  const double dx = Xp - near_copy(Xq, Xp, (double)P.nx, P.perx);
+  const double dy = Yp - near_copy(Yq, Yp, (double)P.ny, P.pery);
+  const double d = sqrt(dx * dx + dy * dy);
+  const double reach = Rp + Rq + zeta;
+  if (d < reach && d > 0.0) {
+    const double s = (reach - d) / zeta;
+    const double mag = P.coll_pp * s * s / d;
+    cx += mag * dx;
+    cy += mag * dy;
   }
-  cx = wave_sum(cx);
-  cy = wave_sum(cy);
+}
+
+// The walls' part of the repulsion on a particle at (Xp, Yp), added to the
+// wave-summed pair part.
+__device__ __forceinline__ void repulsion_walls(const Params& P, double Xp,
+                                                double Yp, double Rp,
+                                                double& cx, double& cy) {
+  const double zeta = P.coll_range;
   const double dist[4] = {Xp, (double)P.nx - Xp, Yp, (double)P.ny - Yp};
   const double nrmx[4] = {1.0, -1.0, 0.0, 0.0};
   const double nrmy[4] = {0.0, 0.0, 1.0, -1.0};
@@ -508,21 +510,42 @@ __device__ __forceinline__ void repulsion(const Params& P, const PState& cur,
   }
 }
 
+__device__ __forceinline__ void repulsion(const Params& P, const PState& cur,
+                                          const PConst& pc, int p, int lane,
+                                          double& cx, double& cy) {
+  cx = cy = 0.0;
+  if (!(P.coll_range > 0.0)) return;
+  const double Xp = cur.X[p], Yp = cur.Y[p], Rp = pc.R[p];
+  for (int q = lane; q < P.np; q += 64) {
+    if (q == p) continue;
+    repulsion_pair(P, Xp, Yp, Rp, cur.X[q], cur.Y[q], pc.R[q], cx, cy);
+  }
+  cx = wave_sum(cx);
+  cy = wave_sum(cy);
+  repulsion_walls(P, Xp, Yp, Rp, cx, cy);
+}
+
 struct PUpd {
   double X, Y, th, Ux, Uy, Om, Uxp, Uyp, Omp, Fx, Fy, Tz;
 };
+
+__device__ PUpd particle_update_with(const Params& P, const PState& cur,
+                                     const PConst& pc, const double* partial,
+                                     int have, int p, int lane, double cx,
+                                     double cy);
 
 // One step of particle p, wave-level (every lane returns the same bits):
 // Newton-Euler (eq. particle; the gyroscopic term vanishes in 2-D) with the
 // inside-fluid correction of eq. inside.fluid by backward differences,
 // total force = hydrodynamic + (rho_s - rho_f) V g + repulsion, forward
 // Euler (Sec. 2.3 end).
-__device__ PUpd particle_update(const Params& P, const PState& cur,
-                                const PConst& pc, const double* partial,
-                                int have, int p, int lane) {
-  double fx, fy, tz, cx, cy;
+// The repulsion (cx, cy) is given.
+__device__ PUpd particle_update_with(const Params& P, const PState& cur,
+                                     const PConst& pc, const double* partial,
+                                     int have, int p, int lane, double cx,
+                                     double cy) {
+  double fx, fy, tz;
   reduce_partials(P, cur, pc, partial, have, p, lane, fx, fy, tz);
-  repulsion(P, cur, pc, p, lane, cx, cy);
   PUpd u;
   const double R = pc.R[p], rs = pc.rhos[p];
   const double V = M_PI * R * R;
@@ -553,6 +576,16 @@ __device__ PUpd particle_update(const Params& P, const PState& cur,
   u.Fy = fy;
   u.Tz = tz;
   return u;
+}
+
+__device__ __forceinline__ PUpd particle_update(const Params& P,
+                                                const PState& cur,
+                                                const PConst& pc,
+                                                const double* partial,
+                                                int have, int p, int lane) {
+  double cx, cy;
+  repulsion(P, cur, pc, p, lane, cx, cy);
+  return particle_update_with(P, cur, pc, partial, have, p, lane, cx, cy);
 }
 
 __device__ __forceinline__ void store_particle(PState& s, int p,

@@ -118,6 +118,40 @@ __global__ __launch_bounds__(256) void k_particles(
   }
   const int lane = threadIdx.x & 63;
   const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+
+  // Repulsion of the update: the block stages the particles 256 at a time
+  // in LDS for its four waves (one load per particle per block instead of
+  // one dependent load per particle per wave); each lane still visits
+  // q = lane, lane + 64, ... in ascending order, as repulsion() does.
+  double cx = 0.0, cy = 0.0;
+  if (mode == kModeUpdate && P.coll_range > 0.0) {   // uniform in the grid
+    __shared__ double sX[256], sY[256], sR[256];
+    const bool mine = p < P.np;
+    const double Xp = mine ? cur.X[p] : 0.0, Yp = mine ? cur.Y[p] : 0.0;
+    const double Rp = mine ? pc.R[p] : 0.0;
+    for (int c0 = 0; c0 < P.np; c0 += 256) {
+      const int q = c0 + (int)threadIdx.x;
+      if (q < P.np) {
+        sX[threadIdx.x] = cur.X[q];
+        sY[threadIdx.x] = cur.Y[q];
+        sR[threadIdx.x] = pc.R[q];
+      }
+      __syncthreads();
+      const int m1 = min(256, P.np - c0);
+      if (mine) {
+        for (int m = lane; m < m1; m += 64) {
+          if (c0 + m == p) continue;
+          repulsion_pair(P, Xp, Yp, Rp, sX[m], sY[m], sR[m], cx, cy);
+        }
+      }
+      __syncthreads();
+    }
+    if (mine) {
+      cx = wave_sum(cx);
+      cy = wave_sum(cy);
+      repulsion_walls(P, Xp, Yp, Rp, cx, cy);
+    }
+  }
   if (p >= P.np) return;  // whole wave
 
   if (mode == kModeReduceOnly) {
@@ -132,7 +166,8 @@ __global__ __launch_bounds__(256) void k_particles(
   }
   double nX = cur.X[p], nY = cur.Y[p];
   if (mode == kModeUpdate) {
-    const PUpd u = particle_update(P, cur, pc, partial, have_partials, p, lane);
+    const PUpd u = particle_update_with(P, cur, pc, partial, have_partials,
+                                        p, lane, cx, cy);
     if (lane == 0) store_particle(next, p, u);
     nX = u.X;
     nY = u.Y;
