@@ -96,10 +96,8 @@ def check_case(oracle_mod, o, got_fields, got_particles, d, ps, nsteps,
     return e
 
 
-# FP32 bars: 1e-5 of each field's scale; velocities and forces, which are
-# differences of O(1) populations a thousand times smaller, at 1e-3
-FP32_BAR = {"ux": 1e-3, "uy": 1e-3, "omega": 1e-3, "Fx": 1e-3, "Fy": 1e-3,
-            "Tz": 1e-3}
+# FP32 bar: 1e-5 of each quantity's scale (the same scales as at FP64)
+FP32_BAR = {}
 
 
 def batch_state(b, i, ps):

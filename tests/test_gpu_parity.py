@@ -354,11 +354,19 @@ def test_fp32_c1(vlb, oracle_mod):
     d, ps = W.c1_tiny()
     say("case: c1_tiny fp32 1000 steps")
     g, o = run_pair(vlb, oracle_mod, d, ps, 1000, "fp32")
-    e = field_errors(g, o, ("rho", "T", "fs"))
-    # velocities are O(1e-4): compare on the scale of the velocity field
-    assert max(e.values()) < 1e-5, e
-    ue = rel(g.field("ux"), o.field("ux"))
-    assert ue < 1e-3, ue
+    e = field_errors(g, o)
+    say(f"  fp32 errors after 1000 steps: {e}")
+    bad = {k: v for k, v in e.items() if v >= FP32_BAR.get(k, 1e-5)}
+    assert not bad, (bad, e)
+
+
+# FP32 after 1000 steps of the tiny channel: 1e-5 of each field's scale,
+# except (a) [df_s/dt], whose recursion keeps every rounding of the FP32
+# carrier (one per step, never damped), and (b) the velocity: the flow here
+# is 1e-4 in lattice units, and FP32 rounds rho ~ 1 at 6e-8, which feeds
+# acoustic velocities of order c_s x 6e-8 ~ 3.5e-8, a few 1e-5 of this
+# flow (measured 2.3e-5).  Both are held to 1e-4.
+FP32_BAR = {"dfs": 1e-4, "ux": 1e-4, "uy": 1e-4}
 
 
 @pytest.mark.parametrize("prec,tol_T", [("fp16s", 5e-2), ("bf16s", 2e-1)])
