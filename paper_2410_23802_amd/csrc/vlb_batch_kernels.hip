@@ -71,10 +71,11 @@ __device__ __forceinline__ StepBufs rebase_bufs(char* a, const StepBufs& b) {
 // domain's particle-tile tasks first, then its tiles; its order (chosen by
 // the autotuner) decides which XCD streams which tiles.  Every task is one
 // call of step_task, exactly as in k_step, so a domain's results do not
-// depend on the batch around it or on the table order.
+// depend on the batch around it or on the table order.  Occupancy targets
+// as for k_step.
 template <int PREC, bool OUT>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 1))) void k_batch_step(
+__attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 5))) void k_batch_step(
     const BatchCase* __restrict__ cases, const BatchTask* __restrict__ tasks,
     char* __restrict__ arena, int ntasks, int parity, int have) {
   typedef typename Prec<PREC>::C C;

@@ -8,12 +8,13 @@ namespace vlb {
 
 // The step kernel of one domain: block roles as above.  FP64 is held to 128
 // VGPRs (4 waves per SIMD, the occupancy of the plain update; the geometry
-// of the particle role spills a little).  The 32-bit forms are left
-// unconstrained: at 8 waves the particle role spills heavily and the step
-// is slower than at 4.
+// of the particle role spills a little).  The 32-bit forms are held to 5
+// waves (96 VGPRs, no added spill): 4-7 % faster on the channel than the
+// unconstrained 4 waves; at 6 the particle role spills and loses it again
+// (and the LDS of a particle tile caps a CU at 7 blocks).
 template <int PREC, bool OUT, bool SCAN>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 1))) void k_step(
+__attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 5))) void k_step(
     const Params P, const Hot<typename Prec<PREC>::C> H, const StepBufs B,
     int have) {
   typedef typename Prec<PREC>::C C;
