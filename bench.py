@@ -160,13 +160,20 @@ def run_batch(vlb, steps, warmup):
                        for k, v in tune.items()}}
 
 
-def cpu_baseline(d, ps, target_s=20.0):
-    """The FP64 oracle as it stands, on a bounded sample of the same
-    workload: as many steps as take about `target_s` seconds."""
-    from oracle import oracle as O
-    if not os.path.exists(O.LIB):
-        O.build()
-    threads = min(os.cpu_count() or 1, 16)
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+def _oracle_rate(O, d, ps, threads, target_s):
+    """MLUPS of the oracle on `threads` threads: one untimed step, then as
+    many steps as take about target_s seconds."""
     O.set_threads(threads)
     o = O.Oracle(d, ps).init()
     t0 = time.perf_counter()
@@ -176,12 +183,26 @@ def cpu_baseline(d, ps, target_s=20.0):
     t0 = time.perf_counter()
     o.step(n)
     dt = time.perf_counter() - t0
-    cells = d["nx"] * d["ny"]
-    return {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS",
+    o.close()
+    return d["nx"] * d["ny"] * n / dt / 1e6, n, dt
+
+
+def cpu_baseline(d, ps, target_s=20.0):
+    """The FP64 oracle as it stands, on a bounded sample of the same
+    workload, on up to 16 host threads (and, for reference, on one)."""
+    from oracle import oracle as O
+    if not os.path.exists(O.LIB):
+        O.build()
+    threads = min(os.cpu_count() or 1, 16)
+    v, n, dt = _oracle_rate(O, d, ps, threads, target_s)
+    v1, n1, dt1 = _oracle_rate(O, d, ps, 1, target_s / 4)
+    return {"value": round(v, 3), "unit": "MLUPS",
             "cores": threads, "kind": "oracle",
             "sample": f"{d['nx']}x{d['ny']} channel, {len(ps)} particle, "
                       f"{n} steps after one untimed step, FP64, "
-                      f"{threads} OpenMP threads, {dt:.1f} s"}
+                      f"{threads} OpenMP threads, {dt:.1f} s, on {_cpu_model()}",
+            "value_1_thread": round(v1, 3),
+            "sample_1_thread": f"{n1} steps on 1 thread, {dt1:.1f} s"}
 
 
 def copy_probe(torch, nbytes):
