@@ -95,6 +95,30 @@ def run_gpu(vlb, d, ps, precision, steps, warmup):
     }
 
 
+def run_large(vlb, precs, steps, warmup):
+    """The channel's physics on a 1000 x 16000 grid (16 M cells): working
+    sets of 1.3-4.9 GB, far beyond the 256 MB Infinity Cache, so these
+    bandwidths are HBM's (the 200 x 4000 channel's FP32 and 16-bit working
+    sets fit that cache)."""
+    import workloads as W
+    d, ps = W.c2_channel(nx=1000, ny=16000)
+    cells = d["nx"] * d["ny"]
+    out = {"workload": "c2_channel at 1000 x 16000", "nx": d["nx"],
+           "ny": d["ny"], "particles": len(ps)}
+    for prec in precs:
+        r = run_gpu(vlb, d, ps, prec, steps, warmup)
+        gbs = BYTES_PER_CELL[prec] * cells / (r["lattice_ms"] * 1e-3) / 1e9
+        out[prec] = {"mlups": round(r["mlups"], 1),
+                     "k_step_us": round(r["lattice_ms"] * 1e3, 1),
+                     "k_step_achieved_GBs": round(gbs, 1),
+                     "k_step_frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+        print(f"# large {prec}: {r['mlups']:.0f} MLUPS, k_step "
+              f"{r['lattice_ms'] * 1e3:.1f} us -> {gbs:.0f} GB/s "
+              f"({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak)",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def run_dense(vlb, steps, warmup):
     """The 1536^2 cavity with 2048 settling disks (list form: a particle
     pass, then the step kernel), FP64 and FP32: whole-step MLUPS, and the
@@ -232,6 +256,8 @@ def main():
                     help="skip the batched-domains measurement")
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense-cavity measurement")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 16 M-cell channel measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="first run 5 device-to-device copies of BYTES bytes "
                          "(the known-size reference for HBM counters)")
@@ -319,6 +345,8 @@ def main():
                 "bytes_per_cell": BYTES_PER_CELL[p],
             } for p in precs},
     }
+    if not args.no_large:
+        line["large"] = run_large(vlb, precs, min(args.steps, 50), 4)
     if not args.no_dense:
         line["dense"] = run_dense(vlb, min(args.steps, 100), 4)
     if not args.no_batch:
