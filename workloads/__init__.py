@@ -137,6 +137,30 @@ def c2_channel(nx=200, ny=4000) -> tuple[dict, list]:
     return d, [p]
 
 
+def e6_cht_channel(R_lambda=1.0, R_cv=1.0, length_D=60, start_D=10,
+                   D=20.0) -> tuple[dict, list]:
+    """The paper's sedimentation of one cold particle with conjugate heat
+    transfer (Sec. 3.3 and the section after it): a channel of width 4 D
+    with walls held at T_h = 1, a disk of diameter D = 20 cells starting on
+    the centre line at T_c = 0 in fluid at T_h, density ratio 1.00232,
+    Re = 10.5, Pr = 0.7, Gr = 1000, tau_f = 0.53, T_ref = T_h.  The paper
+    gives no channel length: length_D diameters here, the disk starting
+    start_D diameters below the top.  U_ref = Re nu / D sets |g| through
+    U_ref = sqrt((rho_r - 1) |g| pi D / 2) and Gr sets beta."""
+    tau_f, Pr, rho_r, Re, Gr = 0.53, 0.7, 1.00232, 10.5, 1000.0
+    nu = viscosity(tau_f)
+    U = Re * nu / D
+    g = U * U / ((rho_r - 1.0) * math.pi * D / 2.0)
+    nx, ny = int(round(4 * D)), int(round(length_D * D))
+    d = domain(nx, ny, tau_f=tau_f, lambda_f=nu / Pr, R_lambda=R_lambda,
+               R_cv=R_cv, gravity=(0.0, -g),
+               beta=beta_from_grashof(Gr, g, 1.0, D, nu), T_ref=1.0,
+               init_T=1.0, **collision_params(rho_r, D / 2, g))
+    d = walls(d, thermal="dirichlet", T_wall=1.0)
+    p = particle(nx / 2.0, ny - start_D * D, D / 2, rho_s=rho_r, T_init=0.0)
+    return d, [p]
+
+
 def rsa_disks(n, radius, box, gap, seed, max_tries=5_000_000):
     """Random sequential addition of n equal disks in box = (x0, y0, x1, y1)
     keeping a surface gap >= gap between disks and from the box edges."""
