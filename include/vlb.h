@@ -191,6 +191,20 @@ int64_t vlb_step_count(const vlb_ctx* ctx);
 vlb_status vlb_timing_enable(vlb_ctx* ctx, int32_t on);
 vlb_status vlb_timing_read(vlb_ctx* ctx, double* total_ms, int64_t* count);
 
+/* Memory-pattern probe (measurement support).  Runs `reps` launches of a
+ * kernel that moves exactly what one step moves -- per cell the nine f and
+ * nine g populations pulled from the neighbours of the streaming step
+ * (Sec. 2.1, eq. lbe.rho; Sec. 2.2, eq. lbe.e) over the context's own SoA
+ * planes and tile order, plus the [df_s/dt] carrier, read once and written
+ * once -- with none of the arithmetic, on the context stream, and stores
+ * the average duration of one launch (microseconds) in *us_per_launch.
+ * Algorithmic bytes per cell over that duration is the bandwidth the
+ * access pattern itself reaches on the device: the ceiling for the step
+ * kernel.  It writes only the buffers the next step overwrites in full, so
+ * the state is unchanged.  Blocks until done.  VLB_EINVAL for reps <= 0 or
+ * a null pointer; VLB_ESTATE before a successful vlb_init. */
+vlb_status vlb_stream_probe(vlb_ctx* ctx, int32_t reps, double* us_per_launch);
+
 /* Bytes of device memory the context holds. */
 size_t vlb_device_bytes(const vlb_ctx* ctx);
 

@@ -706,6 +706,34 @@ vlb_status vlb_timing_read(vlb_ctx* c, double* total_ms, int64_t* count) {
   return VLB_OK;
 }
 
+vlb_status vlb_stream_probe(vlb_ctx* c, int32_t reps, double* us_per_launch) {
+  if (!c) return VLB_EINVAL;
+  if (!us_per_launch || reps <= 0)
+    return fail(c, VLB_EINVAL, "stream probe: reps must be > 0 and the "
+                               "output pointer non-null");
+  if (!c->initialized) return fail(c, VLB_ESTATE, "vlb_init has not succeeded");
+  const StepBufs B = context_step_bufs(c);
+  struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  HIP_TRY(c, hipEventCreate(&ev.a));
+  HIP_TRY(c, hipEventCreate(&ev.b));
+  HIP_TRY(c, launch_stream_probe(c->prec, c->P, B, c->stream));   // warm
+  HIP_TRY(c, hipEventRecord(ev.a, c->stream));
+  for (int32_t k = 0; k < reps; ++k)
+    HIP_TRY(c, launch_stream_probe(c->prec, c->P, B, c->stream));
+  HIP_TRY(c, hipEventRecord(ev.b, c->stream));
+  HIP_TRY(c, hipEventSynchronize(ev.b));
+  float ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, ev.a, ev.b));
+  *us_per_launch = 1e3 * (double)ms / reps;
+  return VLB_OK;
+}
+
 size_t vlb_device_bytes(const vlb_ctx* c) { return c ? c->dev_bytes : 0; }
 
 const char* vlb_last_error(const vlb_ctx* c) {

@@ -182,6 +182,10 @@ hipError_t launch_particle_sums(const Params& P, PState ps, PConst pc,
 hipError_t launch_ownership(const Params& P, PState ps, PConst pc, Lists L,
                             int* count, int* ids, int* full, int* flags,
                             hipStream_t s);
+// The step's memory pattern without its arithmetic (fi -> fo, gi -> go,
+// hin -> hout of B; the state in fi, gi, hin is left as it was).
+hipError_t launch_stream_probe(int prec, const Params& P, const StepBufs& B,
+                              hipStream_t s);
 hipError_t launch_unpack(int prec, const Params& P, const void* pop,
                          size_t plane, int which_g, double* out,
                          hipStream_t s);

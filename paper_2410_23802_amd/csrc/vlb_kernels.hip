@@ -304,6 +304,46 @@ __global__ __launch_bounds__(kBlock) void k_ownership(
   count[c] = n < P.kmax ? n : P.kmax;
 }
 
+// Memory-pattern probe: the step kernel's global-memory traffic without its
+// arithmetic.  Per cell: the pulled loads of the nine f and nine g
+// populations (periodic neighbours, the same SoA planes), the carrier load,
+// and the 9 + 9 + 1 stores, over the same XCD-ordered tiles.  What it
+// reaches is the bandwidth the access pattern itself allows on the device:
+// the ceiling the step kernel's algorithmic bandwidth is compared with.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_stream_probe(
+    const Params P, const typename Prec<PREC>::S* __restrict__ fin,
+    typename Prec<PREC>::S* __restrict__ fout,
+    const typename Prec<PREC>::S* __restrict__ gin,
+    typename Prec<PREC>::S* __restrict__ gout,
+    const typename Prec<PREC>::H* __restrict__ hin,
+    typename Prec<PREC>::H* __restrict__ hout, size_t plane) {
+  typedef typename Prec<PREC>::S S;
+  const int tile = stream_tile(P, blockIdx.x);
+  if (tile >= P.nblocks) return;
+  const int c = tile * kBlock + threadIdx.x;
+  if (c >= P.N) return;
+  const int y = c / P.nx, x = c - y * P.nx;
+  const int xm = x == 0 ? P.nx - 1 : x - 1, xp = x == P.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? P.ny - 1 : y - 1, yp = y == P.ny - 1 ? 0 : y + 1;
+  const int src[9] = {c,           y * P.nx + xm,  ym * P.nx + x,
+                      y * P.nx + xp, yp * P.nx + x, ym * P.nx + xm,
+                      ym * P.nx + xp, yp * P.nx + xp, yp * P.nx + xm};
+  S f[9], g[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    f[q] = fin[(size_t)q * plane + src[q]];
+    g[q] = gin[(size_t)q * plane + src[q]];
+  }
+  const typename Prec<PREC>::H h = hin[c];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    fout[(size_t)q * plane + c] = f[q];
+    gout[(size_t)q * plane + c] = g[q];
+  }
+  hout[c] = h;
+}
+
 // Populations of the current state as FP64 (unshifted).
 template <int PREC>
 __global__ void k_unpack(const Params P, const typename Prec<PREC>::S* pop,
@@ -409,6 +449,26 @@ hipError_t launch_ownership(const Params& P, PState ps, PConst pc, Lists L,
     hipLaunchKernelGGL(k_ownership<false>, dim3(P.nblocks), dim3(kBlock), 0, s,
                        P, ps, pc, L, count, ids, full, flags);
   return hipGetLastError();
+}
+
+hipError_t launch_stream_probe(int prec, const Params& P, const StepBufs& B,
+                              hipStream_t s) {
+  const unsigned nb = (unsigned)P.stream_blocks;
+#define VLB_PROBE(PR)                                                        \
+  hipLaunchKernelGGL(k_stream_probe<PR>, dim3(nb), dim3(kBlock), 0, s, P,     \
+                     (const Prec<PR>::S*)B.fi, (Prec<PR>::S*)B.fo,            \
+                     (const Prec<PR>::S*)B.gi, (Prec<PR>::S*)B.go,            \
+                     (const Prec<PR>::H*)B.hin, (Prec<PR>::H*)B.hout,         \
+                     B.plane);                                                \
+  return hipGetLastError();
+  switch (prec) {
+    case VLB_FP64: VLB_PROBE(VLB_FP64)
+    case VLB_FP32: VLB_PROBE(VLB_FP32)
+    case VLB_FP16_SHIFT: VLB_PROBE(VLB_FP16_SHIFT)
+    case VLB_BF16_SHIFT: VLB_PROBE(VLB_BF16_SHIFT)
+  }
+#undef VLB_PROBE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_unpack(int prec, const Params& P, const void* pop,

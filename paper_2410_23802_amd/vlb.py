@@ -111,6 +111,8 @@ def lib():
         "vlb_timing_enable": ([vp, i32], ctypes.c_int),
         "vlb_timing_read": ([vp, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(i64)], ctypes.c_int),
+        "vlb_stream_probe": ([vp, i32, ctypes.POINTER(ctypes.c_double)],
+                             ctypes.c_int),
         "vlb_device_bytes": ([vp], ctypes.c_size_t),
         "vlb_last_error": ([vp], ctypes.c_char_p),
         "vlb_destroy": ([vp], None),
@@ -286,6 +288,15 @@ def vlb_timing_read(h):
     return ms.value, n.value
 
 
+def vlb_stream_probe(h, reps: int) -> float:
+    """Average microseconds of one launch of the step's memory pattern
+    without its arithmetic (state unchanged)."""
+    us = ctypes.c_double()
+    _check(lib().vlb_stream_probe(h, int(reps), ctypes.byref(us)),
+           "vlb_stream_probe", h)
+    return us.value
+
+
 def vlb_device_bytes(h) -> int:
     return int(lib().vlb_device_bytes(h))
 
@@ -373,6 +384,9 @@ class Domain:
 
     def timing_read(self):
         return vlb_timing_read(self.h)
+
+    def stream_probe(self, reps: int = 50) -> float:
+        return vlb_stream_probe(self.h, reps)
 
 
 # ---- batches ------------------------------------------------------------------

@@ -416,6 +416,31 @@ def test_save_load_continues_bitwise(vlb):
     assert all(np.array_equal(pa[k], pb[k]) for k in pa.dtype.names)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16s"])
+def test_stream_probe_leaves_state_unchanged(vlb, prec):
+    """The memory-pattern probe writes only what the next step overwrites:
+    steps around it give what the same steps without it give, bit for
+    bit."""
+    d, ps = W.c2_channel(nx=48, ny=160)
+    ps[0]["y"] = 120.0
+    say(f"case: stream probe, {prec}")
+    a = vlb.Domain(d, ps, prec).init().step(7)
+    us = a.stream_probe(3)
+    assert us > 0.0
+    a.step(6)
+    b = vlb.Domain(d, ps, prec).init().step(13)
+    for n in ("f", "g", "T", "dfs"):
+        assert np.array_equal(a.field(n), b.field(n)), n
+    pa, pb = a.particles(), b.particles()
+    assert all(np.array_equal(pa[k], pb[k]) for k in pa.dtype.names)
+    with pytest.raises(vlb.VlbError) as ei:
+        a.stream_probe(0)
+    assert ei.value.status == vlb.VLB_EINVAL
+    with pytest.raises(vlb.VlbError) as ei:
+        vlb.Domain(d, ps, prec).stream_probe(1)
+    assert ei.value.status == vlb.VLB_ESTATE
+
+
 def test_unstable_flag(vlb):
     # a force whose square overflows: the populations become non-finite
     d = W.domain(32, 32, body_force=(1e160, 0.0))

@@ -161,6 +161,34 @@ def e6_cht_channel(R_lambda=1.0, R_cv=1.0, length_D=60, start_D=10,
     return d, [p]
 
 
+def e7_cht_cavity(L=1700, D=24.0, rows=32, cols=64, gap=2.0, left=19.0,
+                  top=18.0) -> tuple[dict, list]:
+    """The paper's sedimentation of 2048 cold particles with conjugate heat
+    transfer in a square cavity (its last application section): L = 1700
+    cells, adiabatic no-slip walls, disks of diameter D = 24 in 32 rows and
+    64 columns with gaps of 2 cells, 19 cells from the left wall and 18 from
+    the top; particles at T_c = 0 in fluid at T_h = 1 = T_ref; density ratio
+    1.5, Re = 40.5, Pr = 0.71, Gr = 100, R_lambda = 1, R_cv = 2,
+    tau_f = 0.55 and sigma_e = sigma_eps = 1 (the choice made there for
+    stability)."""
+    tau_f, Pr, rho_r, Re, Gr = 0.55, 0.71, 1.5, 40.5, 100.0
+    nu = viscosity(tau_f)
+    U = Re * nu / D
+    g = U * U / ((rho_r - 1.0) * math.pi * D / 2.0)
+    d = domain(L, L, tau_f=tau_f, lambda_f=nu / Pr, R_lambda=1.0, R_cv=2.0,
+               gravity=(0.0, -g), beta=beta_from_grashof(Gr, g, 1.0, D, nu),
+               T_ref=1.0, init_T=1.0, sigma_rule=1,
+               **collision_params(rho_r, D / 2, g))
+    d = walls(d, thermal="adiabatic")
+    ps = []
+    for i in range(rows):
+        y = L - top - D / 2 - i * (D + gap)
+        for j in range(cols):
+            x = left + D / 2 + j * (D + gap)
+            ps.append(particle(x, y, D / 2, rho_s=rho_r, T_init=0.0))
+    return d, ps
+
+
 def rsa_disks(n, radius, box, gap, seed, max_tries=5_000_000):
     """Random sequential addition of n equal disks in box = (x0, y0, x1, y1)
     keeping a surface gap >= gap between disks and from the box edges."""
