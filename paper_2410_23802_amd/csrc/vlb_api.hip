@@ -115,12 +115,22 @@ static vlb_status validate(const vlb_domain_desc* d, std::string& why) {
 // the list form the particle tiles are updated in place, cluster where the
 // particles are and dominate the time, so tiles are dealt one at a time
 // (group size 1: block k takes tile k), which spreads them evenly.
-static void set_stream_groups(Params& P, bool list_form) {
+//
+// The 16-bit forms stream two tiles per block (each lane loads its cell of
+// both before computing either) where one step moves more than the 256 MB
+// Infinity Cache holds: there a wave with one cell per lane has too few
+// bytes in flight (16 M-cell channel: 344 -> 288 us).  Below that size, and
+// in the list form (a particle tile would share its block), one tile per
+// block is faster (channel of 0.8 M cells: 17.6 vs 18.1 us).
+static void set_stream_groups(Params& P, bool list_form, int prec) {
   int g = list_form ? 1 : (P.nblocks + 7) / 8;
   if (g < 1) g = 1;
   P.xcd_group = g;
   const int per_xcd = (P.nblocks + 8 * g - 1) / (8 * g);
   P.stream_blocks = 8 * g * per_xcd;
+  const bool b16 = prec == VLB_FP16_SHIFT || prec == VLB_BF16_SHIFT;
+  const size_t step_bytes = (size_t)P.N * (2 * 9 * 2 + 2 * 4);
+  P.pair_tiles = b16 && !list_form && step_bytes > ((size_t)256 << 20);
 }
 
 static void derive_params(vlb_ctx* c) {
@@ -132,7 +142,7 @@ static void derive_params(vlb_ctx* c) {
   P.N = d.nx * d.ny;
   P.nblocks = (P.N + kBlock - 1) / kBlock;
   P.nfirst = 0;
-  set_stream_groups(P, false);
+  set_stream_groups(P, false, c->prec);
   P.perx = d.face_flow[VLB_FACE_XLO] == VLB_PERIODIC;
   P.pery = d.face_flow[VLB_FACE_YLO] == VLB_PERIODIC;
   P.kmax = d.kmax;
@@ -327,7 +337,7 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
   const int rows = 2 * (int)ceil(rmax) + 5;
   c->P.maxr = (int)(((int64_t)rows * c->d.nx + kBlock - 1) / kBlock) + 3;
   c->P.nfirst = c->P.scan ? (n * c->P.maxr + 7) / 8 * 8 : 0;
-  set_stream_groups(c->P, n > 0 && !c->P.scan);
+  set_stream_groups(c->P, n > 0 && !c->P.scan, c->prec);
   const size_t part_slots =
       c->P.scan ? (size_t)n * c->P.nblocks : (size_t)n * c->maxb;
   c->initialized = false;
@@ -349,7 +359,7 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
     c->P.np = 0;
     c->P.scan = 0;
     c->P.nfirst = 0;
-    set_stream_groups(c->P, false);
+    set_stream_groups(c->P, false, c->prec);
     return fail(c, VLB_ENOMEM, "particle allocation failed");
   }
   for (int k = 0; k < 2; ++k) {

@@ -53,6 +53,7 @@ struct Prec<VLB_FP64> {
   typedef double S;
   typedef double C;
   typedef double H;
+  static __device__ __forceinline__ C cv(S v) { return v; }
   static __device__ __forceinline__ C ld(const S* p, size_t i) { return p[i]; }
   static __device__ __forceinline__ void st(S* p, size_t i, C v) { p[i] = v; }
 };
@@ -62,6 +63,7 @@ struct Prec<VLB_FP32> {
   typedef float S;
   typedef float C;
   typedef float H;
+  static __device__ __forceinline__ C cv(S v) { return v; }
   static __device__ __forceinline__ C ld(const S* p, size_t i) { return p[i]; }
   static __device__ __forceinline__ void st(S* p, size_t i, C v) { p[i] = v; }
 };
@@ -71,6 +73,7 @@ struct Prec<VLB_FP16_SHIFT> {
   typedef _Float16 S;
   typedef float C;
   typedef float H;
+  static __device__ __forceinline__ C cv(S v) { return (float)v; }
   static __device__ __forceinline__ C ld(const S* p, size_t i) {
     return (float)p[i];
   }
@@ -84,8 +87,11 @@ struct Prec<VLB_BF16_SHIFT> {
   typedef uint16_t S;
   typedef float C;
   typedef float H;
+  static __device__ __forceinline__ C cv(S v) {
+    return __uint_as_float(((uint32_t)v) << 16);
+  }
   static __device__ __forceinline__ C ld(const S* p, size_t i) {
-    return __uint_as_float(((uint32_t)p[i]) << 16);
+    return cv(p[i]);
   }
   static __device__ __forceinline__ void st(S* p, size_t i, C v) {
     // round to nearest even on the upper 16 bits
@@ -796,19 +802,33 @@ __device__ __forceinline__ void gather_particles(
 // upstream cell lies beyond a wall -- the rule of that wall applied to the
 // opposite population of the cell itself.  XS/YS name the wall met across
 // the x / y side (-1: none); when both apply (a corner) the y wall decides.
-// Branch-free: one load from a selected address, then selects of
-// compile-time-indexed wall constants.
+// Two halves, so that a caller can issue the loads of more than one cell
+// before it uses any: pull_load reads the storage value from one selected
+// address, pull_fix converts it and applies the wall's rule (selects of
+// compile-time-indexed wall constants).  Branch-free.
 template <int Q, int OPP, int XS, int YS, class T>
-__device__ __forceinline__ void pull(const typename T::S* __restrict__ fin,
-                                     const typename T::S* __restrict__ gin,
-                                     size_t plane, int cc, int src, bool ox,
-                                     bool oy, const Hot<typename T::C>& H,
-                                     typename T::C& fv, typename T::C& gv) {
-  typedef typename T::C C;
+__device__ __forceinline__ void pull_load(const typename T::S* __restrict__ fin,
+                                          const typename T::S* __restrict__ gin,
+                                          size_t plane, int cc, int src,
+                                          bool ox, bool oy,
+                                          typename T::S& fr,
+                                          typename T::S& gr) {
   const bool out = (XS >= 0 && ox) || (YS >= 0 && oy);
   const size_t idx = out ? (size_t)OPP * plane + cc : (size_t)Q * plane + src;
-  C f = T::ld(fin, idx), g = T::ld(gin, idx);
+  fr = fin[idx];
+  gr = gin[idx];
+}
+
+template <int Q, int XS, int YS, class T>
+__device__ __forceinline__ void pull_fix(typename T::S fr, typename T::S gr,
+                                         bool ox, bool oy,
+                                         const Hot<typename T::C>& H,
+                                         typename T::C& fv,
+                                         typename T::C& gv) {
+  typedef typename T::C C;
+  C f = T::cv(fr), g = T::cv(gr);
   if (XS >= 0 || YS >= 0) {
+    const bool out = (XS >= 0 && ox) || (YS >= 0 && oy);
     constexpr int WX = XS >= 0 ? XS : YS, WY = YS >= 0 ? YS : XS;
     const bool useY = YS >= 0 && oy;
     const C fa = useY ? H.fadd[WY][Q] : H.fadd[WX][Q];
@@ -868,59 +888,101 @@ struct PSums {
   C S0, S1x, S1y, S2xx, S2yy, S2xy;
 };
 
-// The lattice update of the 256 cells of one tile: pull streaming with the
-// wall rules, the volumetric no-slip step with the particle sums `part`
-// supplies, the coupled macroscopic solve and both collisions.  Every thread
-// of the block calls pre() before it issues its population loads, gather()
-// right after (so that its work overlaps them; a true result, which must be
-// uniform over the wave, abandons the tile: the return value is then false)
-// and then part(act, x, y, rho, jx*, jy*, S).
-template <int PREC, bool OUT, class PreFn, class GatherFn, class PartFn>
-__device__ __forceinline__ bool lattice_tile(
-    const Params& P, const Hot<typename Prec<PREC>::C>& H,
-    const typename Prec<PREC>::S* __restrict__ fin,
-    typename Prec<PREC>::S* __restrict__ fout,
-    const typename Prec<PREC>::S* __restrict__ gin,
-    typename Prec<PREC>::S* __restrict__ gout,
-    const typename Prec<PREC>::H* __restrict__ hin,
-    typename Prec<PREC>::H* __restrict__ hout, size_t plane, int tile,
-    double* __restrict__ macro, int* flags, PreFn pre, GatherFn gather,
-    PartFn part) {
-  typedef Prec<PREC> T;
-  typedef typename T::C C;
-  typedef typename T::H HT;
+// The storage values one lane loads for its cell of a tile (the pulled
+// populations and the carrier), with the cell's coordinates.
+template <int PREC>
+struct CellLoad {
+  typename Prec<PREC>::S f[9], g[9];
+  typename Prec<PREC>::H hn;
+  int cc, x, y;
+  bool act;
+};
 
+// Which faces a cell's upstream neighbours lie beyond (walls only).
+struct Beyond {
+  bool xm, xp, ym, yp;
+};
+
+__device__ __forceinline__ Beyond beyond(const Params& P, int x, int y) {
+  Beyond o;
+  o.xm = x == 0 && !P.perx;
+  o.xp = x == P.nx - 1 && !P.perx;
+  o.ym = y == 0 && !P.pery;
+  o.yp = y == P.ny - 1 && !P.pery;
+  return o;
+}
+
+// Issue the loads of this lane's cell of `tile` (pull streaming with the
+// wall rules' addresses, eq. lbe.rho.str and lbe.e.str); inactive lanes
+// read a valid cell.
+template <int PREC>
+__device__ __forceinline__ void load_cell(
+    const Params& P, const typename Prec<PREC>::S* __restrict__ fin,
+    const typename Prec<PREC>::S* __restrict__ gin,
+    const typename Prec<PREC>::H* __restrict__ hin, size_t plane, int tile,
+    CellLoad<PREC>& L) {
+  typedef Prec<PREC> T;
   const int c = tile * kBlock + threadIdx.x;
-  const bool act = c < P.N;
-  const int cc = act ? c : P.N - 1;   // inactive lanes read a valid cell
+  L.act = c < P.N;
+  const int cc = L.act ? c : P.N - 1;
   const int y = cc / P.nx;
   const int x = cc - y * P.nx;
-
-  // ---- pull streaming with the wall rules (eq. lbe.rho.str, lbe.e.str)
+  L.cc = cc;
+  L.x = x;
+  L.y = y;
+  const Beyond o = beyond(P, x, y);
   int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
-  const bool oxm = xm < 0 && !P.perx, oxp = xp >= P.nx && !P.perx;
-  const bool oym = ym < 0 && !P.pery, oyp = yp >= P.ny && !P.pery;
   xm = xm < 0 ? xm + P.nx : xm;
   xp = xp >= P.nx ? xp - P.nx : xp;
   ym = ym < 0 ? ym + P.ny : ym;
   yp = yp >= P.ny ? yp - P.ny : yp;
   const int r0 = y * P.nx, rm = ym * P.nx, rp = yp * P.nx;
-  pre();
-  C f[9], g[9];
-  f[0] = T::ld(fin, cc);
-  g[0] = T::ld(gin, cc);
   constexpr int XLO = VLB_FACE_XLO, XHI = VLB_FACE_XHI;
   constexpr int YLO = VLB_FACE_YLO, YHI = VLB_FACE_YHI;
-  pull<1, 3, XLO, -1, T>(fin, gin, plane, cc, r0 + xm, oxm, false, H, f[1], g[1]);
-  pull<2, 4, -1, YLO, T>(fin, gin, plane, cc, rm + x, false, oym, H, f[2], g[2]);
-  pull<3, 1, XHI, -1, T>(fin, gin, plane, cc, r0 + xp, oxp, false, H, f[3], g[3]);
-  pull<4, 2, -1, YHI, T>(fin, gin, plane, cc, rp + x, false, oyp, H, f[4], g[4]);
-  pull<5, 7, XLO, YLO, T>(fin, gin, plane, cc, rm + xm, oxm, oym, H, f[5], g[5]);
-  pull<6, 8, XHI, YLO, T>(fin, gin, plane, cc, rm + xp, oxp, oym, H, f[6], g[6]);
-  pull<7, 5, XHI, YHI, T>(fin, gin, plane, cc, rp + xp, oxp, oyp, H, f[7], g[7]);
-  pull<8, 6, XLO, YHI, T>(fin, gin, plane, cc, rp + xm, oxm, oyp, H, f[8], g[8]);
-  const HT hn = hin[cc];
-  if (gather()) return false;
+  L.f[0] = fin[cc];
+  L.g[0] = gin[cc];
+  pull_load<1, 3, XLO, -1, T>(fin, gin, plane, cc, r0 + xm, o.xm, false, L.f[1], L.g[1]);
+  pull_load<2, 4, -1, YLO, T>(fin, gin, plane, cc, rm + x, false, o.ym, L.f[2], L.g[2]);
+  pull_load<3, 1, XHI, -1, T>(fin, gin, plane, cc, r0 + xp, o.xp, false, L.f[3], L.g[3]);
+  pull_load<4, 2, -1, YHI, T>(fin, gin, plane, cc, rp + x, false, o.yp, L.f[4], L.g[4]);
+  pull_load<5, 7, XLO, YLO, T>(fin, gin, plane, cc, rm + xm, o.xm, o.ym, L.f[5], L.g[5]);
+  pull_load<6, 8, XHI, YLO, T>(fin, gin, plane, cc, rm + xp, o.xp, o.ym, L.f[6], L.g[6]);
+  pull_load<7, 5, XHI, YHI, T>(fin, gin, plane, cc, rp + xp, o.xp, o.yp, L.f[7], L.g[7]);
+  pull_load<8, 6, XLO, YHI, T>(fin, gin, plane, cc, rp + xm, o.xm, o.yp, L.f[8], L.g[8]);
+  L.hn = hin[cc];
+}
+
+// The lattice update of one loaded cell: the wall rules on the pulled
+// values, the volumetric no-slip step with the particle sums `part`
+// supplies (called as part(act, x, y, rho, jx*, jy*, S)), the coupled
+// macroscopic solve and both collisions, then the stores.
+template <int PREC, bool OUT, class PartFn>
+__device__ __forceinline__ void update_cell(
+    const Params& P, const Hot<typename Prec<PREC>::C>& H,
+    const CellLoad<PREC>& L, typename Prec<PREC>::S* __restrict__ fout,
+    typename Prec<PREC>::S* __restrict__ gout,
+    typename Prec<PREC>::H* __restrict__ hout, size_t plane,
+    double* __restrict__ macro, int* flags, PartFn part) {
+  typedef Prec<PREC> T;
+  typedef typename T::C C;
+  typedef typename T::H HT;
+  const bool act = L.act;
+  const int cc = L.cc, x = L.x, y = L.y;
+  const Beyond o = beyond(P, x, y);
+  constexpr int XLO = VLB_FACE_XLO, XHI = VLB_FACE_XHI;
+  constexpr int YLO = VLB_FACE_YLO, YHI = VLB_FACE_YHI;
+  C f[9], g[9];
+  f[0] = T::cv(L.f[0]);
+  g[0] = T::cv(L.g[0]);
+  pull_fix<1, XLO, -1, T>(L.f[1], L.g[1], o.xm, false, H, f[1], g[1]);
+  pull_fix<2, -1, YLO, T>(L.f[2], L.g[2], false, o.ym, H, f[2], g[2]);
+  pull_fix<3, XHI, -1, T>(L.f[3], L.g[3], o.xp, false, H, f[3], g[3]);
+  pull_fix<4, -1, YHI, T>(L.f[4], L.g[4], false, o.yp, H, f[4], g[4]);
+  pull_fix<5, XLO, YLO, T>(L.f[5], L.g[5], o.xm, o.ym, H, f[5], g[5]);
+  pull_fix<6, XHI, YLO, T>(L.f[6], L.g[6], o.xp, o.ym, H, f[6], g[6]);
+  pull_fix<7, XHI, YHI, T>(L.f[7], L.g[7], o.xp, o.yp, H, f[7], g[7]);
+  pull_fix<8, XLO, YHI, T>(L.f[8], L.g[8], o.xm, o.yp, H, f[8], g[8]);
+  const HT hn = L.hn;
 
   // ---- moments of the deviations f* - w rho_0; the reference adds
   // rho_0 (1, -2, 1, 0, ..., 0) to M f*
@@ -1058,6 +1120,30 @@ __device__ __forceinline__ bool lattice_tile(
     macro[4 * N + cc] = (double)fs;
     macro[5 * N + cc] = (double)dfs;
   }
+}
+
+// The lattice update of the 256 cells of one tile.  Every thread of the
+// block calls pre() before it issues its loads, gather() right after (so
+// that its work overlaps them; a true result, which must be uniform over
+// the wave, abandons the tile: the return value is then false), and part()
+// as update_cell describes.
+template <int PREC, bool OUT, class PreFn, class GatherFn, class PartFn>
+__device__ __forceinline__ bool lattice_tile(
+    const Params& P, const Hot<typename Prec<PREC>::C>& H,
+    const typename Prec<PREC>::S* __restrict__ fin,
+    typename Prec<PREC>::S* __restrict__ fout,
+    const typename Prec<PREC>::S* __restrict__ gin,
+    typename Prec<PREC>::S* __restrict__ gout,
+    const typename Prec<PREC>::H* __restrict__ hin,
+    typename Prec<PREC>::H* __restrict__ hout, size_t plane, int tile,
+    double* __restrict__ macro, int* flags, PreFn pre, GatherFn gather,
+    PartFn part) {
+  CellLoad<PREC> L;
+  pre();
+  load_cell<PREC>(P, fin, gin, hin, plane, tile, L);
+  if (gather()) return false;
+  update_cell<PREC, OUT>(P, H, L, fout, gout, hout, plane, macro, flags,
+                         part);
   return true;
 }
 
@@ -1091,6 +1177,17 @@ __device__ __forceinline__ int stream_tile(const Params& P, int k) {
   const int x = k & 7, j = k >> 3;
   const int gi = j / P.xcd_group, o = j - gi * P.xcd_group;
   return (gi * 8 + x) * P.xcd_group + o;
+}
+
+// The 16-bit forms can stream two tiles per block (pair_task), where the
+// host has set P.pair_tiles.
+template <int PREC>
+constexpr bool kPairedTiles = PREC == VLB_FP16_SHIFT || PREC == VLB_BF16_SHIFT;
+
+// Streaming blocks of one step: one per tile of the XCD-ordered sequence,
+// or one per pair (k, k + 8) of it.
+__host__ __device__ inline int stream_grid(const Params& P, bool pair) {
+  return pair ? (P.stream_blocks + 15) / 16 * 8 : P.stream_blocks;
 }
 
 // LDS of a particle tile: the staged particles, the per-cell particle sums
@@ -1314,6 +1411,65 @@ __device__ __forceinline__ void step_task(
       }
     }
   }
+}
+
+// Two plain tiles per block (the 16-bit forms): each lane issues the loads
+// of its cell in both tiles before it computes either.  The 16-bit forms
+// move half the FP32 bytes per cell with the same arithmetic; with one cell
+// per lane a wave has too few bytes in flight to cover the memory latency,
+// with two it has as many as an FP32 wave.  tB may lie past the last tile
+// (its lanes then only load a valid cell).  Scan form: a tile a particle
+// reaches is left to the particle group, as in step_task.
+template <int PREC, bool OUT, bool SCAN>
+__device__ __forceinline__ void pair_task(
+    const Params& P, const Hot<typename Prec<PREC>::C>& H, const StepBufs& B,
+    int tA, int tB) {
+  typedef typename Prec<PREC>::C C;
+  typedef typename Prec<PREC>::S S;
+  typedef typename Prec<PREC>::H HT;
+  const S* __restrict__ fin = (const S*)B.fi;
+  S* __restrict__ fout = (S*)B.fo;
+  const S* __restrict__ gin = (const S*)B.gi;
+  S* __restrict__ gout = (S*)B.go;
+  const HT* __restrict__ hin = (const HT*)B.hin;
+  HT* __restrict__ hout = (HT*)B.hout;
+  const size_t plane = B.plane;
+  double* __restrict__ macro = B.macro;
+  int* flags = B.flags;
+  const int lane = threadIdx.x & 63;
+  const bool probe = SCAN && lane < P.np;
+  double X = 0.0, Y = 0.0, Ux = 0.0, Uy = 0.0, R = 0.0;
+  if (probe) {
+    X = B.cur.X[lane];
+    Y = B.cur.Y[lane];
+    Ux = B.cur.Ux[lane];
+    Uy = B.cur.Uy[lane];
+    R = B.pc.R[lane];
+  }
+  CellLoad<PREC> a, b;
+  load_cell<PREC>(P, fin, gin, hin, plane, tA, a);
+  load_cell<PREC>(P, fin, gin, hin, plane, tB, b);
+  bool skipA = false, skipB = tB >= P.nblocks;
+  if (SCAN) {
+    bool ha = false, hb = false;
+    if (probe) {
+      advance_position(P, X, Y, Ux, Uy);
+      const BlockRanges r = block_ranges(P, X, Y, R, kBlock);
+      ha = r.contains(tA);
+      hb = r.contains(tB);
+      // a centre the band-box logic cannot place: no tile serves it
+      if (r.n == 0 && (tA == 0 || tB == 0)) atomicOr(flags, kFlagUnstable);
+    }
+    skipA = __ballot(ha) != 0ull;
+    skipB = skipB || __ballot(hb) != 0ull;
+  }
+  auto none = [](bool, int, int, C, C, C, PSums<C>&) {};
+  if (!skipA)
+    update_cell<PREC, OUT>(P, H, a, fout, gout, hout, plane, macro, flags,
+                           none);
+  if (!skipB)
+    update_cell<PREC, OUT>(P, H, b, fout, gout, hout, plane, macro, flags,
+                           none);
 }
 
 static inline unsigned blocks_for(long n, int per) {

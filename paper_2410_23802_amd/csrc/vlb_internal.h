@@ -54,6 +54,8 @@ struct Params {
                       // (scan form: np * maxr rounded up to 8; else 0)
   int xcd_group;      // step kernel: consecutive tiles per XCD group
   int stream_blocks;  // step kernel: blocks of the streaming group
+  int pair_tiles;     // step kernel, 16-bit forms: two plain tiles per
+                      // streaming block (never in the list form)
 };
 
 // The constants the per-cell arithmetic uses, in the compute precision C

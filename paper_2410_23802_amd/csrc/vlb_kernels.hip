@@ -11,8 +11,10 @@ namespace vlb {
 // of the particle role spills a little).  The 32-bit forms are held to 5
 // waves (96 VGPRs, no added spill): 4-7 % faster on the channel than the
 // unconstrained 4 waves; at 6 the particle role spills and loses it again
-// (and the LDS of a particle tile caps a CU at 7 blocks).
-template <int PREC, bool OUT, bool SCAN>
+// (and the LDS of a particle tile caps a CU at 7 blocks).  PAIR (16-bit
+// forms, where the host sets pair_tiles): the streaming blocks take two
+// tiles each; a kernel of its own, so that the one-tile path keeps its code.
+template <int PREC, bool OUT, bool SCAN, bool PAIR>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 5))) void k_step(
     const Params P, const Hot<typename Prec<PREC>::C> H, const StepBufs B,
@@ -25,6 +27,16 @@ __attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 5))) void k_step(
     tile = scan_task_tile(P, B.cur, B.pc, blockIdx.x);  // uniform in the block
     if (tile < 0) return;
     ptile = true;
+  } else if (PAIR) {
+    // streaming block j: tiles k and k + 8 of the XCD-ordered sequence
+    // (the same XCD's band), k = 16 (j / 8) + j mod 8; never in the list
+    // form with particles
+    const int j = blockIdx.x - P.nfirst;
+    const int k = (j >> 3) * 16 + (j & 7);
+    const int tA = stream_tile(P, k), tB = stream_tile(P, k + 8);
+    if (tA >= P.nblocks) return;                         // then tB too
+    pair_task<PREC, OUT, SCAN>(P, H, B, tA, tB);
+    return;
   } else {
     tile = stream_tile(P, blockIdx.x - P.nfirst);
     if (tile >= P.nblocks) return;
@@ -372,23 +384,31 @@ hipError_t launch_particles(const Params& P, PState cur, PState next,
   return hipGetLastError();
 }
 
-template <int PREC, bool OUT, bool SCAN>
+template <int PREC, bool OUT, bool SCAN, bool PAIR>
 static hipError_t step_t(const StepLaunch& a, hipStream_t s) {
   const Params& P = *a.P;
   const Hot<typename Prec<PREC>::C> H = make_hot<typename Prec<PREC>::C>(P);
-  const unsigned grid = (unsigned)(P.nfirst + P.stream_blocks);
-  hipExtLaunchKernelGGL((k_step<PREC, OUT, SCAN>), dim3(grid), dim3(kBlock),
-                        0, s, a.ev_start, a.ev_stop, 0, P, H, a.B, a.have);
+  const unsigned grid = (unsigned)(P.nfirst + stream_grid(P, PAIR));
+  hipExtLaunchKernelGGL((k_step<PREC, OUT, SCAN, PAIR>), dim3(grid),
+                        dim3(kBlock), 0, s, a.ev_start, a.ev_stop, 0, P, H,
+                        a.B, a.have);
   return hipGetLastError();
+}
+
+template <int PREC, bool PAIR>
+static hipError_t step_q(const StepLaunch& a, hipStream_t s) {
+  if (a.P->scan)
+    return a.out ? step_t<PREC, true, true, PAIR>(a, s)
+                 : step_t<PREC, false, true, PAIR>(a, s);
+  return a.out ? step_t<PREC, true, false, PAIR>(a, s)
+               : step_t<PREC, false, false, PAIR>(a, s);
 }
 
 template <int PREC>
 static hipError_t step_p(const StepLaunch& a, hipStream_t s) {
-  if (a.P->scan)
-    return a.out ? step_t<PREC, true, true>(a, s)
-                 : step_t<PREC, false, true>(a, s);
-  return a.out ? step_t<PREC, true, false>(a, s)
-               : step_t<PREC, false, false>(a, s);
+  if constexpr (kPairedTiles<PREC>)
+    if (a.P->pair_tiles) return step_q<PREC, true>(a, s);
+  return step_q<PREC, false>(a, s);
 }
 
 hipError_t launch_step(int prec, const StepLaunch& a, hipStream_t s) {

@@ -416,6 +416,30 @@ def test_save_load_continues_bitwise(vlb):
     assert all(np.array_equal(pa[k], pb[k]) for k in pa.dtype.names)
 
 
+@pytest.mark.parametrize("prec", ["fp16s", "bf16s"])
+def test_paired_tiles_match_single_tile_path(vlb, prec):
+    """16-bit domains whose step moves more than the Infinity Cache holds
+    stream two tiles per block; the batch kernel always takes one.  Same
+    arithmetic, so the same bits: a 2000 x 1801 channel (ragged last tile,
+    an odd number of tile pairs) with a disk whose tiles the paired blocks
+    must leave to the particle group."""
+    d, ps = W.c2_channel(nx=2000, ny=1801)
+    ps[0]["x"], ps[0]["y"] = 1003.3, 1500.7
+    say(f"case: paired tiles, {prec}, {d['nx']} x {d['ny']}")
+    n = 4
+    a = vlb.Domain(d, ps, prec).init().step(n)
+    b = vlb.Batch([(d, ps)], prec).init()
+    b.set_tuning(0, 0, False)
+    b.step(n)
+    for k in ("rho", "ux", "uy", "T", "fs", "dfs"):
+        assert np.array_equal(a.field(k), b.field(0, k)), k
+    pa, pb = a.particles(), b.particles(0)
+    for k in ("x", "y", "ux", "uy", "omega", "Fx", "Fy", "Tz"):
+        assert np.array_equal(pa[k], pb[k]), k
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "bf16s"])
 def test_stream_probe_leaves_state_unchanged(vlb, prec):
     """The memory-pattern probe writes only what the next step overwrites:
