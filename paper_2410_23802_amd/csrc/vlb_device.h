@@ -1208,6 +1208,10 @@ struct TileShared {
   C share[kShareCache][kBlock];
   unsigned char slot[kShareCache][kBlock];
   unsigned char nreach[kBlock];  // particles reaching the cell (saturated)
+  // phase 1: the (cell, cache entry) pairs whose exact area is pending,
+  // packed as cell * kShareCache + entry, and the per-wave counts
+  unsigned short work[kShareCache * kBlock];
+  int wcount[kBlock / 64];
 };
 
 // One tile of one time step (a whole step is one launch of k_step, or of
@@ -1265,27 +1269,99 @@ __device__ __forceinline__ void step_task(
       scan_block(sh.bp, P, tile, cur, nxt, pc, partial_in, have, true, flags);
     else
       load_block_list(sh.bp, sh.tmp, L, tile, nxt, pc, flags);
+    // (a) which particles reach the cell (slot order), whether they cover
+    // it wholly; the first kShareCache are kept
+    const int cnt = sh.bp.cnt;
+    const double xn = (double)cx + 0.5, yn = (double)cy + 0.5;
+    int nin = 0;
+    unsigned cut = 0;                 // cache entries whose area is pending
+    for (int k = 0; k < cnt; ++k) {
+      if (!act0) break;
+      const double X = near_copy(sh.bp.X[k], xn, (double)P.nx, P.perx);
+      const double Y = near_copy(sh.bp.Y[k], yn, (double)P.ny, P.pery);
+      const double R = sh.bp.R[k];
+      if (!owns_cell(X, Y, R, cx, cy)) continue;
+      if (nin < kShareCache) {
+        sh.slot[nin][t] = (unsigned char)k;
+        if (cell_within(X, Y, R, cx, cy))
+          sh.share[nin][t] = (C)1;
+        else
+          cut |= 1u << nin;
+      }
+      ++nin;
+    }
+    // (b) the exact areas of the partly covered cells.  With one particle
+    // each lane computes its own (a wave evaluates one area at most);
+    // with more they are compacted over the block so that every lane of a
+    // wave computes one (a tile has a few dozen of them; lane by lane, a
+    // wave would evaluate one area per particle it meets).
+    if (cnt <= 1) {
+      if (cut) {
+        const int k = sh.slot[0][t];
+        const double X = near_copy(sh.bp.X[k], xn, (double)P.nx, P.perx);
+        const double Y = near_copy(sh.bp.Y[k], yn, (double)P.ny, P.pery);
+        sh.share[0][t] = (C)covered_share(X, Y, sh.bp.R[k], cx, cy);
+      }
+    } else {
+      const int mine = __popc(cut);
+      const int w = t >> 6;
+      const int below = wave_excl_scan(mine, lane);
+      if (lane == 63) sh.wcount[w] = below + mine;
+      __syncthreads();
+      int base = below, total = 0;
+      for (int v = 0; v < kBlock / 64; ++v) {
+        base += v < w ? sh.wcount[v] : 0;
+        total += sh.wcount[v];
+      }
+      for (unsigned m = cut; m; m &= m - 1)
+        sh.work[base++] = (unsigned short)(t * kShareCache + __ffs(m) - 1);
+      __syncthreads();
+      for (int q = t; q < total; q += kBlock) {
+        const int item = sh.work[q];
+        const int tt = item / kShareCache, e = item - tt * kShareCache;
+        const int c = tile * kBlock + tt;
+        const int j = c / P.nx, i = c - j * P.nx;
+        const int k = sh.slot[e][tt];
+        const double X =
+            near_copy(sh.bp.X[k], (double)i + 0.5, (double)P.nx, P.perx);
+        const double Y =
+            near_copy(sh.bp.Y[k], (double)j + 0.5, (double)P.ny, P.pery);
+        sh.share[e][tt] = (C)covered_share(X, Y, sh.bp.R[k], i, j);
+      }
+      __syncthreads();
+    }
+    // (c) the particle sums, in slot order; past the cache (more than
+    // kShareCache particles in one cell) the geometry is computed here
     PSums<C> S;
     S.S0 = S.S1x = S.S1y = S.S2xx = S.S2yy = S.S2xy = (C)0;
-    int nin = 0;
-    const int cnt = sh.bp.cnt;
-    for (int k = 0; k < cnt; ++k) {
-      SlotGeom sg;
-      if (act0 && particle_geometry(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.R[k],
-                                    sh.bp.Ux[k], sh.bp.Uy[k], sh.bp.Om[k],
-                                    cx, cy, sg)) {
-        const C a = (C)sg.fs, ux = (C)sg.usx, uy = (C)sg.usy;
-        if (nin < kShareCache) {
-          sh.slot[nin][t] = (unsigned char)k;
-          sh.share[nin][t] = a;
+    const int ncached = nin < kShareCache ? nin : kShareCache;
+    for (int e = 0; e < ncached; ++e) {
+      const int k = sh.slot[e][t];
+      double rx, ry, usx, usy;
+      particle_motion(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.Ux[k], sh.bp.Uy[k],
+                      sh.bp.Om[k], cx, cy, rx, ry, usx, usy);
+      const C a = sh.share[e][t], ux = (C)usx, uy = (C)usy;
+      S.S0 += a;
+      S.S1x += a * ux;
+      S.S1y += a * uy;
+      S.S2xx += a * ux * ux;
+      S.S2yy += a * uy * uy;
+      S.S2xy += a * ux * uy;
+    }
+    if (nin > kShareCache) {
+      for (int k = sh.slot[kShareCache - 1][t] + 1; k < cnt; ++k) {
+        SlotGeom sg;
+        if (particle_geometry(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.R[k],
+                              sh.bp.Ux[k], sh.bp.Uy[k], sh.bp.Om[k], cx, cy,
+                              sg)) {
+          const C a = (C)sg.fs, ux = (C)sg.usx, uy = (C)sg.usy;
+          S.S0 += a;
+          S.S1x += a * ux;
+          S.S1y += a * uy;
+          S.S2xx += a * ux * ux;
+          S.S2yy += a * uy * uy;
+          S.S2xy += a * ux * uy;
         }
-        ++nin;
-        S.S0 += a;
-        S.S1x += a * ux;
-        S.S1y += a * uy;
-        S.S2xx += a * ux * ux;
-        S.S2yy += a * uy * uy;
-        S.S2xy += a * ux * uy;
       }
     }
     if (act0 && nin > P.kmax) atomicOr(flags, kFlagOverlap);
