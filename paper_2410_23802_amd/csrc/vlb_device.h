@@ -535,9 +535,9 @@ struct PUpd {
   double X, Y, th, Ux, Uy, Om, Uxp, Uyp, Omp, Fx, Fy, Tz;
 };
 
-__device__ PUpd particle_update_with(const Params& P, const PState& cur,
-                                     const PConst& pc, const double* partial,
-                                     int have, int p, int lane, double cx,
+__device__ PUpd particle_update_sums(const Params& P, const PState& cur,
+                                     const PConst& pc, int p, double fx,
+                                     double fy, double tz, double cx,
                                      double cy);
 
 // One step of particle p, wave-level (every lane returns the same bits):
@@ -545,13 +545,12 @@ __device__ PUpd particle_update_with(const Params& P, const PState& cur,
 // inside-fluid correction of eq. inside.fluid by backward differences,
 // total force = hydrodynamic + (rho_s - rho_f) V g + repulsion, forward
 // Euler (Sec. 2.3 end).
-// The repulsion (cx, cy) is given.
-__device__ PUpd particle_update_with(const Params& P, const PState& cur,
-                                     const PConst& pc, const double* partial,
-                                     int have, int p, int lane, double cx,
+// The momentum-exchange sums (fx, fy, tz) and the repulsion (cx, cy) are
+// given.
+__device__ PUpd particle_update_sums(const Params& P, const PState& cur,
+                                     const PConst& pc, int p, double fx,
+                                     double fy, double tz, double cx,
                                      double cy) {
-  double fx, fy, tz;
-  reduce_partials(P, cur, pc, partial, have, p, lane, fx, fy, tz);
   PUpd u;
   const double R = pc.R[p], rs = pc.rhos[p];
   const double V = M_PI * R * R;
@@ -582,6 +581,14 @@ __device__ PUpd particle_update_with(const Params& P, const PState& cur,
   u.Fy = fy;
   u.Tz = tz;
   return u;
+}
+
+__device__ __forceinline__ PUpd particle_update_with(
+    const Params& P, const PState& cur, const PConst& pc,
+    const double* partial, int have, int p, int lane, double cx, double cy) {
+  double fx, fy, tz;
+  reduce_partials(P, cur, pc, partial, have, p, lane, fx, fy, tz);
+  return particle_update_sums(P, cur, pc, p, fx, fy, tz, cx, cy);
 }
 
 __device__ __forceinline__ PUpd particle_update(const Params& P,

@@ -131,26 +131,33 @@ __global__ __launch_bounds__(256) void k_particles(
   }
   const int lane = threadIdx.x & 63;
   const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const bool mine = p < P.np;          // uniform in the wave
 
-  // Repulsion of the update: the block stages the particles 256 at a time
-  // in LDS for its four waves (one load per particle per block instead of
-  // one dependent load per particle per wave); each lane still visits
-  // q = lane, lane + 64, ... in ascending order, as repulsion() does.
+  // The momentum-exchange sums first, so that their loads are in flight
+  // while the repulsion is computed.
+  double fx = 0.0, fy = 0.0, tz = 0.0;
+  if (mine && mode != kModeBinOnly)
+    reduce_partials(P, cur, pc, partial, have_partials, p, lane, fx, fy, tz);
+
+  // Repulsion of the update: the block stages up to kStage particles at a
+  // time in LDS for its four waves, all loads of a chunk issued together
+  // (one load per particle per block instead of one dependent load per
+  // particle per wave); each lane still visits q = lane, lane + 64, ... in
+  // ascending order, as repulsion() does.
   double cx = 0.0, cy = 0.0;
   if (mode == kModeUpdate && P.coll_range > 0.0) {   // uniform in the grid
-    __shared__ double sX[256], sY[256], sR[256];
-    const bool mine = p < P.np;
+    constexpr int kStage = 2048;
+    __shared__ double sX[kStage], sY[kStage], sR[kStage];
     const double Xp = mine ? cur.X[p] : 0.0, Yp = mine ? cur.Y[p] : 0.0;
     const double Rp = mine ? pc.R[p] : 0.0;
-    for (int c0 = 0; c0 < P.np; c0 += 256) {
-      const int q = c0 + (int)threadIdx.x;
-      if (q < P.np) {
-        sX[threadIdx.x] = cur.X[q];
-        sY[threadIdx.x] = cur.Y[q];
-        sR[threadIdx.x] = pc.R[q];
+    for (int c0 = 0; c0 < P.np; c0 += kStage) {
+      const int m1 = min(kStage, P.np - c0);
+      for (int m = (int)threadIdx.x; m < m1; m += (int)blockDim.x) {
+        sX[m] = cur.X[c0 + m];
+        sY[m] = cur.Y[c0 + m];
+        sR[m] = pc.R[c0 + m];
       }
       __syncthreads();
-      const int m1 = min(256, P.np - c0);
       if (mine) {
         for (int m = lane; m < m1; m += 64) {
           if (c0 + m == p) continue;
@@ -165,11 +172,9 @@ __global__ __launch_bounds__(256) void k_particles(
       repulsion_walls(P, Xp, Yp, Rp, cx, cy);
     }
   }
-  if (p >= P.np) return;  // whole wave
+  if (!mine) return;  // whole wave
 
   if (mode == kModeReduceOnly) {
-    double fx, fy, tz;
-    reduce_partials(P, cur, pc, partial, have_partials, p, lane, fx, fy, tz);
     if (lane == 0) {
       cur.Fx[p] = fx;
       cur.Fy[p] = fy;
@@ -179,8 +184,7 @@ __global__ __launch_bounds__(256) void k_particles(
   }
   double nX = cur.X[p], nY = cur.Y[p];
   if (mode == kModeUpdate) {
-    const PUpd u = particle_update_with(P, cur, pc, partial, have_partials,
-                                        p, lane, cx, cy);
+    const PUpd u = particle_update_sums(P, cur, pc, p, fx, fy, tz, cx, cy);
     if (lane == 0) store_particle(next, p, u);
     nX = u.X;
     nY = u.Y;

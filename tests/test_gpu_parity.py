@@ -221,6 +221,27 @@ def test_many_particles_list_form_fp64(vlb, oracle_mod):
     check(e, 120, twin=twin_errors(oracle_mod, d, ps, 120, o, pkeys=keys))
 
 
+def test_particle_pass_more_than_one_staging_chunk_fp64(vlb, oracle_mod):
+    """2100 small moving disks, close enough to collide: the particle pass
+    stages 2048 particles at a time for the repulsion, so this takes two
+    chunks; against the oracle."""
+    rng = np.random.default_rng(12)
+    d = W.walls(W.domain(1200, 600, tau_f=0.7, lambda_f=0.05, R_lambda=3.0,
+                         R_cv=1.5, gravity=(0.0, -4e-5), beta=0.1,
+                         init_T=1.0, coll_range=2.0, coll_stiff_pp=2e-3,
+                         coll_stiff_pw=4e-3), thermal="adiabatic")
+    pts = W.rsa_disks(2100, 2.5, (0.0, 0.0, 1200.0, 600.0), 1.0, seed=6)
+    ps = [W.particle(x, y, 2.5, rho_s=rng.uniform(1.2, 2.0), T_init=0.3,
+                     ux=rng.uniform(-0.01, 0.01), uy=rng.uniform(-0.01, 0.01))
+          for x, y in pts]
+    say("case: 2100 particles list form fp64 6 steps")
+    g, o = run_pair(vlb, oracle_mod, d, ps, 6)
+    e = field_errors(g, o)
+    keys = ("x", "y", "ux", "uy", "omega", "Fx", "Fy", "Tz")
+    e.update(particle_errors(g, o, keys))
+    check(e, 6, twin=twin_errors(oracle_mod, d, ps, 6, o, pkeys=keys))
+
+
 def test_walls_dirichlet_channel_fp64(vlb, oracle_mod):
     """Scaled-down channel: walls on all sides at T = 1, one cold heavy disk
     released near the top, gravity and buoyancy, collisions with walls."""
