@@ -1385,7 +1385,10 @@ __device__ __forceinline__ void step_task(
   }
 
   // ---- phase 2: the lattice update
-  const bool probe = SCAN && !ptile && lane < P.np;
+  // scan form, plain tiles: wave 0 tests whether a particle reaches the
+  // tile (one particle per lane) and shares the answer through LDS; the
+  // test is issued after the population loads, so it hides behind them
+  const bool probe = SCAN && !ptile && t < P.np;
   double X = 0.0, Y = 0.0, Ux = 0.0, Uy = 0.0, R = 0.0;
   auto pre = [&] {
     if (probe) {
@@ -1398,15 +1401,20 @@ __device__ __forceinline__ void step_task(
   };
   auto gather = [&]() -> bool {
     if (!SCAN || ptile) return false;
-    bool hit = false;
-    if (probe) {
-      advance_position(P, X, Y, Ux, Uy);
-      const BlockRanges r = block_ranges(P, X, Y, R, kBlock);
-      hit = r.contains(tile);
-      // a centre the band-box logic cannot place: no tile serves it
-      if (r.n == 0 && tile == 0) atomicOr(flags, kFlagUnstable);
+    if (t < 64) {
+      bool hit = false;
+      if (probe) {
+        advance_position(P, X, Y, Ux, Uy);
+        const BlockRanges r = block_ranges(P, X, Y, R, kBlock);
+        hit = r.contains(tile);
+        // a centre the band-box logic cannot place: no tile serves it
+        if (r.n == 0 && tile == 0) atomicOr(flags, kFlagUnstable);
+      }
+      const bool any = __ballot(hit) != 0ull;
+      if (t == 0) sh.tmp[0] = any ? 1 : 0;
     }
-    return __ballot(hit) != 0ull;   // a particle tile: the first group's
+    __syncthreads();
+    return sh.tmp[0] != 0;   // a particle tile: the first group's
   };
   auto part = [&](bool, int, int, C rho, C jxs, C jys, PSums<C>& S) {
     if (ptile) {
