@@ -67,7 +67,7 @@ static void free_particles(vlb_ctx* c) {
 
 static hipError_t clear_lists(vlb_ctx* c) {
   c->lpar = 0;
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 3; ++k) {
     hipError_t e = hipMemsetAsync(c->blk_cnt[k], 0,
                                   c->P.nblocks * sizeof(int), c->stream);
     if (e != hipSuccess) return e;
@@ -203,19 +203,26 @@ static void derive_params(vlb_ctx* c) {
 static Lists lists(vlb_ctx* c) {
   Lists L;
   L.cnt = c->blk_cnt[c->lpar];
-  L.ent = c->blk_ent;
+  L.ent = c->blk_ent[c->lpar];
   L.clr = nullptr;
+  L.ocnt = nullptr;
+  L.oent = nullptr;
   return L;
 }
 
-// Lists for a particle pass that bins: it fills the zeroed buffer and clears
-// the current one; the filled buffer becomes current.
+// Lists for a particle pass that bins: it reads the current lists (the
+// band boxes of the positions it starts from), fills the next buffer (zero)
+// and clears the one after (stale since the pass before); the filled buffer
+// becomes current.
 static Lists bin_lists(vlb_ctx* c) {
+  const int nxt = (c->lpar + 1) % 3, stale = (c->lpar + 2) % 3;
   Lists L;
-  L.cnt = c->blk_cnt[1 - c->lpar];
-  L.ent = c->blk_ent;
-  L.clr = c->blk_cnt[c->lpar];
-  c->lpar ^= 1;
+  L.cnt = c->blk_cnt[nxt];
+  L.ent = c->blk_ent[nxt];
+  L.clr = c->blk_cnt[stale];
+  L.ocnt = c->blk_cnt[c->lpar];
+  L.oent = c->blk_ent[c->lpar];
+  c->lpar = nxt;
   return L;
 }
 
@@ -281,10 +288,11 @@ vlb_status vlb_create(const vlb_domain_desc* desc, void* hip_stream,
   ok = ok && dalloc(c, &c->h[0], N * c->h_elem);
   ok = ok && dalloc(c, &c->h[1], N * c->h_elem);
   ok = ok && dalloc(c, (void**)&c->macro, 6 * N * sizeof(double));
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < 3; ++k) {
     ok = ok && dalloc(c, (void**)&c->blk_cnt[k], c->P.nblocks * sizeof(int));
-  ok = ok && dalloc(c, (void**)&c->blk_ent,
-                    (size_t)c->P.nblocks * kListCap * sizeof(int2));
+    ok = ok && dalloc(c, (void**)&c->blk_ent[k],
+                      (size_t)c->P.nblocks * kListCap * sizeof(int2));
+  }
   ok = ok && dalloc(c, (void**)&c->flags, 4 * sizeof(int));
   if (ok && hipHostMalloc((void**)&c->flags_host, 4 * sizeof(int),
                           hipHostMallocDefault) != hipSuccess)
@@ -327,6 +335,7 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
   c->np = n;
   // band rows of a particle <= 2R + 4; each row touches <= 4 blocks
   c->maxb = 4 * (2 * (int)ceil(rmax) + 5);
+  c->P.rmax = rmax;
   c->P.np = n;
   c->P.maxb = c->maxb;
   // scan form for few particles: partials [particle][tile] must stay small
@@ -686,6 +695,10 @@ vlb_status vlb_load(vlb_ctx* c, const void* buf, size_t len) {
   }
   HIP_TRY(c, clear_lists(c));
   HIP_TRY(c, hipMemsetAsync(c->flags, 0, 4 * sizeof(int), c->stream));
+  if (c->np > 0 && !c->P.scan)   // the lists of the restored positions
+    HIP_TRY(c, launch_particles(c->P, c->ps[0], c->ps[0], c->pc, bin_lists(c),
+                                c->partial[0], 0, kModeBinOnly, c->flags,
+                                c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->have_partials = hd.have_partials;
   c->step = hd.step;
@@ -762,9 +775,10 @@ void vlb_destroy(vlb_ctx* c) {
   for (int k = 0; k < 2; ++k)
     if (c->h[k]) (void)hipFree(c->h[k]);
   if (c->macro) (void)hipFree(c->macro);
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < 3; ++k) {
     if (c->blk_cnt[k]) (void)hipFree(c->blk_cnt[k]);
-  if (c->blk_ent) (void)hipFree(c->blk_ent);
+    if (c->blk_ent[k]) (void)hipFree(c->blk_ent[k]);
+  }
   if (c->flags) (void)hipFree(c->flags);
   if (c->flags_host) (void)hipHostFree(c->flags_host);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);

@@ -19,9 +19,11 @@ struct vlb_ctx {
   void* h[2] = {nullptr, nullptr};   // [df_s/dt] carrier, alternating
   int cur = 0;                       // f[cur], g[cur], h[cur]: step n
   double* macro = nullptr;
-  int* blk_cnt[2] = {nullptr, nullptr};  // block counts, double buffered
-  int lpar = 0;                          // blk_cnt[lpar]: the current lists
-  int2* blk_ent = nullptr;
+  // block lists, three in turn: the current ones, those a binning pass
+  // fills, and the stale ones it clears
+  int* blk_cnt[3] = {nullptr, nullptr, nullptr};
+  int2* blk_ent[3] = {nullptr, nullptr, nullptr};
+  int lpar = 0;                          // [lpar]: the current lists
   // particles
   int np = 0;
   int maxb = 0;

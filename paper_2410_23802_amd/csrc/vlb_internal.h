@@ -45,6 +45,7 @@ struct Params {
   double fshift[9], gshift[9];
   // particles
   double rho_f, grav_x, grav_y;
+  double rmax;        // largest particle radius
   double coll_range, coll_pp, coll_pw;
   int wall_face[4];   // 1 where the face is a wall (collisions)
   int np, maxb;
@@ -111,6 +112,10 @@ struct Lists {
   int* cnt;     // [nblocks]
   int2* ent;    // [nblocks][kListCap] (particle id, partial slot)
   int* clr;     // [nblocks] or null: counts to reset to zero
+  // or null: the lists of the particle state the pass reads (its
+  // positions' band boxes), for the neighbour search of the repulsion
+  const int* ocnt;
+  const int2* oent;
 };
 
 // The buffers one lattice step of one domain reads and writes (device

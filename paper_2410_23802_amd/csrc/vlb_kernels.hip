@@ -139,32 +139,81 @@ __global__ __launch_bounds__(256) void k_particles(
   if (mine && mode != kModeBinOnly)
     reduce_partials(P, cur, pc, partial, have_partials, p, lane, fx, fy, tz);
 
-  // Repulsion of the update: the block stages up to kStage particles at a
-  // time in LDS for its four waves, all loads of a chunk issued together
-  // (one load per particle per block instead of one dependent load per
-  // particle per wave); each lane still visits q = lane, lane + 64, ... in
-  // ascending order, as repulsion() does.
+  // Repulsion of the update.  The candidates of particle p are the
+  // particles listed in the tiles of the box of half-width R_p + rmax +
+  // zeta around its centre, in the lists of the positions the pass starts
+  // from: a particle within reach (d < R_p + R_q + zeta) has its centre
+  // cell in that box, and a particle's band box holds its centre cell.  The
+  // wave marks them in a bitmap; each lane then visits q = lane, lane + 64,
+  // ... in ascending order, as repulsion() does over all particles, and
+  // calls the pair law for marked ones only -- the others are out of reach
+  // and add nothing, so the sums are those of the all-pairs loop.  Without
+  // those lists (or with more particles than the bitmap holds) the block
+  // stages all particles in LDS, kStage at a time.
   double cx = 0.0, cy = 0.0;
   if (mode == kModeUpdate && P.coll_range > 0.0) {   // uniform in the grid
-    constexpr int kStage = 2048;
-    __shared__ double sX[kStage], sY[kStage], sR[kStage];
+    constexpr int kWords = 128;                      // bitmap: 8192 particles
     const double Xp = mine ? cur.X[p] : 0.0, Yp = mine ? cur.Y[p] : 0.0;
     const double Rp = mine ? pc.R[p] : 0.0;
-    for (int c0 = 0; c0 < P.np; c0 += kStage) {
-      const int m1 = min(kStage, P.np - c0);
-      for (int m = (int)threadIdx.x; m < m1; m += (int)blockDim.x) {
-        sX[m] = cur.X[c0 + m];
-        sY[m] = cur.Y[c0 + m];
-        sR[m] = pc.R[c0 + m];
-      }
+    if (L.ocnt && P.np <= 64 * kWords) {
+      __shared__ unsigned long long marks[4][kWords];
+      const int w = threadIdx.x >> 6, nwords = (P.np + 63) >> 6;
+      for (int k = lane; k < nwords; k += 64) marks[w][k] = 0ull;
       __syncthreads();
       if (mine) {
-        for (int m = lane; m < m1; m += 64) {
-          if (c0 + m == p) continue;
-          repulsion_pair(P, Xp, Yp, Rp, sX[m], sY[m], sR[m], cx, cy);
+        int i0, i1, j0, j1;
+        band_box(P, Xp, Yp, Rp + P.rmax + P.coll_range, i0, i1, j0, j1);
+        ColSegs cs;
+        if (i1 - i0 + 1 >= P.nx) {      // the box spans the periodic axis
+          cs.n = 1; cs.lo[0] = 0; cs.hi[0] = P.nx - 1; cs.lo[1] = 0; cs.hi[1] = -1;
+        } else {
+          cs = col_segments(i0, i1, P.nx);
+        }
+        const int rows = min(j1 - j0 + 1, P.ny);
+        for (int r = lane; r < rows; r += 64) {
+          const int row = ((j0 + r) % P.ny + P.ny) % P.ny;
+          for (int sgm = 0; sgm < cs.n; ++sgm) {
+            if (cs.hi[sgm] < cs.lo[sgm]) continue;
+            const int first = (row * P.nx + cs.lo[sgm]) / kBlock;
+            const int last = (row * P.nx + cs.hi[sgm]) / kBlock;
+            for (int t = first; t <= last; ++t) {
+              const int n = min(L.ocnt[t], kListCap);
+              for (int e = 0; e < n; ++e) {
+                const int q = L.oent[(size_t)t * kListCap + e].x;
+                atomicOr(&marks[w][q >> 6], 1ull << (q & 63));
+              }
+            }
+          }
         }
       }
       __syncthreads();
+      if (mine) {
+        for (int k = 0; k < nwords; ++k) {
+          const int q = k * 64 + lane;
+          if (q < P.np && q != p && ((marks[w][k] >> lane) & 1ull))
+            repulsion_pair(P, Xp, Yp, Rp, cur.X[q], cur.Y[q], pc.R[q], cx,
+                           cy);
+        }
+      }
+    } else {
+      constexpr int kStage = 2048;
+      __shared__ double sX[kStage], sY[kStage], sR[kStage];
+      for (int c0 = 0; c0 < P.np; c0 += kStage) {
+        const int m1 = min(kStage, P.np - c0);
+        for (int m = (int)threadIdx.x; m < m1; m += (int)blockDim.x) {
+          sX[m] = cur.X[c0 + m];
+          sY[m] = cur.Y[c0 + m];
+          sR[m] = pc.R[c0 + m];
+        }
+        __syncthreads();
+        if (mine) {
+          for (int m = lane; m < m1; m += 64) {
+            if (c0 + m == p) continue;
+            repulsion_pair(P, Xp, Yp, Rp, sX[m], sY[m], sR[m], cx, cy);
+          }
+        }
+        __syncthreads();
+      }
     }
     if (mine) {
       cx = wave_sum(cx);

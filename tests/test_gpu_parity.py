@@ -486,6 +486,29 @@ def test_stream_probe_leaves_state_unchanged(vlb, prec):
     assert ei.value.status == vlb.VLB_ESTATE
 
 
+def test_save_load_continues_bitwise_list_form(vlb):
+    """80 colliding disks (list form): a restored context rebuilds the
+    block lists of its particles, which the next step's repulsion searches,
+    and continues bit for bit."""
+    d = W.walls(W.domain(160, 128, tau_f=0.65, lambda_f=0.05, R_lambda=4.0,
+                         R_cv=1.5, gravity=(0.0, -4e-5), beta=0.2,
+                         init_T=1.0, coll_range=2.0, coll_stiff_pp=2e-3,
+                         coll_stiff_pw=4e-3), thermal="adiabatic")
+    pts = W.rsa_disks(80, 5.0, (0.0, 0.0, 160.0, 128.0), 1.0, seed=5)
+    ps = [W.particle(x, y, 4.0, rho_s=1.5, T_init=0.2) for x, y in pts]
+    say("case: save/load, list form")
+    a = vlb.Domain(d, ps).init().step(23)
+    blob = a.save()
+    a.step(17)
+    b = vlb.Domain(d, ps)
+    b.load(blob)
+    b.step(17)
+    for n in ("f", "g", "T", "dfs"):
+        assert np.array_equal(a.field(n), b.field(n))
+    pa, pb = a.particles(), b.particles()
+    assert all(np.array_equal(pa[k], pb[k]) for k in pa.dtype.names)
+
+
 def test_unstable_flag(vlb):
     # a force whose square overflows: the populations become non-finite
     d = W.domain(32, 32, body_force=(1e160, 0.0))
