@@ -65,13 +65,30 @@ static void free_particles(vlb_ctx* c) {
   c->thermal4 = nullptr;
 }
 
+// Scan form: the step kernel reads per-tile particle counts (and keeps
+// them) for these storage forms; it tests its tiles directly for the others.
+static bool tile_counts_kept(const vlb_ctx* c) {
+  return c->np > 0 && c->P.scan &&
+         counted_tiles(c->prec, c->P.pair_tiles != 0);
+}
+
+// Zero the block lists and the scan form's tile counts; in the scan form,
+// count the tiles the particles of the stored state reach at the next step
+// (the step kernel keeps the counts from then on).
 static hipError_t clear_lists(vlb_ctx* c) {
   c->lpar = 0;
+  c->tpar = 0;
   for (int k = 0; k < 3; ++k) {
     hipError_t e = hipMemsetAsync(c->blk_cnt[k], 0,
                                   c->P.nblocks * sizeof(int), c->stream);
+    if (e == hipSuccess)
+      e = hipMemsetAsync(c->tcount[k], 0, c->P.nblocks * sizeof(int),
+                         c->stream);
     if (e != hipSuccess) return e;
   }
+  if (tile_counts_kept(c))
+    return launch_tile_counts(c->P, c->ps[c->pcur], c->pc, c->tcount[0],
+                              c->flags, c->stream);
   return hipSuccess;
 }
 
@@ -244,6 +261,10 @@ StepBufs vlb::context_step_bufs(vlb_ctx* c) {
   B.partial_out = c->partial[1 - c->pp];
   B.macro = c->macro;
   B.flags = c->flags;
+  const bool counted = tile_counts_kept(c);
+  B.tcount = counted ? c->tcount[c->tpar] : nullptr;
+  B.tcount_next = counted ? c->tcount[(c->tpar + 1) % 3] : nullptr;
+  B.tcount_clear = counted ? c->tcount[(c->tpar + 2) % 3] : nullptr;
   return B;
 }
 
@@ -257,6 +278,7 @@ void vlb::context_advance(vlb_ctx* c, int64_t n) {
     c->pp ^= flip;
   }
   c->cur ^= flip;
+  c->tpar = (int)((c->tpar + n) % 3);
   c->step += n;
 }
 
@@ -289,6 +311,7 @@ vlb_status vlb_create(const vlb_domain_desc* desc, void* hip_stream,
   ok = ok && dalloc(c, &c->h[1], N * c->h_elem);
   ok = ok && dalloc(c, (void**)&c->macro, 6 * N * sizeof(double));
   for (int k = 0; k < 3; ++k) {
+    ok = ok && dalloc(c, (void**)&c->tcount[k], c->P.nblocks * sizeof(int));
     ok = ok && dalloc(c, (void**)&c->blk_cnt[k], c->P.nblocks * sizeof(int));
     ok = ok && dalloc(c, (void**)&c->blk_ent[k],
                       (size_t)c->P.nblocks * kListCap * sizeof(int2));
@@ -776,6 +799,7 @@ void vlb_destroy(vlb_ctx* c) {
     if (c->h[k]) (void)hipFree(c->h[k]);
   if (c->macro) (void)hipFree(c->macro);
   for (int k = 0; k < 3; ++k) {
+    if (c->tcount[k]) (void)hipFree(c->tcount[k]);
     if (c->blk_cnt[k]) (void)hipFree(c->blk_cnt[k]);
     if (c->blk_ent[k]) (void)hipFree(c->blk_ent[k]);
   }

@@ -316,7 +316,13 @@ vlb_status vlb_batch_create(int32_t ncases, const vlb_domain_desc* descs,
     hc[i].Hf = make_hot<float>(c->P);
     for (int p = 0; p < 2; ++p) {
       c->cur = c->pcur = c->pp = p;
-      hc[i].B[p] = to_offsets(context_step_bufs(c), (const char*)b->dcases);
+      StepBufs sb = context_step_bufs(c);
+      // the tile counts go round three buffers, which a two-step table
+      // cannot follow: batch tasks test their tiles directly
+      sb.tcount = nullptr;
+      sb.tcount_next = nullptr;
+      sb.tcount_clear = nullptr;
+      hc[i].B[p] = to_offsets(sb, (const char*)b->dcases);
     }
     c->cur = c->pcur = c->pp = 0;
   }

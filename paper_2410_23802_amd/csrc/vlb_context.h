@@ -24,6 +24,10 @@ struct vlb_ctx {
   int* blk_cnt[3] = {nullptr, nullptr, nullptr};
   int2* blk_ent[3] = {nullptr, nullptr, nullptr};
   int lpar = 0;                          // [lpar]: the current lists
+  // scan form: particles reaching each tile, three in turn (the next
+  // step's, the one after, a stale one being cleared)
+  int* tcount[3] = {nullptr, nullptr, nullptr};
+  int tpar = 0;                          // [tpar]: the next step's counts
   // particles
   int np = 0;
   int maxb = 0;

@@ -692,7 +692,7 @@ __device__ __forceinline__ bool slot_geometry(const BlockParticles& bp, int s,
 __device__ void scan_block(BlockParticles& bp, const Params& P, int b,
                            PState cur, PState next, PConst pc,
                            const double* partial, int have, bool advance,
-                           int* flags) {
+                           int* flags, int* tcount_next = nullptr) {
   __shared__ int s_nwork;
   __shared__ int s_work_pid[64], s_work_rank[64], s_work_store[64];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -744,6 +744,17 @@ __device__ void scan_block(BlockParticles& bp, const Params& P, int b,
           bp.Om[r] = u.Om;
         }
         if (s_work_store[k]) store_particle(next, p, u);
+      }
+      if (tcount_next && s_work_store[k]) {
+        // the tiles the particle reaches at the next step's position (the
+        // same arithmetic as that step's scan_task_tile)
+        double Xn = u.X, Yn = u.Y;
+        advance_position(P, Xn, Yn, u.Ux, u.Uy);
+        const BlockRanges r = block_ranges(P, Xn, Yn, pc.R[p], kBlock);
+        for (int j = lane; j < r.count(); j += 64)
+          atomicAdd(&tcount_next[r.at(j)], 1);
+        // a centre the band-box logic cannot place: no tile serves it
+        if (r.n == 0 && lane == 0) atomicOr(flags, kFlagUnstable);
       }
     } else if (lane == 0 && r >= 0) {
       bp.Ux[r] = cur.Ux[p];
@@ -1236,10 +1247,12 @@ struct TileShared {
 // Scan form: the first np * maxr blocks (tasks) take the particle tiles (so
 // their longer dependency chain starts first and overlaps the streaming of
 // the rest); the following ones take every tile and leave those some
-// particle reaches (same advanced positions and band boxes; one particle
-// per lane) to the first group.  List form: each tile in the role its block
-// count gives.
-template <int PREC, bool OUT, bool SCAN>
+// particle reaches to the first group.  COUNTED (one domain): they know
+// those tiles from per-tile counts that the previous step's particle
+// blocks filled (the same advanced positions and band boxes); otherwise
+// (a batch) they test them, one particle per lane.  List form: each tile
+// in the role its block count gives.
+template <int PREC, bool OUT, bool SCAN, bool COUNTED = false>
 __device__ __forceinline__ void step_task(
     const Params& P, const Hot<typename Prec<PREC>::C>& H, const StepBufs& B,
     int have, int tile, bool ptile, TileShared<typename Prec<PREC>::C>& sh) {
@@ -1273,7 +1286,8 @@ __device__ __forceinline__ void step_task(
   // sum to one
   if (ptile) {
     if (SCAN)
-      scan_block(sh.bp, P, tile, cur, nxt, pc, partial_in, have, true, flags);
+      scan_block(sh.bp, P, tile, cur, nxt, pc, partial_in, have, true, flags,
+                 B.tcount_next);
     else
       load_block_list(sh.bp, sh.tmp, L, tile, nxt, pc, flags);
     // (a) which particles reach the cell (slot order), whether they cover
@@ -1385,12 +1399,16 @@ __device__ __forceinline__ void step_task(
   }
 
   // ---- phase 2: the lattice update
-  // scan form, plain tiles: wave 0 tests whether a particle reaches the
-  // tile (one particle per lane) and shares the answer through LDS; the
-  // test is issued after the population loads, so it hides behind them
-  const bool probe = SCAN && !ptile && t < P.np;
+  // scan form, plain tiles: is the tile a particle tile (the first group's)?
+  // COUNTED: the count the previous step left for it (and this block clears
+  // the tile's stale count).  Otherwise wave 0 tests it (one particle per
+  // lane) and shares the answer through LDS; the test is issued after the
+  // population loads, so it hides behind them.
+  const bool counted = COUNTED && SCAN && !ptile;
+  const bool probe = !COUNTED && SCAN && !ptile && t < P.np;
   double X = 0.0, Y = 0.0, Ux = 0.0, Uy = 0.0, R = 0.0;
   auto pre = [&] {
+    if (counted && t == 0) B.tcount_clear[tile] = 0;
     if (probe) {
       X = cur.X[lane];
       Y = cur.Y[lane];
@@ -1401,6 +1419,9 @@ __device__ __forceinline__ void step_task(
   };
   auto gather = [&]() -> bool {
     if (!SCAN || ptile) return false;
+    // read after the population loads are issued (a scalar load, whose
+    // wait would otherwise hold them back)
+    if (counted) return B.tcount[tile] != 0;
     if (t < 64) {
       bool hit = false;
       if (probe) {
@@ -1510,8 +1531,9 @@ __device__ __forceinline__ void step_task(
 // per lane a wave has too few bytes in flight to cover the memory latency,
 // with two it has as many as an FP32 wave.  tB may lie past the last tile
 // (its lanes then only load a valid cell).  Scan form: a tile a particle
-// reaches is left to the particle group, as in step_task.
-template <int PREC, bool OUT, bool SCAN>
+// reaches is left to the particle group, as in step_task (COUNTED as
+// there).
+template <int PREC, bool OUT, bool SCAN, bool COUNTED = false>
 __device__ __forceinline__ void pair_task(
     const Params& P, const Hot<typename Prec<PREC>::C>& H, const StepBufs& B,
     int tA, int tB) {
@@ -1528,8 +1550,13 @@ __device__ __forceinline__ void pair_task(
   double* __restrict__ macro = B.macro;
   int* flags = B.flags;
   const int lane = threadIdx.x & 63;
-  const bool probe = SCAN && lane < P.np;
+  const bool counted = COUNTED && SCAN;
+  const bool probe = !COUNTED && SCAN && lane < P.np;
   double X = 0.0, Y = 0.0, Ux = 0.0, Uy = 0.0, R = 0.0;
+  if (counted && threadIdx.x == 0) {
+    B.tcount_clear[tA] = 0;
+    if (tB < P.nblocks) B.tcount_clear[tB] = 0;
+  }
   if (probe) {
     X = B.cur.X[lane];
     Y = B.cur.Y[lane];
@@ -1541,7 +1568,10 @@ __device__ __forceinline__ void pair_task(
   load_cell<PREC>(P, fin, gin, hin, plane, tA, a);
   load_cell<PREC>(P, fin, gin, hin, plane, tB, b);
   bool skipA = false, skipB = tB >= P.nblocks;
-  if (SCAN) {
+  if (counted) {   // read after the loads, as in step_task
+    skipA = B.tcount[tA] != 0;
+    skipB = skipB || B.tcount[tB] != 0;
+  } else if (SCAN) {
     bool ha = false, hb = false;
     if (probe) {
       advance_position(P, X, Y, Ux, Uy);

@@ -108,6 +108,15 @@ struct PConst {
 // buffered: the particle pass fills `cnt` (all zero on entry) and clears
 // `clr`, the counts of the previous step, which both lattice kernels of
 // that step have finished reading.
+// Scan form: whether the step kernel finds its particle tiles from the
+// per-tile counts (FP64, and the paired 16-bit tiles) or tests them in its
+// streaming blocks (FP32 and the unpaired 16-bit forms, 3-6 % faster that
+// way on a 0.8 M-cell channel, where their particle blocks' chain is as
+// long as the streaming).  The host keeps the counts for the same cases.
+__host__ __device__ constexpr bool counted_tiles(int prec, bool pair) {
+  return prec == VLB_FP64 || pair;
+}
+
 struct Lists {
   int* cnt;     // [nblocks]
   int2* ent;    // [nblocks][kListCap] (particle id, partial slot)
@@ -136,6 +145,13 @@ struct StepBufs {
   double* partial_out;
   double* macro;
   int* flags;
+  // scan form of one domain (null otherwise): per tile, the number of
+  // particles whose band box reaches it at this step's positions (read), at
+  // the next step's (filled by the blocks that store the particles' new
+  // state) and a stale buffer (cleared, one entry per tile)
+  const int* tcount;
+  int* tcount_next;
+  int* tcount_clear;
 };
 
 // Arguments of one launch of the step kernel.  ev_start/ev_stop (may be
@@ -183,6 +199,9 @@ hipError_t launch_gather_flags(const BatchCase* cases, char* arena, int n,
 hipError_t launch_init(int prec, const Params& P, void* f, void* g, void* h,
                        size_t plane, PState pn, PConst pc, Lists L,
                        double* macro, int* flags, hipStream_t s);
+// Scan form: count[tile] += the particles reaching it at the next step.
+hipError_t launch_tile_counts(const Params& P, PState cur, PConst pc,
+                              int* count, int* flags, hipStream_t s);
 hipError_t launch_particle_sums(const Params& P, PState ps, PConst pc,
                                 const double* macro, double* out4,
                                 hipStream_t s);

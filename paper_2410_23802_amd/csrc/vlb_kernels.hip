@@ -35,14 +35,16 @@ __attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 5))) void k_step(
     const int k = (j >> 3) * 16 + (j & 7);
     const int tA = stream_tile(P, k), tB = stream_tile(P, k + 8);
     if (tA >= P.nblocks) return;                         // then tB too
-    pair_task<PREC, OUT, SCAN>(P, H, B, tA, tB);
+    pair_task<PREC, OUT, SCAN, SCAN && counted_tiles(PREC, PAIR)>(P, H, B,
+                                                                  tA, tB);
     return;
   } else {
     tile = stream_tile(P, blockIdx.x - P.nfirst);
     if (tile >= P.nblocks) return;
     ptile = !SCAN && P.np > 0 && B.L.cnt[tile] != 0;    // uniform in the block
   }
-  step_task<PREC, OUT, SCAN>(P, H, B, have, tile, ptile, sh);
+  step_task<PREC, OUT, SCAN, SCAN && counted_tiles(PREC, PAIR)>(
+      P, H, B, have, tile, ptile, sh);
 }
 
 // -------------------------------------------------------------------------
@@ -278,6 +280,23 @@ __global__ __launch_bounds__(256) void k_particles(
   }
 }
 
+// Scan form: per tile, the particles whose band box reaches it at the next
+// step's positions (X + U of the stored state; the arithmetic of that
+// step's scan_task_tile), one wave per particle.  Afterwards the step
+// kernel keeps the counts itself.
+__global__ __launch_bounds__(256) void k_tile_counts(const Params P,
+                                                     PState cur, PConst pc,
+                                                     int* count, int* flags) {
+  const int p = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (p >= P.np) return;
+  double X = cur.X[p], Y = cur.Y[p];
+  advance_position(P, X, Y, cur.Ux[p], cur.Uy[p]);
+  const BlockRanges r = block_ranges(P, X, Y, pc.R[p], kBlock);
+  for (int j = lane; j < r.count(); j += 64) atomicAdd(&count[r.at(j)], 1);
+  // a centre the band-box logic cannot place: no tile serves it
+  if (r.n == 0 && lane == 0) atomicOr(flags, kFlagUnstable);
+}
+
 // -------------------------------------------------------------------------
 // Per-particle thermal sums over the band box, one block per particle, in a
 // fixed order: sum f_s,p, sum f_s,p T, sum f_s,p c_vs T, min T over cells
@@ -440,6 +459,10 @@ hipError_t launch_particles(const Params& P, PState cur, PState next,
 template <int PREC, bool OUT, bool SCAN, bool PAIR>
 static hipError_t step_t(const StepLaunch& a, hipStream_t s) {
   const Params& P = *a.P;
+  // the host keeps the tile counts exactly where this kernel reads them
+  if (SCAN && counted_tiles(PREC, PAIR) &&
+      !(a.B.tcount && a.B.tcount_next && a.B.tcount_clear))
+    return hipErrorInvalidValue;
   const Hot<typename Prec<PREC>::C> H = make_hot<typename Prec<PREC>::C>(P);
   const unsigned grid = (unsigned)(P.nfirst + stream_grid(P, PAIR));
   hipExtLaunchKernelGGL((k_step<PREC, OUT, SCAN, PAIR>), dim3(grid),
@@ -501,6 +524,14 @@ hipError_t launch_init(int prec, const Params& P, void* f, void* g, void* h,
   }
 #undef VLB_INIT
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_tile_counts(const Params& P, PState cur, PConst pc,
+                              int* count, int* flags, hipStream_t s) {
+  if (P.np == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_counts, dim3(blocks_for(P.np, 4)), dim3(256), 0,
+                     s, P, cur, pc, count, flags);
+  return hipGetLastError();
 }
 
 hipError_t launch_particle_sums(const Params& P, PState ps, PConst pc,
