@@ -1232,6 +1232,41 @@ struct TileShared {
   int wcount[kBlock / 64];
 };
 
+// Whether the cell span [a0, a1] (unwrapped on a periodic axis of n cells)
+// meets [b0, b1] (within the axis).
+__device__ __forceinline__ bool span_meets(int a0, int a1, int b0, int b1,
+                                           int n, int periodic) {
+  if (a1 - a0 + 1 >= n) return true;
+  if (!periodic) return a1 >= b0 && a0 <= b1;
+  for (int sh = -n; sh <= n; sh += n)
+    if (a1 + sh >= b0 && a0 + sh <= b1) return true;
+  return false;
+}
+
+// The particles of a tile whose band box meets the 64 cells of wave w: bit
+// k for slot k (every lane gets the same mask).  A particle owns no cell
+// outside its band box, so a wave may skip the others.
+__device__ __forceinline__ unsigned long long wave_particle_mask(
+    const Params& P, const BlockParticles& bp, int cnt, int tile, int w,
+    int lane) {
+  const int c0 = tile * kBlock + w * 64;
+  bool hit = false;
+  if (lane < cnt && c0 < P.N) {
+    const int c1 = min(c0 + 63, P.N - 1);
+    const int r0 = c0 / P.nx, r1 = c1 / P.nx;
+    int x0 = 0, x1 = P.nx - 1;   // whole rows where the wave spans two
+    if (r0 == r1) {
+      x0 = c0 - r0 * P.nx;
+      x1 = c1 - r0 * P.nx;
+    }
+    int i0, i1, j0, j1;
+    band_box(P, bp.X[lane], bp.Y[lane], bp.R[lane], i0, i1, j0, j1);
+    hit = span_meets(j0, j1, r0, r1, P.ny, P.pery) &&
+          span_meets(i0, i1, x0, x1, P.nx, P.perx);
+  }
+  return __ballot(hit);
+}
+
 // One tile of one time step (a whole step is one launch of k_step, or of
 // k_batch_step for many domains).  Two roles:
 //
@@ -1280,6 +1315,7 @@ __device__ __forceinline__ void step_task(
   const int cy = (act0 ? c0 : P.N - 1) / P.nx;
   const int cx = (act0 ? c0 : P.N - 1) - cy * P.nx;
 
+  unsigned long long wmask = 0ull;  // particle tiles: the wave's particles
   // ---- phase 1 (particle tiles): particles of the tile, and per cell the
   // solid fraction f_s = sum_p f_s,p and sum_p f_s,p (u_s, u_s u_s); where
   // overlapping disks cover more than the cell the shares are scaled to
@@ -1290,14 +1326,17 @@ __device__ __forceinline__ void step_task(
                  B.tcount_next);
     else
       load_block_list(sh.bp, sh.tmp, L, tile, nxt, pc, flags);
-    // (a) which particles reach the cell (slot order), whether they cover
-    // it wholly; the first kShareCache are kept
+    // (a) which particles reach the cell (slot order; only those whose
+    // band box meets the wave's cells), whether they cover it wholly; the
+    // first kShareCache are kept
     const int cnt = sh.bp.cnt;
+    wmask = cnt > 1 ? wave_particle_mask(P, sh.bp, cnt, tile, t >> 6, lane)
+                    : (unsigned long long)cnt;   // one particle: no test
     const double xn = (double)cx + 0.5, yn = (double)cy + 0.5;
     int nin = 0;
     unsigned cut = 0;                 // cache entries whose area is pending
-    for (int k = 0; k < cnt; ++k) {
-      if (!act0) break;
+    for (unsigned long long m = act0 ? wmask : 0ull; m; m &= m - 1) {
+      const int k = __ffsll((long long)m) - 1;
       const double X = near_copy(sh.bp.X[k], xn, (double)P.nx, P.perx);
       const double Y = near_copy(sh.bp.Y[k], yn, (double)P.ny, P.pery);
       const double R = sh.bp.R[k];
@@ -1371,6 +1410,7 @@ __device__ __forceinline__ void step_task(
     }
     if (nin > kShareCache) {
       for (int k = sh.slot[kShareCache - 1][t] + 1; k < cnt; ++k) {
+        if (!((wmask >> k) & 1ull)) continue;
         SlotGeom sg;
         if (particle_geometry(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.R[k],
                               sh.bp.Ux[k], sh.bp.Uy[k], sh.bp.Om[k], cx, cy,
@@ -1468,7 +1508,14 @@ __device__ __forceinline__ void step_task(
     const bool over = pass == 1 && S0raw > (C)1;
     const C inv = over ? (C)1 / S0raw : (C)1;
     int e = 0;                       // next cached share of this cell
-    for (int k = 0; k < cnt; ++k) {
+    // slots whose band box misses the wave: nothing to add
+    if (lane < cnt && !((wmask >> lane) & 1ull)) {
+      sh.red[lane][wv][0] = 0.0;
+      sh.red[lane][wv][1] = 0.0;
+      sh.red[lane][wv][2] = 0.0;
+    }
+    for (unsigned long long m = wmask; m; m &= m - 1) {
+      const int k = __ffsll((long long)m) - 1;
       bool has = false;
       C a = (C)0;
       if (e < ncached && sh.slot[e][t] == k) {
