@@ -16,6 +16,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -42,9 +43,20 @@ KERNEL_SOURCES = ["paper_2410_23802_amd/csrc/vlb_device.h",
 def kernel_hash() -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, p)) as fh:
+            h.update(code_only(fh.read(), p.endswith(".py")).encode())
     return h.hexdigest()[:16]
+
+
+def code_only(text: str, python: bool) -> str:
+    """The source without its comments and blank-space differences, so that
+    an edit of comments alone keeps the hash (it changes no kernel)."""
+    if python:
+        text = re.sub(r"#[^\n]*", "", text)
+    else:
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+    return " ".join(text.split())
 
 
 def measured_traffic(workload: str, precision: str):

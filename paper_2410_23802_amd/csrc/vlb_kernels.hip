@@ -6,9 +6,9 @@
 
 namespace vlb {
 
-// The step kernel of one domain: block roles as above.  FP64 is held to 128
-// VGPRs (4 waves per SIMD, the occupancy of the plain update; the geometry
-// of the particle role spills a little).  The 32-bit forms are held to 5
+// The step kernel of one domain, one launch per step: block roles as
+// step_task (vlb_device.h) describes.  FP64 is held to 128 VGPRs (4 waves
+// per SIMD, the occupancy of the plain update).  The 32-bit forms are held to 5
 // waves (96 VGPRs, no added spill): 4-7 % faster on the channel than the
 // unconstrained 4 waves; at 6 the particle role spills and loses it again
 // (and the LDS of a particle tile caps a CU at 7 blocks).  PAIR (16-bit
