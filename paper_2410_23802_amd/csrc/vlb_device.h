@@ -346,19 +346,24 @@ __device__ __forceinline__ bool centre_ok(const Params& P, double X,
   return okx && oky;
 }
 
-// The 256-cell blocks that row `row` of the band box touches, ascending, at
-// most four.  Returns their number.
-__device__ __forceinline__ int row_blocks(int row, const ColSegs& cs, int nx,
-                                          int* b) {
-  int n = 0;
-  for (int k = 0; k < cs.n; ++k) {
-    if (cs.hi[k] < cs.lo[k]) continue;
-    const int first = (row * nx + cs.lo[k]) / kBlock;
-    const int last = (row * nx + cs.hi[k]) / kBlock;
-    for (int q = first; q <= last; ++q)
-      if (n == 0 || b[n - 1] != q) b[n++] = q;
+// The 256-cell blocks that row `row` of the band box touches, ascending and
+// without repeats: the ranges [f0, l0] and [f1, l1] (empty when l < f), one
+// per column segment; the second starts past the first's last block.
+// Scalars rather than an indexed array, which the compiler would otherwise
+// place in LDS behind a read of the dispatch packet.
+__device__ __forceinline__ void row_block_ranges(int row, const ColSegs& cs,
+                                                 int nx, int& f0, int& l0,
+                                                 int& f1, int& l1) {
+  f0 = 0; l0 = -1; f1 = 0; l1 = -1;
+  if (cs.hi[0] >= cs.lo[0]) {
+    f0 = (row * nx + cs.lo[0]) / kBlock;
+    l0 = (row * nx + cs.hi[0]) / kBlock;
   }
-  return n;
+  if (cs.n > 1 && cs.hi[1] >= cs.lo[1]) {
+    f1 = (row * nx + cs.lo[1]) / kBlock;
+    l1 = (row * nx + cs.hi[1]) / kBlock;
+    if (l0 >= f0 && f1 == l0) ++f1;   // the block the first range ends in
+  }
 }
 
 
@@ -413,17 +418,20 @@ __device__ BlockRanges block_ranges(const Params& P, double X, double Y,
   int i0, i1, j0, j1;
   band_box(P, X, Y, R, i0, i1, j0, j1);
   if (i1 < i0 || j1 < j0) return r;
-  int a0[2] = {j0, 0}, a1[2] = {j1, -1}, na = 1;
+  // row spans: [a0, a1], and [b0, b1] when the box wraps around y
+  int a0 = j0, a1 = j1, b0 = 0, b1 = -1, na = 1;
   if (P.pery && j0 < 0) {          // rows 0..j1 and j0+ny..ny-1
-    na = 2; a0[0] = 0; a1[0] = j1; a0[1] = j0 + P.ny; a1[1] = P.ny - 1;
+    na = 2; a0 = 0; a1 = j1; b0 = j0 + P.ny; b1 = P.ny - 1;
   } else if (P.pery && j1 >= P.ny) {  // rows 0..j1-ny and j0..ny-1
-    na = 2; a0[0] = 0; a1[0] = j1 - P.ny; a0[1] = j0; a1[1] = P.ny - 1;
+    na = 2; a0 = 0; a1 = j1 - P.ny; b0 = j0; b1 = P.ny - 1;
   }
   const bool xfull = P.perx && (i0 < 0 || i1 >= P.nx);
   const int ca = xfull ? 0 : i0, cb = xfull ? P.nx - 1 : i1;
-  for (int k = 0; k < na; ++k) {
-    r.lo[k] = (a0[k] * P.nx + ca) / unit;
-    r.hi[k] = (a1[k] * P.nx + cb) / unit;
+  r.lo[0] = (a0 * P.nx + ca) / unit;
+  r.hi[0] = (a1 * P.nx + cb) / unit;
+  if (na == 2) {
+    r.lo[1] = (b0 * P.nx + ca) / unit;
+    r.hi[1] = (b1 * P.nx + cb) / unit;
   }
   r.n = na;
   if (na == 2 && r.hi[0] >= r.lo[1]) {  // the two ranges touch: merge

@@ -116,6 +116,68 @@ __global__ __launch_bounds__(kBlock) void k_init(
   macro[5 * N + c] = 0.0;
 }
 
+// LDS of the particle pass's repulsion: the neighbour search (a bitmap of
+// kWords x 64 particles per wave, kCand candidates gathered at a time) or
+// the all-pairs staging (kStage particles at a time).
+constexpr int kWords = 128;
+constexpr int kCand = 128;
+constexpr int kStage = 1024;
+union PassShared {
+  struct {
+    unsigned long long marks[4][kWords];
+    int wbase[4][kWords];
+    int cq[4][kCand];
+    double X[4][kCand], Y[4][kCand], R[4][kCand];
+  } nb;
+  struct {
+    double X[kStage], Y[kStage], R[kStage];
+  } all;
+};
+
+// Orders a wave's LDS writes before its later LDS reads (other lanes'
+// included); no block barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sets in `marks` the bit of every particle listed in the tiles f0 ..
+// f0 + n0 - 1 and f1 .. f1 + n1 - 1 (the previous positions' lists): four
+// tiles at a time, whose counts and first eight entries are each loaded
+// together.
+__device__ __forceinline__ void mark_listed(const Lists& L, int f0, int n0,
+                                            int f1, int n1,
+                                            unsigned long long* marks) {
+  const int nt = n0 + n1;
+  for (int g = 0; g < nt; g += 4) {
+    int tt[4], n[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = g + u;
+      tt[u] = i < n0 ? f0 + i : f1 + (i - n0);
+      n[u] = i < nt ? min(L.ocnt[tt[u]], kListCap) : 0;
+    }
+    int q[4][8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        q[u][e] = e < n[u] ? L.oent[(size_t)tt[u] * kListCap + e].x : -1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (q[u][e] >= 0)
+          atomicOr(&marks[q[u][e] >> 6], 1ull << (q[u][e] & 63));
+      for (int e = 8; e < n[u]; ++e) {
+        const int qq = L.oent[(size_t)tt[u] * kListCap + e].x;
+        atomicOr(&marks[qq >> 6], 1ull << (qq & 63));
+      }
+    }
+  }
+}
+
 // -------------------------------------------------------------------------
 // Particle pass (list form, and the force read-out of both forms): one wave
 // (64 lanes) per particle.  Modes: update (Newton-Euler step, then the block
@@ -135,30 +197,47 @@ __global__ __launch_bounds__(256) void k_particles(
   const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
   const bool mine = p < P.np;          // uniform in the wave
 
-  // The momentum-exchange sums first, so that their loads are in flight
-  // while the repulsion is computed.
+  // The momentum-exchange sums.  List form: the slot count, then the first
+  // 64 slots' partials, are loaded now and added after the repulsion, in
+  // the order of reduce_partials (lane l: slots l, l + 64, ...; then the
+  // butterfly).  Scan form (the force read-out only): reduce_partials.
+  const bool sums = mine && mode != kModeBinOnly;
   double fx = 0.0, fy = 0.0, tz = 0.0;
-  if (mine && mode != kModeBinOnly)
-    reduce_partials(P, cur, pc, partial, have_partials, p, lane, fx, fy, tz);
+  const double* src = partial + (size_t)(mine ? p : 0) * P.maxb * kRedVals;
+  int ns = 0;
+  double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+  if (sums && !P.scan && have_partials) {
+    ns = cur.nslot[p];
+    if (lane < ns) {
+      o0 = src[lane * kRedVals + 0];
+      o1 = src[lane * kRedVals + 1];
+      o2 = src[lane * kRedVals + 2];
+    }
+  }
 
   // Repulsion of the update.  The candidates of particle p are the
   // particles listed in the tiles of the box of half-width R_p + rmax +
   // zeta around its centre, in the lists of the positions the pass starts
   // from: a particle within reach (d < R_p + R_q + zeta) has its centre
   // cell in that box, and a particle's band box holds its centre cell.  The
-  // wave marks them in a bitmap; each lane then visits q = lane, lane + 64,
-  // ... in ascending order, as repulsion() does over all particles, and
-  // calls the pair law for marked ones only -- the others are out of reach
-  // and add nothing, so the sums are those of the all-pairs loop.  Without
-  // those lists (or with more particles than the bitmap holds) the block
-  // stages all particles in LDS, kStage at a time.
+  // wave marks them in a bitmap, gathers their positions into LDS, and
+  // each lane then visits its own (q = lane, lane + 64, ...) in ascending
+  // order, as repulsion() does over all particles -- the others are out
+  // of reach and add nothing, so the sums are those of the all-pairs loop.
+  // Without those lists (or with more particles than the bitmap holds)
+  // the block stages all particles in LDS, kStage at a time.
   double cx = 0.0, cy = 0.0;
   if (mode == kModeUpdate && P.coll_range > 0.0) {   // uniform in the grid
-    constexpr int kWords = 128;                      // bitmap: 8192 particles
+    __shared__ PassShared psh;
     const double Xp = mine ? cur.X[p] : 0.0, Yp = mine ? cur.Y[p] : 0.0;
     const double Rp = mine ? pc.R[p] : 0.0;
     if (L.ocnt && P.np <= 64 * kWords) {
-      __shared__ unsigned long long marks[4][kWords];
+      auto& marks = psh.nb.marks;
+      auto& wbase = psh.nb.wbase;
+      auto& cq = psh.nb.cq;
+      auto& cX = psh.nb.X;
+      auto& cY = psh.nb.Y;
+      auto& cR = psh.nb.R;
       const int w = threadIdx.x >> 6, nwords = (P.np + 63) >> 6;
       for (int k = lane; k < nwords; k += 64) marks[w][k] = 0ull;
       __syncthreads();
@@ -174,32 +253,78 @@ __global__ __launch_bounds__(256) void k_particles(
         const int rows = min(j1 - j0 + 1, P.ny);
         for (int r = lane; r < rows; r += 64) {
           const int row = ((j0 + r) % P.ny + P.ny) % P.ny;
-          for (int sgm = 0; sgm < cs.n; ++sgm) {
-            if (cs.hi[sgm] < cs.lo[sgm]) continue;
-            const int first = (row * P.nx + cs.lo[sgm]) / kBlock;
-            const int last = (row * P.nx + cs.hi[sgm]) / kBlock;
-            for (int t = first; t <= last; ++t) {
-              const int n = min(L.ocnt[t], kListCap);
-              for (int e = 0; e < n; ++e) {
-                const int q = L.oent[(size_t)t * kListCap + e].x;
-                atomicOr(&marks[w][q >> 6], 1ull << (q & 63));
-              }
-            }
+          int f0 = 0, n0 = 0, f1 = 0, n1 = 0;   // per segment: first tile, tiles
+          if (cs.hi[0] >= cs.lo[0]) {
+            f0 = (row * P.nx + cs.lo[0]) / kBlock;
+            n0 = (row * P.nx + cs.hi[0]) / kBlock - f0 + 1;
           }
+          if (cs.n > 1 && cs.hi[1] >= cs.lo[1]) {
+            f1 = (row * P.nx + cs.lo[1]) / kBlock;
+            n1 = (row * P.nx + cs.hi[1]) / kBlock - f1 + 1;
+          }
+          mark_listed(L, f0, n0, f1, n1, marks[w]);
         }
       }
       __syncthreads();
       if (mine) {
+        // the marked particles but p, ascending: the m of them are
+        // gathered kCand at a time; word k's come after wbase[k] others.
+        // Lane l's own (q mod 64 = l) are bit l of the words, the words
+        // holding one listed in col0 (0..63) and col1 (64..127).
+        if (lane == 0) marks[w][p >> 6] &= ~(1ull << (p & 63));
+        wave_lds_sync();
+        int m = 0;
+        for (int k0 = 0; k0 < nwords; k0 += 64) {
+          const int k = k0 + lane;
+          const unsigned long long bits = k < nwords ? marks[w][k] : 0ull;
+          const int c = __popcll(bits);
+          const int b = m + wave_excl_scan(c, lane);
+          if (k < nwords) wbase[w][k] = b;
+          m = __shfl(b + c, 63, 64);
+        }
+        unsigned long long col0 = 0ull, col1 = 0ull;
         for (int k = 0; k < nwords; ++k) {
-          const int q = k * 64 + lane;
-          if (q < P.np && q != p && ((marks[w][k] >> lane) & 1ull))
-            repulsion_pair(P, Xp, Yp, Rp, cur.X[q], cur.Y[q], pc.R[q], cx,
+          if ((marks[w][k] >> lane) & 1ull) {
+            if (k < 64) col0 |= 1ull << k;
+            else col1 |= 1ull << (k - 64);
+          }
+        }
+        wave_lds_sync();
+        const unsigned long long below = (1ull << lane) - 1ull;
+        for (int c0 = 0; c0 < m; c0 += kCand) {
+          const int mc = min(kCand, m - c0);
+          for (int k = lane; k < nwords; k += 64) {
+            unsigned long long bits = marks[w][k];
+            for (int pos = wbase[w][k]; bits && pos < c0 + kCand;
+                 bits &= bits - 1ull, ++pos)
+              if (pos >= c0)
+                cq[w][pos - c0] = k * 64 + __ffsll((long long)bits) - 1;
+          }
+          wave_lds_sync();
+          for (int i = lane; i < mc; i += 64) {
+            const int q = cq[w][i];
+            cX[w][i] = cur.X[q];
+            cY[w][i] = cur.Y[q];
+            cR[w][i] = pc.R[q];
+          }
+          wave_lds_sync();
+          while (col0 | col1) {
+            const int k = col0 ? __ffsll((long long)col0) - 1
+                               : 64 + __ffsll((long long)col1) - 1;
+            const int i = wbase[w][k] + __popcll(marks[w][k] & below) - c0;
+            if (i >= kCand) break;                 // a later chunk's
+            repulsion_pair(P, Xp, Yp, Rp, cX[w][i], cY[w][i], cR[w][i], cx,
                            cy);
+            if (col0) col0 &= col0 - 1ull;
+            else col1 &= col1 - 1ull;
+          }
+          wave_lds_sync();
         }
       }
     } else {
-      constexpr int kStage = 2048;
-      __shared__ double sX[kStage], sY[kStage], sR[kStage];
+      auto& sX = psh.all.X;
+      auto& sY = psh.all.Y;
+      auto& sR = psh.all.R;
       for (int c0 = 0; c0 < P.np; c0 += kStage) {
         const int m1 = min(kStage, P.np - c0);
         for (int m = (int)threadIdx.x; m < m1; m += (int)blockDim.x) {
@@ -224,6 +349,23 @@ __global__ __launch_bounds__(256) void k_particles(
     }
   }
   if (!mine) return;  // whole wave
+  if (sums) {
+    if (P.scan) {
+      reduce_partials(P, cur, pc, partial, have_partials, p, lane, fx, fy, tz);
+    } else {
+      fx += o0;
+      fy += o1;
+      tz += o2;
+      for (int k = lane + 64; k < ns; k += 64) {
+        fx += src[k * kRedVals + 0];
+        fy += src[k * kRedVals + 1];
+        tz += src[k * kRedVals + 2];
+      }
+      fx = wave_sum(fx);
+      fy = wave_sum(fy);
+      tz = wave_sum(tz);
+    }
+  }
 
   if (mode == kModeReduceOnly) {
     if (lane == 0) {
@@ -249,28 +391,32 @@ __global__ __launch_bounds__(256) void k_particles(
   if (ok) band_box(P, nX, nY, R, i0, i1, j0, j1);
   const int rows = j1 - j0 + 1;
   const ColSegs cs = col_segments(i0, i1, P.nx);
-  int b[4];
-  int nb = 0;
+  int f0 = 0, l0 = -1, f1 = 0, l1 = -1;   // this row's blocks
   if (lane < rows) {
-    const int row = sorted_row(lane, j0, j1, P.ny);
-    nb = row_blocks(row, cs, P.nx, b);
-    if (lane > 0 && nb > 0) {
-      int pb[4];
-      const int prow = sorted_row(lane - 1, j0, j1, P.ny);
-      const int pn = row_blocks(prow, cs, P.nx, pb);
-      if (pn > 0 && pb[pn - 1] == b[0]) {   // shared with the previous row
-        for (int k = 1; k < nb; ++k) b[k - 1] = b[k];
-        --nb;
+    row_block_ranges(sorted_row(lane, j0, j1, P.ny), cs, P.nx, f0, l0, f1,
+                     l1);
+    if (lane > 0 && (l0 >= f0 || l1 >= f1)) {
+      int g0, m0, g1, m1;
+      row_block_ranges(sorted_row(lane - 1, j0, j1, P.ny), cs, P.nx, g0, m0,
+                       g1, m1);
+      const bool prev = m0 >= g0 || m1 >= g1;
+      const int plast = m1 >= g1 ? m1 : m0;   // the previous row's last
+      if (prev && plast == (l0 >= f0 ? f0 : f1)) {  // shared: listed there
+        if (l0 >= f0) ++f0;
+        else ++f1;
       }
     }
   }
+  const int n0 = max(l0 - f0 + 1, 0);
+  const int nb = n0 + max(l1 - f1 + 1, 0);
   const int base = wave_excl_scan(nb, lane);
   const int total = __shfl(base + nb, 63, 64);
   for (int k = 0; k < nb; ++k) {
+    const int blk = k < n0 ? f0 + k : f1 + (k - n0);
     const int slot = p * P.maxb + base + k;
-    const int pos = atomicAdd(&L.cnt[b[k]], 1);
+    const int pos = atomicAdd(&L.cnt[blk], 1);
     if (pos < kListCap)
-      L.ent[(size_t)b[k] * kListCap + pos] = make_int2(p, slot);
+      L.ent[(size_t)blk * kListCap + pos] = make_int2(p, slot);
     else
       atomicOr(flags, kFlagListFull);
   }

@@ -221,10 +221,10 @@ def test_many_particles_list_form_fp64(vlb, oracle_mod):
     check(e, 120, twin=twin_errors(oracle_mod, d, ps, 120, o, pkeys=keys))
 
 
-def test_particle_pass_more_than_one_staging_chunk_fp64(vlb, oracle_mod):
-    """2100 small moving disks, close enough to collide: the particle pass
-    stages 2048 particles at a time for the repulsion, so this takes two
-    chunks; against the oracle."""
+def test_particle_pass_neighbour_search_2100_particles_fp64(vlb, oracle_mod):
+    """2100 small moving disks, close enough to collide, on 1200 x 600
+    cells: the list form's neighbour search for the repulsion at a larger
+    particle count; against the oracle."""
     rng = np.random.default_rng(12)
     d = W.walls(W.domain(1200, 600, tau_f=0.7, lambda_f=0.05, R_lambda=3.0,
                          R_cv=1.5, gravity=(0.0, -4e-5), beta=0.1,
@@ -240,6 +240,91 @@ def test_particle_pass_more_than_one_staging_chunk_fp64(vlb, oracle_mod):
     keys = ("x", "y", "ux", "uy", "omega", "Fx", "Fy", "Tz")
     e.update(particle_errors(g, o, keys))
     check(e, 6, twin=twin_errors(oracle_mod, d, ps, 6, o, pkeys=keys))
+
+
+def _box_tiles(x, y, h, nx, ny):
+    """The 256-cell tiles that the box of half-width h around (x, y) meets,
+    on walled axes: cells floor(x - h) - 1 .. floor(x + h) + 1 clipped to
+    the domain, likewise in y (the band box of the kernels)."""
+    i0, i1 = max(math.floor(x - h) - 1, 0), min(math.floor(x + h) + 1, nx - 1)
+    j0, j1 = max(math.floor(y - h) - 1, 0), min(math.floor(y + h) + 1, ny - 1)
+    out = set()
+    for row in range(j0, j1 + 1):
+        out.update(range((row * nx + i0) // 256, (row * nx + i1) // 256 + 1))
+    return out
+
+
+def _tile_lists(pts, R, nx, ny):
+    """Per tile, the particles whose band box meets it (the block lists)."""
+    lists = {}
+    for q, (x, y) in enumerate(pts):
+        for t in _box_tiles(x, y, R, nx, ny):
+            lists.setdefault(t, set()).add(q)
+    return lists
+
+
+def _max_candidates(pts, R, zeta, nx, ny, lists):
+    """The largest number of repulsion candidates of one particle: those
+    listed in the tiles of its box of half-width 2 R + zeta."""
+    best = 0
+    for p, (x, y) in enumerate(pts):
+        c = set()
+        for t in _box_tiles(x, y, 2 * R + zeta, nx, ny):
+            c |= lists.get(t, set())
+        c.discard(p)
+        best = max(best, len(c))
+    return best
+
+
+def test_particle_pass_many_candidates_fp64(vlb, oracle_mod):
+    """1000 small disks (R = 1.5) in a 2048 x 64 channel with a long
+    repulsion range (zeta = 20): a particle's neighbour search meets up to
+    250 listed particles, more than the 128 a wave gathers at a time, so
+    the candidates are taken in two chunks; against the oracle."""
+    nx, ny, R, zeta = 2048, 64, 1.5, 20.0
+    rng = np.random.default_rng(13)
+    d = W.walls(W.domain(nx, ny, tau_f=0.7, lambda_f=0.05, R_lambda=3.0,
+                         R_cv=1.5, gravity=(0.0, -2e-5), beta=0.1,
+                         init_T=1.0, coll_range=zeta, coll_stiff_pp=2e-5,
+                         coll_stiff_pw=4e-5), thermal="adiabatic")
+    pts = W.rsa_disks(1000, R, (0.0, 0.0, float(nx), float(ny)), 1.0, seed=8)
+    lists = _tile_lists(pts, R, nx, ny)
+    assert max(len(v) for v in lists.values()) <= 32      # no list overflow
+    assert _max_candidates(pts, R, zeta, nx, ny, lists) > 128
+    ps = [W.particle(x, y, R, rho_s=rng.uniform(1.2, 2.0), T_init=0.3,
+                     ux=rng.uniform(-0.01, 0.01), uy=rng.uniform(-0.01, 0.01))
+          for x, y in pts]
+    say("case: 1000 particles, zeta 20, list form fp64 6 steps")
+    g, o = run_pair(vlb, oracle_mod, d, ps, 6)
+    e = field_errors(g, o)
+    keys = ("x", "y", "ux", "uy", "omega", "Fx", "Fy", "Tz")
+    e.update(particle_errors(g, o, keys))
+    check(e, 6, twin=twin_errors(oracle_mod, d, ps, 6, o, pkeys=keys))
+
+
+def test_particle_pass_all_pairs_staging_fp64(vlb, oracle_mod):
+    """8400 small disks on 1200 x 1200 cells: more than the neighbour
+    search's bitmap holds (8192), so the particle pass stages all particles
+    in LDS, 1024 at a time (nine chunks), for the repulsion; against the
+    oracle."""
+    nx = ny = 1200
+    R = 1.5
+    rng = np.random.default_rng(14)
+    d = W.walls(W.domain(nx, ny, tau_f=0.7, lambda_f=0.05, R_lambda=3.0,
+                         R_cv=1.5, gravity=(0.0, -4e-5), beta=0.1,
+                         init_T=1.0, coll_range=2.0, coll_stiff_pp=2e-3,
+                         coll_stiff_pw=4e-3), thermal="adiabatic")
+    pts = W.rsa_disks(8400, R, (0.0, 0.0, float(nx), float(ny)), 1.0, seed=8)
+    assert max(len(v) for v in _tile_lists(pts, R, nx, ny).values()) <= 32
+    ps = [W.particle(x, y, R, rho_s=rng.uniform(1.2, 2.0), T_init=0.3,
+                     ux=rng.uniform(-0.01, 0.01), uy=rng.uniform(-0.01, 0.01))
+          for x, y in pts]
+    say("case: 8400 particles list form fp64 4 steps")
+    g, o = run_pair(vlb, oracle_mod, d, ps, 4)
+    e = field_errors(g, o)
+    keys = ("x", "y", "ux", "uy", "omega", "Fx", "Fy", "Tz")
+    e.update(particle_errors(g, o, keys))
+    check(e, 4, twin=twin_errors(oracle_mod, d, ps, 4, o, pkeys=keys))
 
 
 def test_walls_dirichlet_channel_fp64(vlb, oracle_mod):
