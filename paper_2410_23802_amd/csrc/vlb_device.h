@@ -241,18 +241,45 @@ __device__ double covered_share(double X, double Y, double R, int i, int j) {
 }
 
 // -------------------------------------------------------------------------
-// Reductions (fixed order: xor butterfly inside a wave, waves in index order).
+// Reductions (fixed order: a tree inside a wave, waves in index order).
 
+// The value of the lane that DPP control CTRL pairs with this one (the
+// quad permutations and row mirrors used here are involutions, so partners
+// exchange values).
+template <int CTRL>
+__device__ __forceinline__ double dpp_partner(double v) {
+  return __builtin_amdgcn_update_dpp(0.0, v, CTRL, 0xF, 0xF, false);
+}
+
+// Lane `lane`'s value, uniform.
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the wave's 64 lanes (all active), the same bits in every lane:
+// inside each row of 16 lanes, partners add (lane ^ 1, lane ^ 2, the
+// mirror in 8, the mirror in 16; a + b and b + a are the same bits), then
+// the four row sums are added in a fixed order.  DPP moves instead of
+// LDS permutes: a few cycles per step instead of an LDS round trip.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_partner<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_partner<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_partner<0x141>(v);   // row_half_mirror
+  v += dpp_partner<0x140>(v);   // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) +
+         (lane_value(v, 32) + lane_value(v, 48));
 }
 
 __device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmin(v, dpp_partner<0xB1>(v));
+  v = fmin(v, dpp_partner<0x4E>(v));
+  v = fmin(v, dpp_partner<0x141>(v));
+  v = fmin(v, dpp_partner<0x140>(v));
+  return fmin(fmin(lane_value(v, 0), lane_value(v, 16)),
+              fmin(lane_value(v, 32), lane_value(v, 48)));
 }
 
 // Sum of three values over the 256 threads of a block, result in thread 0.
@@ -442,8 +469,8 @@ __device__ BlockRanges block_ranges(const Params& P, double X, double Y,
 }
 
 // Momentum-exchange force and torque of particle p: the sum of the partials
-// the last lattice pass wrote, lanes striding the slots, then an xor
-// butterfly (every lane ends with the same bits).
+// the last lattice pass wrote, lanes striding the slots, then wave_sum
+// (every lane ends with the same bits).
 __device__ __forceinline__ void reduce_partials(const Params& P,
                                                 const PState& cur,
                                                 const PConst& pc,
@@ -1198,8 +1225,12 @@ __device__ __forceinline__ int scan_task_tile(const Params& P, PState cur,
 // groups of G consecutive tiles, dealt to the XCDs in turn, and each XCD
 // walks its groups' tiles in order: the rows a tile pulls from its
 // neighbours are then mostly in the XCD's own L2 already.  (The group
-// starts at a multiple of 8 blocks.)  Tiles >= nblocks: none.
+// starts at a multiple of 8 blocks.)  With a tile stride (list form) block
+// k takes tile k * stride mod stream_blocks instead, a permutation that
+// scatters the tiles over the launch.  Tiles >= nblocks: none.
 __device__ __forceinline__ int stream_tile(const Params& P, int k) {
+  if (P.tile_stride)
+    return (int)((long long)k * P.tile_stride % P.stream_blocks);
   const int x = k & 7, j = k >> 3;
   const int gi = j / P.xcd_group, o = j - gi * P.xcd_group;
   return (gi * 8 + x) * P.xcd_group + o;

@@ -55,6 +55,9 @@ struct Params {
                       // (scan form: np * maxr rounded up to 8; else 0)
   int xcd_group;      // step kernel: consecutive tiles per XCD group
   int stream_blocks;  // step kernel: blocks of the streaming group
+  int tile_stride;    // step kernel, list form: block k of the streaming
+                      // group takes tile k * tile_stride mod stream_blocks
+                      // (0: the XCD groups)
   int pair_tiles;     // step kernel, 16-bit forms: two plain tiles per
                       // streaming block (never in the list form)
 };

@@ -199,8 +199,8 @@ __global__ __launch_bounds__(256) void k_particles(
 
   // The momentum-exchange sums.  List form: the slot count, then the first
   // 64 slots' partials, are loaded now and added after the repulsion, in
-  // the order of reduce_partials (lane l: slots l, l + 64, ...; then the
-  // butterfly).  Scan form (the force read-out only): reduce_partials.
+  // the order of reduce_partials (lane l: slots l, l + 64, ...; then
+  // wave_sum).  Scan form (the force read-out only): reduce_partials.
   const bool sums = mine && mode != kModeBinOnly;
   double fx = 0.0, fy = 0.0, tz = 0.0;
   const double* src = partial + (size_t)(mine ? p : 0) * P.maxb * kRedVals;
