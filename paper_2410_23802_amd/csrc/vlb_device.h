@@ -307,13 +307,31 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c,
 // -------------------------------------------------------------------------
 // Band boxes and block bookkeeping.
 
-__device__ __forceinline__ int wave_excl_scan(int v, int lane) {
+// Exclusive prefix sum of v over the wave's lanes in lane order (all lanes
+// active), and the wave's total.  Values below 2^BITS are summed one bit
+// plane at a time from ballots (no LDS traffic); a wave holding a larger
+// value takes the shuffle scan.
+template <int BITS>
+__device__ __forceinline__ int wave_excl_scan(int v, int lane, int& total) {
+  const unsigned long long below = (1ull << lane) - 1ull;
+  if (__ballot(v >= (1 << BITS)) == 0ull) {
+    int s = 0, all = 0;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+      const unsigned long long m = __ballot((v >> b) & 1);
+      s += __popcll(m & below) << b;
+      all += __popcll(m) << b;
+    }
+    total = all;
+    return s;
+  }
   int incl = v;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    int t = __shfl_up(incl, o, 64);
+    const int t = __shfl_up(incl, o, 64);
     if (lane >= o) incl += t;
   }
+  total = __shfl(incl, 63, 64);
   return incl - v;
 }
 
@@ -1404,8 +1422,9 @@ __device__ __forceinline__ void step_task(
     } else {
       const int mine = __popc(cut);
       const int w = t >> 6;
-      const int below = wave_excl_scan(mine, lane);
-      if (lane == 63) sh.wcount[w] = below + mine;
+      int wtotal;
+      const int below = wave_excl_scan<3>(mine, lane, wtotal);
+      if (lane == 0) sh.wcount[w] = wtotal;
       __syncthreads();
       int base = below, total = 0;
       for (int v = 0; v < kBlock / 64; ++v) {

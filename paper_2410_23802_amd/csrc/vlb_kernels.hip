@@ -278,9 +278,10 @@ __global__ __launch_bounds__(256) void k_particles(
           const int k = k0 + lane;
           const unsigned long long bits = k < nwords ? marks[w][k] : 0ull;
           const int c = __popcll(bits);
-          const int b = m + wave_excl_scan(c, lane);
+          int ctotal;
+          const int b = m + wave_excl_scan<7>(c, lane, ctotal);
           if (k < nwords) wbase[w][k] = b;
-          m = __shfl(b + c, 63, 64);
+          m += ctotal;
         }
         unsigned long long col0 = 0ull, col1 = 0ull;
         for (int k = 0; k < nwords; ++k) {
@@ -409,8 +410,8 @@ __global__ __launch_bounds__(256) void k_particles(
   }
   const int n0 = max(l0 - f0 + 1, 0);
   const int nb = n0 + max(l1 - f1 + 1, 0);
-  const int base = wave_excl_scan(nb, lane);
-  const int total = __shfl(base + nb, 63, 64);
+  int total;
+  const int base = wave_excl_scan<3>(nb, lane, total);
   for (int k = 0; k < nb; ++k) {
     const int blk = k < n0 ? f0 + k : f1 + (k - n0);
     const int slot = p * P.maxb + base + k;
