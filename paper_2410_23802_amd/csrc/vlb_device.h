@@ -488,7 +488,34 @@ __device__ BlockRanges block_ranges(const Params& P, double X, double Y,
 
 // Momentum-exchange force and torque of particle p: the sum of the partials
 // the last lattice pass wrote, lanes striding the slots, then wave_sum
-// (every lane ends with the same bits).
+// (every lane ends with the same bits).  Scan form, with the particle's
+// centre (X, Y) at the step the partials belong to and its radius R: one
+// slot per (particle, 256-cell tile) of its band box.
+__device__ __forceinline__ void reduce_partials_at(const Params& P, double X,
+                                                   double Y, double R,
+                                                   const double* partial,
+                                                   int have, int p, int lane,
+                                                   double& fx, double& fy,
+                                                   double& tz) {
+  fx = fy = tz = 0.0;
+  if (have) {
+    const BlockRanges r = block_ranges(P, X, Y, R, kBlock);
+    const int nb = r.count();
+    const double* src = partial + (size_t)p * P.nblocks * kRedVals;
+    for (int k = lane; k < nb; k += 64) {
+      const double* o = src + (size_t)r.at(k) * kRedVals;
+      fx += o[0];
+      fy += o[1];
+      tz += o[2];
+    }
+  }
+  fx = wave_sum(fx);
+  fy = wave_sum(fy);
+  tz = wave_sum(tz);
+}
+
+// The same sums from the stored state: scan form as above; list form, the
+// particle's nslot slots in order.
 __device__ __forceinline__ void reduce_partials(const Params& P,
                                                 const PState& cur,
                                                 const PConst& pc,
@@ -496,28 +523,19 @@ __device__ __forceinline__ void reduce_partials(const Params& P,
                                                 int have, int p, int lane,
                                                 double& fx, double& fy,
                                                 double& tz) {
+  if (P.scan) {
+    reduce_partials_at(P, cur.X[p], cur.Y[p], pc.R[p], partial, have, p,
+                       lane, fx, fy, tz);
+    return;
+  }
   fx = fy = tz = 0.0;
   if (have) {
-    if (P.scan) {
-      // scan form: one slot per (particle, 256-cell tile)
-      const BlockRanges r =
-          block_ranges(P, cur.X[p], cur.Y[p], pc.R[p], kBlock);
-      const int nb = r.count();
-      const double* src = partial + (size_t)p * P.nblocks * kRedVals;
-      for (int k = lane; k < nb; k += 64) {
-        const double* o = src + (size_t)r.at(k) * kRedVals;
-        fx += o[0];
-        fy += o[1];
-        tz += o[2];
-      }
-    } else {
-      const int ns = cur.nslot[p];
-      const double* src = partial + (size_t)p * P.maxb * kRedVals;
-      for (int k = lane; k < ns; k += 64) {
-        fx += src[k * kRedVals + 0];
-        fy += src[k * kRedVals + 1];
-        tz += src[k * kRedVals + 2];
-      }
+    const int ns = cur.nslot[p];
+    const double* src = partial + (size_t)p * P.maxb * kRedVals;
+    for (int k = lane; k < ns; k += 64) {
+      fx += src[k * kRedVals + 0];
+      fy += src[k * kRedVals + 1];
+      tz += src[k * kRedVals + 2];
     }
   }
   fx = wave_sum(fx);
@@ -569,16 +587,17 @@ __device__ __forceinline__ void repulsion_walls(const Params& P, double Xp,
   }
 }
 
-__device__ __forceinline__ void repulsion(const Params& P, const PState& cur,
-                                          const PConst& pc, int p, int lane,
-                                          double& cx, double& cy) {
+// The repulsion on particle p (centre Xp, Yp, radius Rp) for at most 64
+// particles, lane q holding particle q (Xq, Yq, Rq; `other`: q < np and
+// q != p): the pairs lane by lane, wave_sum, then the walls.
+__device__ __forceinline__ void repulsion_lanes(const Params& P, double Xp,
+                                                double Yp, double Rp,
+                                                double Xq, double Yq,
+                                                double Rq, bool other,
+                                                double& cx, double& cy) {
   cx = cy = 0.0;
   if (!(P.coll_range > 0.0)) return;
-  const double Xp = cur.X[p], Yp = cur.Y[p], Rp = pc.R[p];
-  for (int q = lane; q < P.np; q += 64) {
-    if (q == p) continue;
-    repulsion_pair(P, Xp, Yp, Rp, cur.X[q], cur.Y[q], pc.R[q], cx, cy);
-  }
+  if (other) repulsion_pair(P, Xp, Yp, Rp, Xq, Yq, Rq, cx, cy);
   cx = wave_sum(cx);
   cy = wave_sum(cy);
   repulsion_walls(P, Xp, Yp, Rp, cx, cy);
@@ -588,45 +607,70 @@ struct PUpd {
   double X, Y, th, Ux, Uy, Om, Uxp, Uyp, Omp, Fx, Fy, Tz;
 };
 
-__device__ PUpd particle_update_sums(const Params& P, const PState& cur,
-                                     const PConst& pc, int p, double fx,
-                                     double fy, double tz, double cx,
-                                     double cy);
+// One particle's stored state and constants, in registers.
+struct POne {
+  double X, Y, th, Ux, Uy, Om, Uxp, Uyp, Omp, R, rhos, Tinit;
+  int fixed;
+};
 
-// One step of particle p, wave-level (every lane returns the same bits):
-// Newton-Euler (eq. particle; the gyroscopic term vanishes in 2-D) with the
-// inside-fluid correction of eq. inside.fluid by backward differences,
-// total force = hydrodynamic + (rho_s - rho_f) V g + repulsion, forward
-// Euler (Sec. 2.3 end).
-// The momentum-exchange sums (fx, fy, tz) and the repulsion (cx, cy) are
-// given.
-__device__ PUpd particle_update_sums(const Params& P, const PState& cur,
-                                     const PConst& pc, int p, double fx,
-                                     double fy, double tz, double cx,
-                                     double cy) {
+__device__ __forceinline__ POne load_one(const PState& s, const PConst& pc,
+                                         int p) {
+  POne o;
+  o.X = s.X[p]; o.Y = s.Y[p]; o.th = s.th[p];
+  o.Ux = s.Ux[p]; o.Uy = s.Uy[p]; o.Om = s.Om[p];
+  o.Uxp = s.Uxp[p]; o.Uyp = s.Uyp[p]; o.Omp = s.Omp[p];
+  o.R = pc.R[p]; o.rhos = pc.rhos[p]; o.Tinit = pc.Tinit[p];
+  o.fixed = pc.fixed[p];
+  return o;
+}
+
+// Lane src's POne, in every lane (src uniform).
+__device__ __forceinline__ POne lane_one(const POne& v, int src) {
+  POne o;
+  o.X = lane_value(v.X, src); o.Y = lane_value(v.Y, src);
+  o.th = lane_value(v.th, src);
+  o.Ux = lane_value(v.Ux, src); o.Uy = lane_value(v.Uy, src);
+  o.Om = lane_value(v.Om, src);
+  o.Uxp = lane_value(v.Uxp, src); o.Uyp = lane_value(v.Uyp, src);
+  o.Omp = lane_value(v.Omp, src);
+  o.R = lane_value(v.R, src); o.rhos = lane_value(v.rhos, src);
+  o.Tinit = lane_value(v.Tinit, src);
+  o.fixed = __builtin_amdgcn_readlane(v.fixed, src);
+  return o;
+}
+
+// One step of a particle (state s), wave-level (every lane returns the same
+// bits): Newton-Euler (eq. particle; the gyroscopic term vanishes in 2-D)
+// with the inside-fluid correction of eq. inside.fluid by backward
+// differences, total force = hydrodynamic + (rho_s - rho_f) V g +
+// repulsion, forward Euler (Sec. 2.3 end).  The momentum-exchange sums
+// (fx, fy, tz) and the repulsion (cx, cy) are given.
+__device__ PUpd particle_update_one(const Params& P, const POne& s,
+                                    double fx, double fy, double tz,
+                                    double cx, double cy) {
   PUpd u;
-  const double R = pc.R[p], rs = pc.rhos[p];
+  const double R = s.R, rs = s.rhos;
   const double V = M_PI * R * R;
   const double M = rs * V, I = 0.5 * M * R * R;
   const double Min = P.rho_f * M / rs, Iin = P.rho_f * I / rs;
-  const double Ux = cur.Ux[p], Uy = cur.Uy[p], Om = cur.Om[p];
+  const double Ux = s.Ux, Uy = s.Uy, Om = s.Om;
   u.Ux = Ux;
   u.Uy = Uy;
   u.Om = Om;
-  if (!pc.fixed[p]) {
-    const double Finx = -Min * (Ux - cur.Uxp[p]);
-    const double Finy = -Min * (Uy - cur.Uyp[p]);
-    const double Tin = -Iin * (Om - cur.Omp[p]);
+  if (!s.fixed) {
+    const double Finx = -Min * (Ux - s.Uxp);
+    const double Finy = -Min * (Uy - s.Uyp);
+    const double Tin = -Iin * (Om - s.Omp);
     const double Fcx = (fx - Finx) + (rs - P.rho_f) * V * P.grav_x + cx;
     const double Fcy = (fy - Finy) + (rs - P.rho_f) * V * P.grav_y + cy;
     u.Ux = Ux + Fcx / M;
     u.Uy = Uy + Fcy / M;
     u.Om = Om + (tz - Tin) / I;
   }
-  u.X = cur.X[p];
-  u.Y = cur.Y[p];
+  u.X = s.X;
+  u.Y = s.Y;
   advance_position(P, u.X, u.Y, Ux, Uy);
-  u.th = cur.th[p] + Om;
+  u.th = s.th + Om;
   u.Uxp = Ux;
   u.Uyp = Uy;
   u.Omp = Om;
@@ -636,22 +680,11 @@ __device__ PUpd particle_update_sums(const Params& P, const PState& cur,
   return u;
 }
 
-__device__ __forceinline__ PUpd particle_update_with(
-    const Params& P, const PState& cur, const PConst& pc,
-    const double* partial, int have, int p, int lane, double cx, double cy) {
-  double fx, fy, tz;
-  reduce_partials(P, cur, pc, partial, have, p, lane, fx, fy, tz);
-  return particle_update_sums(P, cur, pc, p, fx, fy, tz, cx, cy);
-}
-
-__device__ __forceinline__ PUpd particle_update(const Params& P,
-                                                const PState& cur,
-                                                const PConst& pc,
-                                                const double* partial,
-                                                int have, int p, int lane) {
-  double cx, cy;
-  repulsion(P, cur, pc, p, lane, cx, cy);
-  return particle_update_with(P, cur, pc, partial, have, p, lane, cx, cy);
+// The same from the stored state of particle p.
+__device__ __forceinline__ PUpd particle_update_sums(
+    const Params& P, const PState& cur, const PConst& pc, int p, double fx,
+    double fy, double tz, double cx, double cy) {
+  return particle_update_one(P, load_one(cur, pc, p), fx, fy, tz, cx, cy);
 }
 
 __device__ __forceinline__ void store_particle(PState& s, int p,
@@ -749,14 +782,20 @@ __device__ void scan_block(BlockParticles& bp, const Params& P, int b,
   __shared__ int s_nwork;
   __shared__ int s_work_pid[64], s_work_rank[64], s_work_store[64];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // every wave loads the stored state of particle `lane`: a wave that
+  // advances particle p then takes p's values from lane p, with no second
+  // round trip to memory
+  const bool held = lane < P.np;
+  POne own = {};
+  if (held) own = load_one(cur, pc, lane);
   if (wave == 0) {
     bool cand = false, store = false;
     double X = 0.0, Y = 0.0;
-    if (lane < P.np) {
-      X = cur.X[lane];
-      Y = cur.Y[lane];
-      if (advance) advance_position(P, X, Y, cur.Ux[lane], cur.Uy[lane]);
-      const BlockRanges r = block_ranges(P, X, Y, pc.R[lane], kBlock);
+    if (held) {
+      X = own.X;
+      Y = own.Y;
+      if (advance) advance_position(P, X, Y, own.Ux, own.Uy);
+      const BlockRanges r = block_ranges(P, X, Y, own.R, kBlock);
       cand = r.contains(b);
       if (r.n == 0 && b == 0) atomicOr(flags, kFlagUnstable);
       store = advance && (r.n > 0 ? b == r.lo[0] : b == 0);
@@ -769,8 +808,8 @@ __device__ void scan_block(BlockParticles& bp, const Params& P, int b,
       bp.slot[rank] = lane * P.nblocks + b;
       bp.X[rank] = X;
       bp.Y[rank] = Y;
-      bp.R[rank] = pc.R[lane];
-      bp.Tp[rank] = pc.Tinit[lane];
+      bp.R[rank] = own.R;
+      bp.Tp[rank] = own.Tinit;
     }
     const unsigned long long mw = __ballot(cand || store);
     const int wrank = __popcll(mw & below);
@@ -788,8 +827,14 @@ __device__ void scan_block(BlockParticles& bp, const Params& P, int b,
   const int nwork = s_nwork;
   for (int k = wave; k < nwork; k += 4) {
     const int p = s_work_pid[k], r = s_work_rank[k];
+    const POne sp = lane_one(own, p);
     if (advance) {
-      const PUpd u = particle_update(P, cur, pc, partial, have, p, lane);
+      double cx, cy, fx, fy, tz;
+      repulsion_lanes(P, sp.X, sp.Y, sp.R, own.X, own.Y, own.R,
+                      held && lane != p, cx, cy);
+      reduce_partials_at(P, sp.X, sp.Y, sp.R, partial, have, p, lane, fx, fy,
+                         tz);
+      const PUpd u = particle_update_one(P, sp, fx, fy, tz, cx, cy);
       if (lane == 0) {
         if (r >= 0) {
           bp.Ux[r] = u.Ux;
@@ -803,16 +848,16 @@ __device__ void scan_block(BlockParticles& bp, const Params& P, int b,
         // same arithmetic as that step's scan_task_tile)
         double Xn = u.X, Yn = u.Y;
         advance_position(P, Xn, Yn, u.Ux, u.Uy);
-        const BlockRanges r = block_ranges(P, Xn, Yn, pc.R[p], kBlock);
-        for (int j = lane; j < r.count(); j += 64)
-          atomicAdd(&tcount_next[r.at(j)], 1);
+        const BlockRanges rn = block_ranges(P, Xn, Yn, sp.R, kBlock);
+        for (int j = lane; j < rn.count(); j += 64)
+          atomicAdd(&tcount_next[rn.at(j)], 1);
         // a centre the band-box logic cannot place: no tile serves it
-        if (r.n == 0 && lane == 0) atomicOr(flags, kFlagUnstable);
+        if (rn.n == 0 && lane == 0) atomicOr(flags, kFlagUnstable);
       }
     } else if (lane == 0 && r >= 0) {
-      bp.Ux[r] = cur.Ux[p];
-      bp.Uy[r] = cur.Uy[p];
-      bp.Om[r] = cur.Om[p];
+      bp.Ux[r] = sp.Ux;
+      bp.Uy[r] = sp.Uy;
+      bp.Om[r] = sp.Om;
     }
   }
   __syncthreads();

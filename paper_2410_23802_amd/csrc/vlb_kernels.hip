@@ -222,8 +222,9 @@ __global__ __launch_bounds__(256) void k_particles(
   // cell in that box, and a particle's band box holds its centre cell.  The
   // wave marks them in a bitmap, gathers their positions into LDS, and
   // each lane then visits its own (q = lane, lane + 64, ...) in ascending
-  // order, as repulsion() does over all particles -- the others are out
-  // of reach and add nothing, so the sums are those of the all-pairs loop.
+  // order, as a loop over all particles q = lane, lane + 64, ... would --
+  // the others are out of reach and add nothing, so the sums are those of
+  // that all-pairs loop.
   // Without those lists (or with more particles than the bitmap holds)
   // the block stages all particles in LDS, kStage at a time.
   double cx = 0.0, cy = 0.0;
