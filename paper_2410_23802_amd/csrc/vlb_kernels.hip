@@ -41,10 +41,20 @@ __attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 5))) void k_step(
   } else {
     tile = stream_tile(P, blockIdx.x - P.nfirst);
     if (tile >= P.nblocks) return;
-    ptile = !SCAN && P.np > 0 && B.L.cnt[tile] != 0;    // uniform in the block
+    ptile = false;
+  }
+  // list form: the tile's count decides its role; entry t of its list is
+  // read together with it, before the count is known (kListEntryAhead)
+  int lcnt = 0;
+  int2 lent = make_int2(0, 0);
+  if (!SCAN && P.np > 0) {
+    if (kListEntryAhead<PREC> && threadIdx.x < kListCap)
+      lent = B.L.ent[(size_t)tile * kListCap + threadIdx.x];
+    lcnt = B.L.cnt[tile];                                // uniform
+    ptile = lcnt != 0;
   }
   step_task<PREC, OUT, SCAN, SCAN && counted_tiles(PREC, PAIR)>(
-      P, H, B, have, tile, ptile, sh);
+      P, H, B, have, tile, ptile, sh, lcnt, lent);
 }
 
 // -------------------------------------------------------------------------
@@ -151,24 +161,24 @@ __device__ __forceinline__ void mark_listed(const Lists& L, int f0, int n0,
                                             unsigned long long* marks) {
   const int nt = n0 + n1;
   for (int g = 0; g < nt; g += 4) {
-    int tt[4], n[4];
+    int tt[4], n[4], q[4][8];
+    // the counts and the first eight entries, all issued before any is
+    // used (entries past a count are stale and left out below)
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = g + u;
       tt[u] = i < n0 ? f0 + i : f1 + (i - n0);
-      n[u] = i < nt ? min(L.ocnt[tt[u]], kListCap) : 0;
-    }
-    int q[4][8];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
+      n[u] = i < nt ? L.ocnt[tt[u]] : 0;
 #pragma unroll
       for (int e = 0; e < 8; ++e)
-        q[u][e] = e < n[u] ? L.oent[(size_t)tt[u] * kListCap + e].x : -1;
+        q[u][e] = i < nt ? L.oent[(size_t)tt[u] * kListCap + e].x : 0;
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
+      n[u] = min(n[u], kListCap);
 #pragma unroll
       for (int e = 0; e < 8; ++e)
-        if (q[u][e] >= 0)
+        if (e < n[u])
           atomicOr(&marks[q[u][e] >> 6], 1ull << (q[u][e] & 63));
       for (int e = 8; e < n[u]; ++e) {
         const int qq = L.oent[(size_t)tt[u] * kListCap + e].x;
@@ -196,6 +206,10 @@ __global__ __launch_bounds__(256) void k_particles(
   const int lane = threadIdx.x & 63;
   const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
   const bool mine = p < P.np;          // uniform in the wave
+  // the particle's stored state, loaded up front (the update needs it only
+  // after the repulsion)
+  POne own = {};
+  if (mine) own = load_one(cur, pc, p);
 
   // The momentum-exchange sums.  List form: the slot count, then the first
   // 64 slots' partials, are loaded now and added after the repulsion, in
@@ -230,8 +244,7 @@ __global__ __launch_bounds__(256) void k_particles(
   double cx = 0.0, cy = 0.0;
   if (mode == kModeUpdate && P.coll_range > 0.0) {   // uniform in the grid
     __shared__ PassShared psh;
-    const double Xp = mine ? cur.X[p] : 0.0, Yp = mine ? cur.Y[p] : 0.0;
-    const double Rp = mine ? pc.R[p] : 0.0;
+    const double Xp = own.X, Yp = own.Y, Rp = own.R;
     if (L.ocnt && P.np <= 64 * kWords) {
       auto& marks = psh.nb.marks;
       auto& wbase = psh.nb.wbase;
@@ -377,16 +390,16 @@ __global__ __launch_bounds__(256) void k_particles(
     }
     return;
   }
-  double nX = cur.X[p], nY = cur.Y[p];
+  double nX = own.X, nY = own.Y;
   if (mode == kModeUpdate) {
-    const PUpd u = particle_update_sums(P, cur, pc, p, fx, fy, tz, cx, cy);
+    const PUpd u = particle_update_one(P, own, fx, fy, tz, cx, cy);
     if (lane == 0) store_particle(next, p, u);
     nX = u.X;
     nY = u.Y;
   }
 
   // ---- block lists for the band box at the new position
-  const double R = pc.R[p];
+  const double R = own.R;
   const bool ok = centre_ok(P, nX, nY);
   if (!ok && lane == 0) atomicOr(flags, kFlagUnstable);
   int i0 = 0, i1 = -1, j0 = 0, j1 = -1;
