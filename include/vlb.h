@@ -106,6 +106,12 @@ typedef struct {
   double rho_s;              /* solid density                                 */
   double T_init;             /* initial particle temperature                  */
   int32_t fixed;             /* 1: velocity held (prescribed motion)          */
+  int32_t hold_T;            /* 1: temperature held at T_init (a particle of
+                                fixed temperature, Sec. 3.3; the rule that
+                                holds it is this library's reading: the
+                                energy populations of the cells it covers
+                                take the volumetric step, share-weighted,
+                                towards their equilibrium at T_init)          */
 } vlb_particle_desc;
 
 typedef struct {

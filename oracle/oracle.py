@@ -70,7 +70,8 @@ class _Domain(ctypes.Structure):
 class _Particle(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("x", "y", "theta", "ux", "uy", "omega", "radius", "rho_s",
-                 "T_init")] + [("fixed", ctypes.c_int32)]
+                 "T_init")] + [("fixed", ctypes.c_int32),
+                               ("hold_T", ctypes.c_int32)]
 
 
 class _PState(ctypes.Structure):
@@ -161,6 +162,7 @@ def _particles_struct(ps):
                      "T_init"):
             setattr(arr[k], name, float(p[name]))
         arr[k].fixed = int(p["fixed"])
+        arr[k].hold_T = int(p.get("hold_T", 0))
     return arr
 
 

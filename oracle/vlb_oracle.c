@@ -25,6 +25,7 @@
  *   3  [df_s/dt] at n+1                                        (eq. dfs_dt)
  *   4  streaming of f and g, with wall rules                   (eq. lbe.rho.str, lbe.e.str)
  *   5  volumetric no-slip step and momentum exchange           (eq. fi, Sec. 2.3)
+ *   5b held particle temperatures (a reading)                  (Sec. 3.3)
  *   6  per-cell properties                                     (Sec. 2.2, eq. lambda)
  *   7  macroscopic rho, u, T, eps, q_c                         (eq. rho.rhou, eq. e)
  *   8  flow MRT collision with the discrete force term         (eq. lbe.rho.col)
@@ -80,6 +81,7 @@ struct or_state {
   double *X, *Y, *th, *Ux, *Uy, *Om, *Uxp, *Uyp, *Omp;
   double *R, *rhos, *Tp0;
   int *fixed;
+  int *hold;  /* 1: temperature held at Tp0 (stage 5b) */
   double *Fx, *Fy, *Tz; /* momentum-exchange force/torque, current step */
   double *Tmean, *Tmin, *E, *fssum, *Fabs;
   /* fields */
@@ -314,6 +316,7 @@ void or_destroy(or_state* s) {
                   s->dPy};
   for (size_t k = 0; k < sizeof(dp) / sizeof(dp[0]); ++k) free(dp[k]);
   free(s->fixed);
+  free(s->hold);
   free(s->cnt);
   free(s->ids);
   free(s->full);
@@ -352,6 +355,7 @@ int or_create(const or_domain* d, int32_t np, const or_particle* p,
   for (size_t k = 0; k < sizeof(dp) / sizeof(dp[0]); ++k)
     *dp[k] = (double*)zalloc(sizeof(double) * n);
   s->fixed = (int*)zalloc(sizeof(int) * n);
+  s->hold = (int*)zalloc(sizeof(int) * n);
   s->f = (double*)zalloc(sizeof(double) * Q * nc);
   s->g = (double*)zalloc(sizeof(double) * Q * nc);
   s->fst = (double*)zalloc(sizeof(double) * Q * nc);
@@ -382,6 +386,7 @@ int or_create(const or_domain* d, int32_t np, const or_particle* p,
     s->rhos[k] = p[k].rho_s;
     s->Tp0[k] = p[k].T_init;
     s->fixed[k] = p[k].fixed;
+    s->hold[k] = p[k].hold_T;
   }
   *out = s;
   return OR_OK;
@@ -682,6 +687,33 @@ static int update_cell(or_state* s, size_t c, int i, int j) {
       jx += EX[q] * f[q];
       jy += EY[q] * f[q];
     }
+  }
+
+  /* ---- stage 5b: particles whose temperature is held (Sec. 3.3's cold
+   * particle of fixed temperature).  Reading (the paper does not give the
+   * rule): the energy distribution gets the volumetric step that eq. fi
+   * gives the flow distribution, g = (1 - sum_h f_s,p) g* + sum_h f_s,p
+   * g^eq(c_v T_p, T_p), the sums over the held particles p reaching the
+   * cell, c_v the cell's heat capacity of stage 6 (as eq. fi takes the
+   * cell's rho); a cell wholly inside one is set to the solid's
+   * equilibrium at T_p, and a uniform temperature stays uniform.  It acts
+   * before the macroscopic quantities of stage 7. ---- */
+  {
+    double phi = 0.0, gh[Q];
+    double cv_cell = (1.0 - fs) * cvf + fs * cvs;
+    for (int q = 0; q < Q; ++q) gh[q] = 0.0;
+    for (int k = 0; k < s->cnt[c]; ++k) {
+      size_t sl = c * K + k;
+      int p = s->ids[sl];
+      if (!s->hold[p]) continue;
+      double n[Q], geq[Q];
+      neq_energy(cv_cell * s->Tp0[p], s->Tp0[p], cref, n);
+      mat_vec(s->Minv, n, geq);
+      phi += s->fsp[sl];
+      for (int q = 0; q < Q; ++q) gh[q] += s->fsp[sl] * geq[q];
+    }
+    if (phi > 0.0)
+      for (int q = 0; q < Q; ++q) g[q] = (1.0 - phi) * g[q] + gh[q];
   }
 
   /* ---- stage 6: per-cell properties (Sec. 2.2) ---- */

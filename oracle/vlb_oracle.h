@@ -56,6 +56,7 @@ typedef struct {
 typedef struct {
   double x, y, theta, ux, uy, omega, radius, rho_s, T_init;
   int32_t fixed;             /* 1: velocity prescribed (not integrated)      */
+  int32_t hold_T;            /* 1: temperature held at T_init (stage 5b)     */
 } or_particle;
 
 /* Per-particle state and outputs (stage 10 of a step). */

@@ -464,7 +464,7 @@ vlb_status vlb_init(vlb_ctx* c) {
       cst[k] = p.radius;
       cst[n + k] = p.rho_s;
       cst[2 * n + k] = p.T_init;
-      fx[k] = p.fixed ? 1 : 0;
+      fx[k] = (p.fixed ? 1 : 0) | (p.hold_T ? 2 : 0);
     }
     HIP_TRY(c, hipMemcpyAsync(c->pmem[0], host.data(), host.size() * 8,
                               hipMemcpyHostToDevice, c->stream));
@@ -724,7 +724,7 @@ vlb_status vlb_load(vlb_ctx* c, const void* buf, size_t len) {
       cst[k] = c->parts[k].radius;
       cst[n + k] = c->parts[k].rho_s;
       cst[2 * n + k] = c->parts[k].T_init;
-      fx[k] = c->parts[k].fixed ? 1 : 0;
+      fx[k] = (c->parts[k].fixed ? 1 : 0) | (c->parts[k].hold_T ? 2 : 0);
     }
     HIP_TRY(c, hipMemcpyAsync(c->pmem[0], o, 12 * n * 8, H2D, c->stream)); o += 12 * n * 8;
     HIP_TRY(c, hipMemcpyAsync(c->pslot[0], o, n * 4, H2D, c->stream)); o += n * 4;

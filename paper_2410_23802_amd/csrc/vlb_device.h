@@ -657,7 +657,7 @@ __device__ PUpd particle_update_one(const Params& P, const POne& s,
   u.Ux = Ux;
   u.Uy = Uy;
   u.Om = Om;
-  if (!s.fixed) {
+  if (!(s.fixed & 1)) {
     const double Finx = -Min * (Ux - s.Uxp);
     const double Finy = -Min * (Uy - s.Uyp);
     const double Tin = -Iin * (Om - s.Omp);
@@ -701,8 +701,10 @@ __device__ __forceinline__ void store_particle(PState& s, int p,
 
 struct BlockParticles {
   int cnt;
+  int nheld;            // of them, particles whose temperature is held
   int pid[kListCap];
   int slot[kListCap];
+  int held[kListCap];   // 1: the particle's temperature is held (at Tp)
   double X[kListCap], Y[kListCap], R[kListCap];
   double Ux[kListCap], Uy[kListCap], Om[kListCap], Tp[kListCap];
 };
@@ -718,6 +720,7 @@ __device__ __forceinline__ void load_block_list(BlockParticles& bp, int* tmp,
       n = kListCap;
     }
     bp.cnt = n;
+    bp.nheld = 0;
   }
   __syncthreads();
   const int n = bp.cnt;
@@ -740,6 +743,8 @@ __device__ __forceinline__ void load_block_list(BlockParticles& bp, int* tmp,
     bp.Uy[rank] = pn.Uy[e.x];
     bp.Om[rank] = pn.Om[e.x];
     bp.Tp[rank] = pc.Tinit[e.x];
+    bp.held[rank] = (pc.fixed[e.x] >> 1) & 1;
+    if (bp.held[rank]) atomicAdd(&bp.nheld, 1);
   }
   __syncthreads();
 }
@@ -763,6 +768,7 @@ __device__ __forceinline__ void load_block_list_known(BlockParticles& bp,
   if (t == 0) {
     if (cnt > kListCap) atomicOr(flags, kFlagListFull);
     bp.cnt = n;
+    bp.nheld = 0;
   }
   if (t < n) tmp[t] = e.x;
   __syncthreads();
@@ -778,6 +784,8 @@ __device__ __forceinline__ void load_block_list_known(BlockParticles& bp,
     bp.Uy[rank] = pn.Uy[e.x];
     bp.Om[rank] = pn.Om[e.x];
     bp.Tp[rank] = pc.Tinit[e.x];
+    bp.held[rank] = (pc.fixed[e.x] >> 1) & 1;
+    if (bp.held[rank]) atomicAdd(&bp.nheld, 1);
   }
   __syncthreads();
 }
@@ -848,6 +856,7 @@ __device__ void scan_block(BlockParticles& bp, const Params& P, int b,
       bp.Y[rank] = Y;
       bp.R[rank] = own.R;
       bp.Tp[rank] = own.Tinit;
+      bp.held[rank] = (own.fixed >> 1) & 1;
     }
     const unsigned long long mw = __ballot(cand || store);
     const int wrank = __popcll(mw & below);
@@ -856,8 +865,10 @@ __device__ void scan_block(BlockParticles& bp, const Params& P, int b,
       s_work_rank[wrank] = cand ? rank : -1;
       s_work_store[wrank] = store ? 1 : 0;
     }
+    const unsigned long long mh = __ballot(cand && ((own.fixed >> 1) & 1));
     if (lane == 0) {
       bp.cnt = __popcll(mc);
+      bp.nheld = __popcll(mh);
       s_nwork = __popcll(mw);
     }
   }
@@ -1040,6 +1051,7 @@ __device__ __forceinline__ void inverse(const C* m, C* o) {
 template <class C>
 struct PSums {
   C S0, S1x, S1y, S2xx, S2yy, S2xy;
+  C H0, H1;   // over particles whose temperature is held: sum f_s,p, sum f_s,p T_p
 };
 
 // The storage values one lane loads for its cell of a tile (the pulled
@@ -1149,6 +1161,7 @@ __device__ __forceinline__ void update_cell(
   // ---- particles: solid fraction, u_s, momentum exchange (Sec. 2.3)
   PSums<C> S;
   S.S0 = S.S1x = S.S1y = S.S2xx = S.S2yy = S.S2xy = (C)0;
+  S.H0 = S.H1 = (C)0;
   part(act, x, y, rho, jxs, jys, S);
 
   // ---- volumetric no-slip step in moment space (eq. fi):
@@ -1189,6 +1202,20 @@ __device__ __forceinline__ void update_cell(
   C n[9];
   moments(g, n);
   const C cT0 = H.cT0s;
+  // ---- particles whose temperature is held (a reading; the paper gives
+  // no rule): the volumetric step of the energy distribution, g = (1 -
+  // sum_h f_s,p) g* + sum_h f_s,p g^eq(c_v T_p, T_p), with c_v the cell's
+  // heat capacity.  g^eq is linear in (eps, T), so the held particles
+  // enter through H0 = sum_h f_s,p and H1 = sum_h f_s,p T_p; in moments,
+  // minus the reference c_ref T_0 (1, -2, 1, 0, ..., 0)
+  if (S.H0 != (C)0) {
+    const C wh = (C)1 - S.H0, e1 = cv * S.H1, c1 = H.cref * S.H1;
+    n[0] = wh * n[0] - S.H0 * cT0 + e1;
+    n[1] = wh * n[1] + 2 * S.H0 * cT0 + (-4 * e1 + 2 * c1);
+    n[2] = wh * n[2] - S.H0 * cT0 + (4 * e1 - 3 * c1);
+#pragma unroll
+    for (int k = 3; k < 9; ++k) n[k] = wh * n[k];
+  }
   const C G = n[0] + cT0;                          // sum g_i
   const C gcoef = H.grad_coef * sig_j;             // -3 / (c_ref tau_g)
   const C gTx = gcoef * n[3], gTy = gcoef * n[5];
@@ -1360,7 +1387,8 @@ struct TileShared {
   double red[kListCap][4][3];  // per slot and wave: force x, y, torque
   C S[6][kBlock];      // f_s and sum_p f_s,p (u_s, u_s u_s), shares scaled
   C S0raw[kBlock];     // sum_p f_s,p before scaling
-  C M[3][kBlock];      // rho, jx*, jy* after streaming
+  C M[3][kBlock];      // rho, jx*, jy* after streaming (before the lattice
+                       // update: the held sums H0, H1 of phase 1)
   // the first kShareCache particles reaching each cell (slot order): slot
   // and share, so the momentum exchange need not recompute the areas
   C share[kShareCache][kBlock];
@@ -1457,6 +1485,7 @@ __device__ __forceinline__ void step_task(
   const int cx = (act0 ? c0 : P.N - 1) - cy * P.nx;
 
   unsigned long long wmask = 0ull;  // particle tiles: the wave's particles
+  bool anyheld = false;             // particle tiles: a held particle among them
   // ---- phase 1 (particle tiles): particles of the tile, and per cell the
   // solid fraction f_s = sum_p f_s,p and sum_p f_s,p (u_s, u_s u_s); where
   // overlapping disks cover more than the cell the shares are scaled to
@@ -1474,6 +1503,7 @@ __device__ __forceinline__ void step_task(
     // band box meets the wave's cells), whether they cover it wholly; the
     // first kShareCache are kept
     const int cnt = sh.bp.cnt;
+    anyheld = sh.bp.nheld > 0;
     wmask = cnt > 1 ? wave_particle_mask(P, sh.bp, cnt, tile, t >> 6, lane)
                     : (unsigned long long)cnt;   // one particle: no test
     const double xn = (double)cx + 0.5, yn = (double)cy + 0.5;
@@ -1539,6 +1569,7 @@ __device__ __forceinline__ void step_task(
     // kShareCache particles in one cell) the geometry is computed here
     PSums<C> S;
     S.S0 = S.S1x = S.S1y = S.S2xx = S.S2yy = S.S2xy = (C)0;
+    S.H0 = S.H1 = (C)0;
     const int ncached = nin < kShareCache ? nin : kShareCache;
     for (int e = 0; e < ncached; ++e) {
       const int k = sh.slot[e][t];
@@ -1552,6 +1583,10 @@ __device__ __forceinline__ void step_task(
       S.S2xx += a * ux * ux;
       S.S2yy += a * uy * uy;
       S.S2xy += a * ux * uy;
+      if (anyheld && sh.bp.held[k]) {
+        S.H0 += a;
+        S.H1 += a * (C)sh.bp.Tp[k];
+      }
     }
     if (nin > kShareCache) {
       for (int k = sh.slot[kShareCache - 1][t] + 1; k < cnt; ++k) {
@@ -1567,6 +1602,10 @@ __device__ __forceinline__ void step_task(
           S.S2xx += a * ux * ux;
           S.S2yy += a * uy * uy;
           S.S2xy += a * ux * uy;
+          if (anyheld && sh.bp.held[k]) {
+            S.H0 += a;
+            S.H1 += a * (C)sh.bp.Tp[k];
+          }
         }
       }
     }
@@ -1576,11 +1615,17 @@ __device__ __forceinline__ void step_task(
     if (S.S0 > (C)1) {
       const C inv = (C)1 / S.S0;
       S.S1x *= inv; S.S1y *= inv; S.S2xx *= inv; S.S2yy *= inv;
-      S.S2xy *= inv;
+      S.S2xy *= inv; S.H0 *= inv; S.H1 *= inv;
       S.S0 = (C)1;
     }
     sh.S[0][t] = S.S0; sh.S[1][t] = S.S1x; sh.S[2][t] = S.S1y;
     sh.S[3][t] = S.S2xx; sh.S[4][t] = S.S2yy; sh.S[5][t] = S.S2xy;
+    // the held sums wait in M, which the lattice update fills only after
+    // part() has read them
+    if (anyheld) {
+      sh.M[0][t] = S.H0;
+      sh.M[1][t] = S.H1;
+    }
   }
 
   // ---- phase 2: the lattice update
@@ -1626,6 +1671,10 @@ __device__ __forceinline__ void step_task(
     if (ptile) {
       S.S0 = sh.S[0][t]; S.S1x = sh.S[1][t]; S.S1y = sh.S[2][t];
       S.S2xx = sh.S[3][t]; S.S2yy = sh.S[4][t]; S.S2xy = sh.S[5][t];
+      if (anyheld) {
+        S.H0 = sh.M[0][t];
+        S.H1 = sh.M[1][t];
+      }
       sh.M[0][t] = rho; sh.M[1][t] = jxs; sh.M[2][t] = jys;
     }
   };

@@ -104,7 +104,7 @@ struct PState {
 
 struct PConst {
   const double *R, *rhos, *Tinit;
-  const int* fixed;
+  const int* fixed;   // bit 0: velocity held; bit 1: temperature held at Tinit
 };
 
 // Per-tile particle lists of the list form.  The counts are double

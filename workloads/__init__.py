@@ -18,7 +18,8 @@ Descriptor keys (both sides read the same dict):
   tau_f, rho_f, cv_f, lambda_f, R_lambda, R_cv, body_force, gravity, beta,
   T_ref, sigma_rule (0: Lambda_g = 1/4 rule, 1: sigma_e = 1), coll_range,
   coll_stiff_pp, coll_stiff_pw, init_rho, init_u, init_T, kmax.
-Particle keys: x, y, theta, ux, uy, omega, radius, rho_s, T_init, fixed.
+Particle keys: x, y, theta, ux, uy, omega, radius, rho_s, T_init, fixed,
+hold_T (temperature held at T_init).
 """
 from __future__ import annotations
 
@@ -79,10 +80,11 @@ def walls(d: dict, which=(XLO, XHI, YLO, YHI), thermal="adiabatic",
 
 
 def particle(x, y, radius, rho_s=1.0, T_init=0.0, ux=0.0, uy=0.0, omega=0.0,
-             theta=0.0, fixed=False) -> dict:
+             theta=0.0, fixed=False, hold_T=False) -> dict:
     return dict(x=float(x), y=float(y), theta=float(theta), ux=float(ux),
                 uy=float(uy), omega=float(omega), radius=float(radius),
-                rho_s=float(rho_s), T_init=float(T_init), fixed=int(bool(fixed)))
+                rho_s=float(rho_s), T_init=float(T_init), fixed=int(bool(fixed)),
+                hold_T=int(bool(hold_T)))
 
 
 def collision_params(rho_r: float, radius: float, g: float, zeta=2.0,
