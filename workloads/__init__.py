@@ -139,6 +139,30 @@ def c2_channel(nx=200, ny=4000) -> tuple[dict, list]:
     return d, [p]
 
 
+def e5_held_channel(Gr, length_D=180, start_D=5, D=20.0) -> tuple[dict, list]:
+    """The paper's sedimentation of one cold particle of fixed temperature
+    (Sec. 3.3): a channel of width L = 4 D with walls held at T_h = 1, a disk
+    of diameter D = 20 cells starting D / 2 left of the centre line (x =
+    1.5 D) and held at T_c = 0, density ratio 1.00232, Re = 40.5, Pr = 0.7,
+    the given Gr, tau_f = 0.53, R_lambda = R_cv = 1, T_ref = T_h.  The paper
+    gives no channel length: length_D diameters here, the disk starting
+    start_D diameters below the top.  U_ref = Re nu / D sets |g| and Gr
+    sets beta, as for e6_cht_channel."""
+    tau_f, Pr, rho_r, Re = 0.53, 0.7, 1.00232, 40.5
+    nu = viscosity(tau_f)
+    U = Re * nu / D
+    g = U * U / ((rho_r - 1.0) * math.pi * D / 2.0)
+    nx, ny = int(round(4 * D)), int(round(length_D * D))
+    d = domain(nx, ny, tau_f=tau_f, lambda_f=nu / Pr, R_lambda=1.0,
+               R_cv=1.0, gravity=(0.0, -g),
+               beta=beta_from_grashof(Gr, g, 1.0, D, nu), T_ref=1.0,
+               init_T=1.0, **collision_params(rho_r, D / 2, g))
+    d = walls(d, thermal="dirichlet", T_wall=1.0)
+    p = particle(1.5 * D, ny - start_D * D, D / 2, rho_s=rho_r, T_init=0.0,
+                 hold_T=True)
+    return d, [p]
+
+
 def e6_cht_channel(R_lambda=1.0, R_cv=1.0, length_D=60, start_D=10,
                    D=20.0) -> tuple[dict, list]:
     """The paper's sedimentation of one cold particle with conjugate heat
