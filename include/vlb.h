@@ -88,6 +88,11 @@ typedef struct {
   double  beta, T_ref;
   int32_t sigma_rule;        /* 0: (1/sigma_j - 1/2)(1/sigma_e - 1/2) = 1/4;
                                 1: sigma_e = 1 (the dense case of Sec. 3.5)   */
+  int32_t fluid_gravity;     /* 0: situation I of Sec. 3.2 (gravity as above);
+                                1: situation II: the fluid's share also
+                                carries rho_f g, the particles feel
+                                rho_s V g, and the initial density is the
+                                hydrostatic rho_0 + 3 rho_f g.(x - centre)  */
   double  coll_range;        /* repulsion range zeta; 0 disables collisions   */
   double  coll_stiff_pp;     /* particle-particle repulsion at contact        */
   double  coll_stiff_pw;     /* particle-wall repulsion at contact            */

@@ -59,6 +59,7 @@ class _Domain(ctypes.Structure):
         ("body_force", ctypes.c_double * 2), ("gravity", ctypes.c_double * 2),
         ("beta", ctypes.c_double), ("T_ref", ctypes.c_double),
         ("sigma_rule", ctypes.c_int32),
+        ("fluid_gravity", ctypes.c_int32),
         ("coll_range", ctypes.c_double), ("coll_stiff_pp", ctypes.c_double),
         ("coll_stiff_pw", ctypes.c_double),
         ("init_rho", ctypes.c_double), ("init_u", ctypes.c_double * 2),
@@ -151,6 +152,7 @@ def _domain_struct(d: dict) -> _Domain:
     s.gravity[0], s.gravity[1] = d["gravity"]
     s.init_u[0], s.init_u[1] = d["init_u"]
     s.sigma_rule = int(d["sigma_rule"])
+    s.fluid_gravity = int(d.get("fluid_gravity", 0))
     s.kmax = int(d["kmax"])
     return s
 

@@ -506,8 +506,12 @@ static void particle_update(or_state* s) {
       double Tin = -Iin * (Om - s->Omp[i]);
       double Foutx = s->Fx[i] - Finx, Fouty = s->Fy[i] - Finy;
       double Tout = s->Tz[i] - Tin;
-      double Fcx = Foutx + (s->rhos[i] - d->rho_f) * V * d->gravity[0] + nFx[i];
-      double Fcy = Fouty + (s->rhos[i] - d->rho_f) * V * d->gravity[1] + nFy[i];
+      /* gravity: (rho_s - rho_f) V g (situation I of Sec. 3.2), or rho_s V
+       * g when the fluid carries its own weight (situation II; the
+       * buoyancy then comes through the momentum exchange) */
+      double rg = d->fluid_gravity ? s->rhos[i] : s->rhos[i] - d->rho_f;
+      double Fcx = Foutx + rg * V * d->gravity[0] + nFx[i];
+      double Fcy = Fouty + rg * V * d->gravity[1] + nFy[i];
       nUx = Ux + Fcx / Mp;
       nUy = Uy + Fcy / Mp;
       nOm = Om + Tout / Ip;
@@ -753,8 +757,12 @@ static int update_cell(or_state* s, size_t c, int i, int j) {
      * together; eq. rho.rhou gives u = (j + F/2)/rho, and the implicit T of
      * Sec. 2.2 then is linear in T. */
     double wf = 1.0 - fs;
-    double ax = wf * (d->body_force[0] + d->rho_f * d->beta * d->T_ref * d->gravity[0]);
-    double ay = wf * (d->body_force[1] + d->rho_f * d->beta * d->T_ref * d->gravity[1]);
+    /* situation II of Sec. 3.2 adds the fluid's own weight rho_f g */
+    double gw = d->fluid_gravity ? d->rho_f : 0.0;
+    double ax = wf * (d->body_force[0] + gw * d->gravity[0] +
+                      d->rho_f * d->beta * d->T_ref * d->gravity[0]);
+    double ay = wf * (d->body_force[1] + gw * d->gravity[1] +
+                      d->rho_f * d->beta * d->T_ref * d->gravity[1]);
     double bx = -wf * d->rho_f * d->beta * d->gravity[0];
     double by = -wf * d->rho_f * d->beta * d->gravity[1];
     double num = G - 0.5 * cv * ((jx + 0.5 * ax) * gTx + (jy + 0.5 * ay) * gTy) / rho;
@@ -898,12 +906,23 @@ int or_init(or_state* s) {
     if (st != OR_OK) return st;
   }
   double cvf = d->cv_f, cvs = cv_solid(s), cref = c_ref(s);
-  /* Reading of the initial state: rho = rho_0; u and the internal energy
-   * are the volume-weighted mixtures of the fluid and particle values;
-   * f = f^eq(rho, u), g = g^eq(eps, T) are taken as the post-collision
-   * populations at n = 0; [df_s/dt] = q_c = 0. */
+  /* Reading of the initial state: rho = rho_0 (situation II of Sec. 3.2:
+   * the hydrostatic rho_0 + 3 rho_f g.(x - x_m), from grad p = rho_f g
+   * with p = rho c_s^2, c_s^2 = 1/3, for the constant force density rho_f
+   * g on the fluid, x_m the domain's centre; the paper asks only that the
+   * initialisation consider the pressure gradient); u and the internal
+   * energy are the volume-weighted mixtures of the fluid and particle
+   * values; f = f^eq(rho, u), g = g^eq(eps, T) are taken as the
+   * post-collision populations at n = 0; [df_s/dt] = q_c = 0. */
   for (size_t c = 0; c < nc; ++c) {
     double fs = s->fs[c];
+    double rho0 = d->init_rho;
+    if (d->fluid_gravity) {
+      int ci = (int)(c % (size_t)d->nx), cj = (int)(c / (size_t)d->nx);
+      double hx = (ci + 0.5) - 0.5 * d->nx, hy = (cj + 0.5) - 0.5 * d->ny;
+      rho0 = d->init_rho +
+             3.0 * d->rho_f * (d->gravity[0] * hx + d->gravity[1] * hy);
+    }
     double ux, uy, T, eps;
     double cv = (1.0 - fs) * cvf + fs * cvs;
     if (s->hk.fs_from_array) {
@@ -929,7 +948,7 @@ int or_init(or_state* s) {
       }
     }
     double feq[Q], n[Q], geq[Q];
-    feq_velocity(s->Minv, d->init_rho, ux, uy, feq);
+    feq_velocity(s->Minv, rho0, ux, uy, feq);
     neq_energy(eps, T, cref, n);
     mat_vec(s->Minv, n, geq);
     for (int q = 0; q < Q; ++q) {
@@ -937,7 +956,7 @@ int or_init(or_state* s) {
       s->g[q * nc + c] = geq[q];
     }
     s->dfs[c] = 0.0;
-    s->rho[c] = d->init_rho;
+    s->rho[c] = rho0;
     s->ux[c] = ux;
     s->uy[c] = uy;
     s->T[c] = T;

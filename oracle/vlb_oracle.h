@@ -46,6 +46,7 @@ typedef struct {
   double  gravity[2];
   double  beta, T_ref;       /* Boussinesq buoyancy -rho_f g beta (T-T_ref)  */
   int32_t sigma_rule;        /* 0: (1/sj-1/2)(1/se-1/2)=1/4; 1: se=1         */
+  int32_t fluid_gravity;     /* 1: situation II of Sec. 3.2                  */
   double  coll_range;        /* repulsion range zeta (cells)                 */
   double  coll_stiff_pp;     /* particle-particle force at contact           */
   double  coll_stiff_pw;     /* particle-wall force at contact               */

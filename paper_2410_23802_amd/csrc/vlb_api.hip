@@ -116,6 +116,8 @@ static vlb_status validate(const vlb_domain_desc* d, std::string& why) {
            VLB_EINVAL;
   if (d->sigma_rule != 0 && d->sigma_rule != 1)
     return why = "sigma_rule must be 0 or 1", VLB_EINVAL;
+  if (d->fluid_gravity != 0 && d->fluid_gravity != 1)
+    return why = "fluid_gravity must be 0 or 1", VLB_EINVAL;
   if (d->kmax < 1 || d->kmax > 8) return why = "kmax must be in 1..8", VLB_EINVAL;
   if (d->precision < VLB_FP64 || d->precision > VLB_BF16_SHIFT)
     return why = "unknown precision", VLB_EINVAL;
@@ -181,6 +183,7 @@ static void derive_params(vlb_ctx* c) {
   P.pery = d.face_flow[VLB_FACE_YLO] == VLB_PERIODIC;
   P.kmax = d.kmax;
   P.sigma_rule = d.sigma_rule;
+  P.fluid_gravity = d.fluid_gravity;
   // flow relaxation (Sec. 3): s_e = s_eps = 1.25, s_p = 1/tau_f,
   // (1/s_p - 1/2)(1/s_q - 1/2) = 1/12
   P.s_e = 1.25;
@@ -195,8 +198,12 @@ static void derive_params(vlb_ctx* c) {
   // eq. lambda with alpha1 = -2: lambda/rho_f = c_ref (tau_g - 1/2)/3
   P.taug_coef = 3.0 / (d.rho_f * P.cref);
   // fluid force (1 - f_s)[F_ext - rho_f g beta (T - T_ref)] = (1-f_s)(A0 + B0 T)
-  P.A0x = d.body_force[0] + d.rho_f * d.beta * d.T_ref * d.gravity[0];
-  P.A0y = d.body_force[1] + d.rho_f * d.beta * d.T_ref * d.gravity[1];
+  // situation II of Sec. 3.2: the fluid's share also carries rho_f g
+  const double gw = d.fluid_gravity ? d.rho_f : 0.0;
+  P.A0x = d.body_force[0] + gw * d.gravity[0] +
+          d.rho_f * d.beta * d.T_ref * d.gravity[0];
+  P.A0y = d.body_force[1] + gw * d.gravity[1] +
+          d.rho_f * d.beta * d.T_ref * d.gravity[1];
   P.B0x = -d.rho_f * d.beta * d.gravity[0];
   P.B0y = -d.rho_f * d.beta * d.gravity[1];
   P.init_rho = d.init_rho;

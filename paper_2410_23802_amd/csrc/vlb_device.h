@@ -661,8 +661,11 @@ __device__ PUpd particle_update_one(const Params& P, const POne& s,
     const double Finx = -Min * (Ux - s.Uxp);
     const double Finy = -Min * (Uy - s.Uyp);
     const double Tin = -Iin * (Om - s.Omp);
-    const double Fcx = (fx - Finx) + (rs - P.rho_f) * V * P.grav_x + cx;
-    const double Fcy = (fy - Finy) + (rs - P.rho_f) * V * P.grav_y + cy;
+    // gravity: (rho_s - rho_f) V g, or rho_s V g when the fluid carries
+    // its own weight (situation II of Sec. 3.2)
+    const double rg = P.fluid_gravity ? rs : rs - P.rho_f;
+    const double Fcx = (fx - Finx) + rg * V * P.grav_x + cx;
+    const double Fcy = (fy - Finy) + rg * V * P.grav_y + cy;
     u.Ux = Ux + Fcx / M;
     u.Uy = Uy + Fcy / M;
     u.Om = Om + (tz - Tin) / I;

@@ -26,6 +26,7 @@ struct Params {
   int nx, ny, N, nblocks;
   int perx, pery;
   int kmax, sigma_rule;
+  int fluid_gravity;   // situation II of Sec. 3.2 (see vlb_domain_desc)
   // flow lattice (s_0 = s_j = 1, s_e = s_eps = 1.25; Sec. 3)
   double s_e, s_q, s_p;
   // energy lattice

@@ -100,7 +100,14 @@ __global__ __launch_bounds__(kBlock) void k_init(
   const double eps = (1.0 - fs) * P.cvf * P.init_T + Se;
   const double cv = P.cvf + P.dcv * fs;
   const double Tt = eps / cv;
-  const double rho = P.init_rho;
+  // situation II of Sec. 3.2: the hydrostatic rho_0 + 3 rho_f g.(x - x_m)
+  // of the constant force density rho_f g (p = rho / 3), x_m the centre
+  const double rho =
+      P.fluid_gravity
+          ? P.init_rho + 3.0 * P.rho_f *
+                             (P.grav_x * ((x + 0.5) - 0.5 * P.nx) +
+                              P.grav_y * ((y + 0.5) - 0.5 * P.ny))
+          : P.init_rho;
   // f^eq = w_i rho [1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u^2] (= M^{-1} m^eq);
   // g^eq_i = w_i c_ref T (i >= 1), g^eq_0 = eps - 5/9 c_ref T (= M^{-1} n^eq)
   const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,

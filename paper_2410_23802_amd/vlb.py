@@ -55,6 +55,7 @@ class vlb_domain_desc(ctypes.Structure):
         ("body_force", ctypes.c_double * 2), ("gravity", ctypes.c_double * 2),
         ("beta", ctypes.c_double), ("T_ref", ctypes.c_double),
         ("sigma_rule", ctypes.c_int32),
+        ("fluid_gravity", ctypes.c_int32),
         ("coll_range", ctypes.c_double), ("coll_stiff_pp", ctypes.c_double),
         ("coll_stiff_pw", ctypes.c_double),
         ("init_rho", ctypes.c_double), ("init_u", ctypes.c_double * 2),
@@ -173,6 +174,7 @@ def make_domain_desc(d: dict, precision="fp64", shift_rho0=None,
     s.gravity[0], s.gravity[1] = d["gravity"]
     s.init_u[0], s.init_u[1] = d["init_u"]
     s.sigma_rule = int(d["sigma_rule"])
+    s.fluid_gravity = int(d.get("fluid_gravity", 0))
     s.kmax = int(d["kmax"])
     s.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     s.shift_rho0 = float(d["init_rho"] if shift_rho0 is None else shift_rho0)

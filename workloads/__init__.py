@@ -16,7 +16,8 @@ Descriptor keys (both sides read the same dict):
   face_thermal[4] ('adiabatic' | 'dirichlet'), T_wall[4]  -- faces are
   ordered x-, x+, y-, y+;
   tau_f, rho_f, cv_f, lambda_f, R_lambda, R_cv, body_force, gravity, beta,
-  T_ref, sigma_rule (0: Lambda_g = 1/4 rule, 1: sigma_e = 1), coll_range,
+  T_ref, sigma_rule (0: Lambda_g = 1/4 rule, 1: sigma_e = 1),
+  fluid_gravity (1: situation II of Sec. 3.2), coll_range,
   coll_stiff_pp, coll_stiff_pw, init_rho, init_u, init_T, kmax.
 Particle keys: x, y, theta, ux, uy, omega, radius, rho_s, T_init, fixed,
 hold_T (temperature held at T_init).
@@ -48,7 +49,7 @@ def domain(nx: int, ny: int, **kw) -> dict:
         tau_f=0.8, rho_f=1.0, cv_f=1.0, lambda_f=0.1,
         R_lambda=1.0, R_cv=1.0,
         body_force=(0.0, 0.0), gravity=(0.0, 0.0), beta=0.0, T_ref=1.0,
-        sigma_rule=0,
+        sigma_rule=0, fluid_gravity=0,
         coll_range=0.0, coll_stiff_pp=0.0, coll_stiff_pw=0.0,
         init_rho=1.0, init_u=(0.0, 0.0), init_T=1.0,
         kmax=4,
