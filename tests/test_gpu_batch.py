@@ -28,9 +28,10 @@ def say(msg):
 
 
 def ragged_cases():
-    """Five small domains of uneven, ragged sizes (not multiples of the
+    """Six small domains of uneven, ragged sizes (not multiples of the
     256-cell tile), different walls and properties; one has no particle,
-    one has two."""
+    one has two, one holds its particle's temperature in a fluid that
+    carries its own weight."""
     cases = []
     d = W.walls(W.domain(40, 97, tau_f=0.62, lambda_f=0.05, R_lambda=5.0,
                          R_cv=1.5, gravity=(0.0, -2e-5), beta=0.3,
@@ -58,6 +59,13 @@ def ragged_cases():
                          R_cv=0.6, gravity=(0.0, -1e-5), beta=1.0),
                 thermal="dirichlet", T_wall=[1.0, 1.0, 1.0, 0.0])
     cases.append((d, [W.particle(36.0, 150.4, 10.5, rho_s=1.3, T_init=0.0)]))
+    d = W.walls(W.domain(56, 150, tau_f=0.6, lambda_f=0.04, R_lambda=2.0,
+                         R_cv=1.5, gravity=(0.0, -2e-5), beta=0.4,
+                         fluid_gravity=1, coll_range=2.0, coll_stiff_pp=1e-3,
+                         coll_stiff_pw=2e-3),
+                thermal="dirichlet", T_wall=1.0)
+    cases.append((d, [W.particle(27.4, 100.2, 7.5, rho_s=1.4, T_init=0.0,
+                                 hold_T=True)]))
     return cases
 
 
