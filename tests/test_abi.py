@@ -35,6 +35,19 @@ def test_descriptor_mirror_matches_header_field_order(vlb):
     assert decl == [f[0] for f in vlb.vlb_domain_desc._fields_]
 
 
+def test_particle_mirror_matches_header(vlb):
+    """The ctypes mirror of vlb_particle_desc lists the header's members in
+    order, and the struct keeps its 80-byte size (hold_T fills the padding
+    after fixed)."""
+    import re
+    with open(vlb.HEADER) as fh:
+        txt = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\} vlb_particle_desc;", txt)
+    decl = re.findall(r"\b([A-Za-z_]\w*)\s*(?:\[[^\]]*\])*\s*[,;]", body.group(1))
+    assert decl == [f[0] for f in vlb.vlb_particle_desc._fields_]
+    assert ctypes.sizeof(vlb.vlb_particle_desc) == 80
+
+
 @pytest.mark.parametrize("patch,msg", [
     ({"nx": 0}, "nx and ny"),
     ({"tau_f": 0.5}, "tau_f"),
@@ -42,6 +55,7 @@ def test_descriptor_mirror_matches_header_field_order(vlb):
     ({"kmax": 0}, "kmax"),
     ({"lambda_f": -1.0}, "> 0"),
     ({"sigma_rule": 3}, "sigma_rule"),
+    ({"fluid_gravity": 2}, "fluid_gravity"),
 ])
 def test_create_rejects_bad_descriptor(vlb, patch, msg):
     d = W.domain(16, 16)
