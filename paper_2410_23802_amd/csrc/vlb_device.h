@@ -1701,7 +1701,10 @@ __device__ __forceinline__ void step_task(
   const int ncached = nreach < kShareCache ? nreach : kShareCache;
   const int wv = t >> 6;
   for (int pass = 0; pass < 2; ++pass) {
-    if (pass == 1 && !__syncthreads_or(act0 && S0raw > (C)1)) break;
+    // pass 2 only where shares were scaled: never with one particle (its
+    // share of a cell is at most 1), so that tile skips the barrier
+    if (pass == 1 && (cnt <= 1 || !__syncthreads_or(act0 && S0raw > (C)1)))
+      break;
     const bool over = pass == 1 && S0raw > (C)1;
     const C inv = over ? (C)1 / S0raw : (C)1;
     int e = 0;                       // next cached share of this cell
