@@ -93,3 +93,32 @@ def test_held_particles_list_form_fp64(vlb, oracle_mod):
     keys = ("x", "y", "ux", "uy", "omega", "Fx", "Fy", "Tz")
     e.update(particle_errors(g, o, keys))
     check(e, 120, twin=twin_errors(oracle_mod, d, ps, 120, o, pkeys=keys))
+
+
+@pytest.mark.parametrize("list_form", [False, True])
+def test_save_load_continues_bitwise_held_and_fluid_gravity(vlb, list_form):
+    """A checkpoint taken with held particles and the fluid-gravity option
+    restores both (the flag word is rebuilt from the descriptors on load)
+    and the run continues bit for bit; scan and list form."""
+    d = W.walls(W.domain(96, 160, tau_f=0.6, lambda_f=0.05, R_lambda=3.0,
+                         R_cv=1.5, gravity=(0.0, -2e-5), beta=0.3,
+                         fluid_gravity=1, init_T=1.0, coll_range=2.0,
+                         coll_stiff_pp=1e-3, coll_stiff_pw=2e-3),
+                thermal="dirichlet", T_wall=1.0)
+    n = 70 if list_form else 2
+    pts = W.rsa_disks(n, 4.0, (0.0, 0.0, 96.0, 160.0), 1.5, seed=9)
+    ps = [W.particle(x, y, 4.0, rho_s=1.4, T_init=0.1 * (k % 3),
+                     hold_T=(k % 2 == 0)) for k, (x, y) in enumerate(pts)]
+    say(f"case: save/load held + fluid gravity, {n} particles")
+    a = vlb.Domain(d, ps).init().step(23)
+    blob = a.save()
+    a.step(17)
+    b = vlb.Domain(d, ps)
+    b.load(blob)
+    b.step(17)
+    for k in ("f", "g", "T", "dfs"):
+        assert np.array_equal(a.field(k), b.field(k)), k
+    pa, pb = a.particles(), b.particles()
+    assert all(np.array_equal(pa[k], pb[k]) for k in pa.dtype.names)
+    a.close()
+    b.close()

@@ -61,3 +61,21 @@ def test_held_temperatures_superpose(oracle_mod):
     assert np.abs(Ta + Tb - 1.0).max() < 1e-12
     # the fields are far from uniform (the held disk matters)
     assert Ta.min() < 0.2 and Ta.max() > 0.9
+
+
+def test_fixed_temperature_channel_recipe():
+    """The Sec. 3.3 channel as the workload builds it: Re = 40.5 with
+    tau_f = 0.53 and D = 20 gives U_ref = 0.02025, |g| from U_ref =
+    sqrt((rho_r - 1) |g| pi D / 2), beta from Gr; the disk starts D/2 left of
+    the centre line and is held at T_c = 0."""
+    import math
+    d, ps = W.e5_held_channel(1000.0)
+    nu = 0.01
+    U = 40.5 * nu / 20.0
+    g = U * U / (0.00232 * math.pi * 10.0)
+    assert abs(W.u_ref(1.00232, d["gravity"][1], 20.0) - 0.02025) < 1e-15
+    assert abs(-d["gravity"][1] - g) < 1e-15 and d["gravity"][0] == 0.0
+    assert abs(d["beta"] - 1000.0 * nu * nu / (g * 20.0 ** 3)) < 1e-15
+    assert d["nx"] == 80 and d["R_lambda"] == 1.0 and d["R_cv"] == 1.0
+    assert abs(d["lambda_f"] - nu / 0.7) < 1e-15
+    assert ps[0]["x"] == 30.0 and ps[0]["hold_T"] == 1 and ps[0]["T_init"] == 0.0
