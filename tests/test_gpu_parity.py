@@ -354,6 +354,89 @@ def test_moving_wall_and_corners_fp64(vlb, oracle_mod):
 
 
 # --------------------------------------------------------------------------
+# degenerate and ragged shapes
+
+
+def degenerate_domains():
+    """Domains smaller than one tile in which every cell is a boundary cell:
+    one periodic cell under a body force (a cell that is its own neighbour
+    in every direction), a one-cell-wide conduction column between two
+    Dirichlet walls, a one-cell-high channel between two walls, and a
+    3 x 2 box walled on every side (every cell touches a corner)."""
+    Y, X = (W.YLO, W.YHI), (W.XLO, W.XHI)
+    return {
+        "1x1": W.domain(1, 1, init_u=(0.01, -0.02), body_force=(1e-5, 2e-6),
+                        init_T=0.7),
+        "1x9": W.walls(W.domain(1, 9, init_T=0.5, gravity=(0.0, -1e-4),
+                                beta=0.3, T_ref=0.5),
+                       Y, "dirichlet", [0.0, 0.0, 1.0, 0.0]),
+        "7x1": W.walls(W.domain(7, 1, init_u=(0.0, 0.01), init_T=0.2),
+                       X, "dirichlet", [1.0, 0.0, 0.0, 0.0]),
+        "3x2": W.walls(W.domain(3, 2, init_u=(0.02, 0.01), init_T=0.4),
+                       thermal="dirichlet", T_wall=[1.0, 0.0, 0.5, 0.25]),
+    }
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["1x1", "1x9", "7x1", "3x2"])
+def test_degenerate_shapes(vlb, oracle_mod, name, prec):
+    d = degenerate_domains()[name]
+    say(f"case: degenerate {name} {prec} 300 steps")
+    g, o = run_pair(vlb, oracle_mod, d, [], 300, prec)
+    names = ("rho", "ux", "uy", "T")
+    e = field_errors(g, o, names)
+    say(f"  errors: {e}")
+    if prec == "fp64":
+        # the column and the channel end at rest: their speeds are a few
+        # 1e-16 of rounding, where the oracle's own FMA twin differs by up
+        # to 3e-12 of the 1e-4 speed floor
+        check(e, 300, twin=twin_errors(oracle_mod, d, [], 300, o, names))
+    else:
+        bad = {k: v for k, v in e.items() if v >= FP32_BAR.get(k, 1e-5)}
+        assert not bad, (bad, e)
+
+
+def ragged_seam_case():
+    """37 x 53 cells (1961 cells: a partial last tile), walls at y = 0 (hot)
+    and y = 53 (cold), periodic in x.  A heavy, warm, spinning disk
+    straddles the periodic seam inside the wall's collision range, so the
+    wrap, the wall rules and the repulsion act on the same cells."""
+    cp = W.collision_params(1.5, 4.3, 2e-4)
+    d = W.walls(W.domain(37, 53, tau_f=0.7, lambda_f=0.05, R_lambda=4.0,
+                         R_cv=2.0, gravity=(0.0, -2e-4), beta=0.2, T_ref=0.5,
+                         init_T=0.5, **cp),
+                (W.YLO, W.YHI), "dirichlet", [0.0, 0.0, 1.0, 0.0])
+    ps = [W.particle(1.2, 6.0, 4.3, rho_s=1.5, T_init=0.9, ux=-0.01,
+                     uy=-0.01, omega=0.004)]
+    return d, ps
+
+
+def test_ragged_domain_disk_across_seam_at_wall_fp64(vlb, oracle_mod):
+    d, ps = ragged_seam_case()
+    say("case: ragged 37x53 seam/wall disk fp64 400 steps")
+    g, o = run_pair(vlb, oracle_mod, d, ps, 400)
+    keys = ("x", "y", "ux", "uy", "omega", "Fx", "Fy", "Tz")
+    e = field_errors(g, o)
+    e.update(particle_errors(g, o, keys))
+    say(f"  errors: {e}")
+    check(e, 400, twin=twin_errors(oracle_mod, d, ps, 400, o, pkeys=keys))
+
+
+def test_ragged_domain_disk_across_seam_at_wall_fp32(vlb, oracle_mod):
+    """FP32 storage: fields to the FP32 bar, the disk's path to 1e-3 of a
+    diameter."""
+    d, ps = ragged_seam_case()
+    say("case: ragged 37x53 seam/wall disk fp32 400 steps")
+    g, o = run_pair(vlb, oracle_mod, d, ps, 400, "fp32")
+    e = field_errors(g, o)
+    say(f"  errors: {e}")
+    bad = {k: v for k, v in e.items() if v >= FP32_BAR.get(k, 1e-5)}
+    assert not bad, (bad, e)
+    p = particle_errors(g, o, ("x", "y"))
+    assert p["x"] < 1e-3 and p["y"] < 1e-3, p
+
+
+# --------------------------------------------------------------------------
 # integer work: ownership, bit for bit
 
 
