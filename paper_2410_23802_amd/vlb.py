@@ -94,6 +94,11 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise VlbLibraryMissing(
             f"{LIB_PATH} is not built; run paper_2410_23802_amd.build.build()")
+    # PyTorch carries its own HIP runtime (soname libamdhip64.so.7), and the
+    # binding hands torch's device pointers and streams across the ABI, so
+    # the library must run on that same runtime: with torch loaded first,
+    # the library's HIP and HSA dependencies resolve to torch's copies.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     sig = {
