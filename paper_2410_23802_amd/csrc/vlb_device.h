@@ -1026,15 +1026,33 @@ __device__ __forceinline__ void moments(const C* f, C* m) {
   m[8] = f[5] - f[6] + f[7] - f[8];
 }
 
+// m / d for the moment norms d = 9, 36, 6, 12.  In FP32 the reciprocal is
+// split into two floats, hi = fl(1/d) and lo = fl(1/d - hi), so that the
+// product carries no systematic error: with hi alone, the momentum the
+// populations rebuild is 6 fl(1/6) j = (1 + 3e-8) j and the rest moment
+// 9 fl(1/9) m_0, a gain the same in every cell at every step.  At
+// tau_f = 0.53 that acts as negative friction worth about 5e-4 of the
+// steady speed of a body-force channel, and in the energy lattice as a
+// heat source.  FP64's fl(1/d) is exact to 1e-17 and keeps one product.
+template <int D, class C>
+__device__ __forceinline__ C over(C m) {
+  constexpr double r = 1.0 / D;
+  if constexpr (sizeof(C) == sizeof(float)) {
+    constexpr float hi = (float)r;
+    constexpr float lo = (float)(r - (double)hi);
+    return m * hi + m * lo;
+  } else {
+    return m * (C)r;
+  }
+}
+
 // M^{-1} m = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m
 // (the rows of M are orthogonal with those squared norms).
 template <class C>
 __device__ __forceinline__ void inverse(const C* m, C* o) {
-  const C k0 = m[0] * (C)(1.0 / 9.0), k1 = m[1] * (C)(1.0 / 36.0),
-          k2 = m[2] * (C)(1.0 / 36.0), k3 = m[3] * (C)(1.0 / 6.0),
-          k4 = m[4] * (C)(1.0 / 12.0), k5 = m[5] * (C)(1.0 / 6.0),
-          k6 = m[6] * (C)(1.0 / 12.0), k7 = m[7] * (C)0.25,
-          k8 = m[8] * (C)0.25;
+  const C k0 = over<9>(m[0]), k1 = over<36>(m[1]), k2 = over<36>(m[2]),
+          k3 = over<6>(m[3]), k4 = over<12>(m[4]), k5 = over<6>(m[5]),
+          k6 = over<12>(m[6]), k7 = m[7] * (C)0.25, k8 = m[8] * (C)0.25;
   o[0] = k0 - 4 * k1 + 4 * k2;
   const C ax = k0 - k1 - 2 * k2;
   o[1] = ax + k3 - 2 * k4 + k7;
@@ -1123,8 +1141,18 @@ __device__ __forceinline__ void load_cell(
 
 // The lattice update of one loaded cell: the wall rules on the pulled
 // values, the volumetric no-slip step with the particle sums `part`
-// supplies (called as part(act, x, y, rho, jx*, jy*, S)), the coupled
-// macroscopic solve and both collisions, then the stores.
+// supplies (called as part(act, x, y, rho - rho_0, jx*, jy*, S)), the
+// coupled macroscopic solve and both collisions, then the stores.
+//
+// Conserved moments are updated in the form that rounds no quantity of
+// order one: the density moment keeps rho - rho_0, the momentum after the
+// collision is j + F (exactly rho u + F/2 with rho u = j + F/2), the rest
+// moment of the energy is n_0 + q_c (exactly eps + q_c/2, since the
+// implicit relation for T makes eps - q_c/2 the streamed sum G), and a
+// product rho v is formed as rho_0 v + (rho - rho_0) v.  In FP64 these
+// equal the literal forms to rounding; in the 32- and 16-bit forms they
+// keep the per-step rounding from acting as a small systematic force or
+// heat source.
 template <int PREC, bool OUT, class PartFn>
 __device__ __forceinline__ void update_cell(
     const Params& P, const Hot<typename Prec<PREC>::C>& H,
@@ -1160,12 +1188,14 @@ __device__ __forceinline__ void update_cell(
   const C drho = m[0];                 // rho - rho_0
   const C rho = H.rho0s + drho;        // rho = sum f*_i, kept by eq. fi
   const C jxs = m[3], jys = m[5];
+  // rho v without rounding rho = rho_0 + drho first
+  auto rmul = [&](C v) { return H.rho0s * v + drho * v; };
 
   // ---- particles: solid fraction, u_s, momentum exchange (Sec. 2.3)
   PSums<C> S;
   S.S0 = S.S1x = S.S1y = S.S2xx = S.S2yy = S.S2xy = (C)0;
   S.H0 = S.H1 = (C)0;
-  part(act, x, y, rho, jxs, jys, S);
+  part(act, x, y, drho, jxs, jys, S);
 
   // ---- volumetric no-slip step in moment space (eq. fi):
   // M f = (1 - f_s) M f* + rho sum_p f_s,p m^eq(1, u_s,p), written for the
@@ -1176,13 +1206,14 @@ __device__ __forceinline__ void update_cell(
   const C wf = (C)1 - fs;
   {
     const C tr = S2xx + S2yy;
-    m[0] = wf * m[0] + S0 * drho;
+    const C rS1x = rmul(S1x), rS1y = rmul(S1y);
+    m[0] = drho;                       // eq. fi keeps rho
     m[1] = wf * m[1] + (-2 * S0 * drho + 3 * rho * tr);
     m[2] = wf * m[2] + (S0 * drho - 3 * rho * tr);
-    m[3] = wf * m[3] + rho * S1x;
-    m[4] = wf * m[4] - rho * S1x;
-    m[5] = wf * m[5] + rho * S1y;
-    m[6] = wf * m[6] - rho * S1y;
+    m[3] = wf * m[3] + rS1x;
+    m[4] = wf * m[4] - rS1x;
+    m[5] = wf * m[5] + rS1y;
+    m[6] = wf * m[6] - rS1y;
     m[7] = wf * m[7] + rho * (S2xx - S2yy);
     m[8] = wf * m[8] + rho * S2xy;
   }
@@ -1254,10 +1285,11 @@ __device__ __forceinline__ void update_cell(
     mb[0] = drho;
     mb[1] = m[1] - se * (m[1] - (-2 * drho + 3 * ru2)) + he * (6 * Fu);
     mb[2] = m[2] - se * (m[2] - (drho - 3 * ru2)) - he * (6 * Fu);
-    mb[3] = rho * ux + (C)0.5 * Fx;
-    mb[4] = m[4] - sq * (m[4] + rho * ux) - hq * Fx;
-    mb[5] = rho * uy + (C)0.5 * Fy;
-    mb[6] = m[6] - sq * (m[6] + rho * uy) - hq * Fy;
+    const C rux = jx + (C)0.5 * Fx, ruy = jy + (C)0.5 * Fy;   // rho u
+    mb[3] = jx + Fx;
+    mb[4] = m[4] - sq * (m[4] + rux) - hq * Fx;
+    mb[5] = jy + Fy;
+    mb[6] = m[6] - sq * (m[6] + ruy) - hq * Fy;
     mb[7] = m[7] - sp * (m[7] - rho * (ux * ux - uy * uy)) + hp * (2 * (Fx * ux - Fy * uy));
     mb[8] = m[8] - sp * (m[8] - rho * ux * uy) + hp * (Fx * uy + Fy * ux);
     C o[9];
@@ -1276,7 +1308,7 @@ __device__ __forceinline__ void update_cell(
     const C cT = H.cref * Tc;
     const C he = (C)1 - (C)0.5 * sig_e;
     C nb[9];
-    nb[0] = (eps - cT0) + (C)0.5 * qc;
+    nb[0] = n[0] + qc;   // eps + q_c/2 minus the reference
     nb[1] = n[1] - sig_e * (n[1] - (-4 * eps + 2 * cT + 2 * cT0)) - he * (4 * qc);
     nb[2] = n[2] - sig_e * (n[2] - (4 * eps - 3 * cT - cT0)) + he * (4 * qc);
     const C rj = (C)1 - sig_j, re = (C)1 - sig_e;
@@ -1670,7 +1702,7 @@ __device__ __forceinline__ void step_task(
     __syncthreads();
     return sh.tmp[0] != 0;   // a particle tile: the first group's
   };
-  auto part = [&](bool, int, int, C rho, C jxs, C jys, PSums<C>& S) {
+  auto part = [&](bool, int, int, C drho, C jxs, C jys, PSums<C>& S) {
     if (ptile) {
       S.S0 = sh.S[0][t]; S.S1x = sh.S[1][t]; S.S1y = sh.S[2][t];
       S.S2xx = sh.S[3][t]; S.S2yy = sh.S[4][t]; S.S2xy = sh.S[5][t];
@@ -1678,7 +1710,7 @@ __device__ __forceinline__ void step_task(
         S.H0 = sh.M[0][t];
         S.H1 = sh.M[1][t];
       }
-      sh.M[0][t] = rho; sh.M[1][t] = jxs; sh.M[2][t] = jys;
+      sh.M[0][t] = drho; sh.M[1][t] = jxs; sh.M[2][t] = jys;
     }
   };
   if (!lattice_tile<PREC, OUT>(P, H, fin, fout, gin, gout, hin, hout, plane,
@@ -1694,7 +1726,8 @@ __device__ __forceinline__ void step_task(
   // The shares come from phase 1 (recomputed only past kShareCache per
   // cell); every slot's sums are reduced per wave into LDS, then the four
   // waves in order by one thread per slot.
-  const C rho = sh.M[0][t], jxs = sh.M[1][t], jys = sh.M[2][t];
+  const C drho = sh.M[0][t], jxs = sh.M[1][t], jys = sh.M[2][t];
+  const C rho0s = H.rho0s;
   const C S0raw = sh.S0raw[t];
   const int cnt = sh.bp.cnt;
   const int nreach = act0 ? sh.nreach[t] : 0;
@@ -1739,8 +1772,10 @@ __device__ __forceinline__ void step_task(
                         sh.bp.Om[k], cx, cy, rx, ry, usx, usy);
         const C ux = (C)usx, uy = (C)usy;
         const double kk = pass == 0 ? 1.0 : (double)(inv - (C)1);
-        const double dpx = (double)(a * (rho * ux - jxs));
-        const double dpy = (double)(a * (rho * uy - jys));
+        // rho u_s - j* with rho = rho_0 + drho: the O(1) parts cancel
+        // before anything of order one is rounded
+        const double dpx = (double)(a * ((rho0s * ux - jxs) + drho * ux));
+        const double dpy = (double)(a * ((rho0s * uy - jys) + drho * uy));
         cfx = -dpx * kk;
         cfy = -dpy * kk;
         ctz = -(rx * dpy - ry * dpx) * kk;

@@ -129,12 +129,8 @@ def channel_track(vlb, prec, steps, every):
 def test_channel_full_run_forms_against_fp64(vlb):
     """The channel's whole run, 100 000 steps: the disk's path in each
     storage form against the FP64 form on the same GPU, every 1000 steps.
-    The FP64 form is tied to the oracle by the 20 000-step sweep above and
-    by the parity tests.  Measured: FP32 stays within 1e-3 diameters of
-    the FP64 path for the first 48 000 steps and ends 4.7e-3 D from it,
-    having settled 0.03 % slower (FP32 arithmetic on populations of order
-    one); it is held to 1e-3 D over the first 40 000 steps and to 1e-2 D
-    over the whole run.  The 16-bit forms are reported."""
+    FP32 is held to 1e-3 diameters over the whole run, and its mean
+    particle temperature to 1e-3; the 16-bit forms are reported."""
     steps, every = 100_000, 1000
     ref, refT, D = channel_track(vlb, "fp64", steps, every)
     drop = (ref[0, 1] - ref[-1, 1]) / D
@@ -156,11 +152,7 @@ def test_channel_full_run_forms_against_fp64(vlb):
             json.dump({"steps": steps, "every": every, "fell_D": drop,
                        "rows": rows, "tracks": tracks}, fh)
     assert drop > 1.0
-    early = float(np.hypot(*(np.array(tracks["fp32"][:40]) - ref[:40]).T)
-                  .max()) / D
-    print(f"  fp32 over the first 40000 steps: {early:.2e} D", flush=True)
-    assert early < 1e-3, early
-    assert rows["fp32"]["traj_hist_err_D"] < 1e-2, rows
+    assert rows["fp32"]["traj_hist_err_D"] < 1e-3, rows
     assert rows["fp32"]["T_mean_err"] < 1e-3, rows
     for prec in ("fp16s", "bf16s"):
         assert rows[prec]["finite"], rows
