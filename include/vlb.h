@@ -184,6 +184,22 @@ vlb_status vlb_read_particles(vlb_ctx* ctx, int32_t n,
 vlb_status vlb_read_ownership(vlb_ctx* ctx, int32_t* count, int32_t* ids,
                               int32_t* full);
 
+/* vlb_read_ownership for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same outputs, bit for bit, with no hipMalloc, hipFree or other
+ * allocation.  The kernels stage their results in a 16 MiB array in device
+ * memory that the library holds on every GPU it runs on until the process
+ * ends; the domain is read in chunks of whole 256-cell tiles that fit it
+ * (at most 963 tiles per chunk at kmax = 8), so no domain size is refused.
+ * The array is shared by every call on a GPU and keeps the last call's
+ * contents (each call overwrites every entry it copies out): calls that
+ * overlap on one GPU, from any context or thread, race and must be
+ * serialised by the caller.  count, ids, full: host buffers as for
+ * vlb_read_ownership.  VLB_EHIP if the array's device address cannot be
+ * obtained on the context's device. */
+vlb_status vlb_read_ownership_noalloc(vlb_ctx* ctx, int32_t* count,
+                                      int32_t* ids, int32_t* full);
+
 /* Checkpoint: vlb_save writes the complete state (populations, [df_s/dt]
  * carrier, particle state, step counter) into buf.  With buf == NULL it only
  * stores the needed size in *inout_len.  vlb_load restores a buffer written

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -630,8 +631,8 @@ vlb_status vlb_read_ownership(vlb_ctx* c, int32_t* count, int32_t* ids,
                          c->partial[c->pp], 0, kModeBinOnly, c->flags,
                          c->stream);
   if (e == hipSuccess)
-    e = launch_ownership(c->P, cur, c->pc, lists(c), dc, di, df, c->flags,
-                         c->stream);
+    e = launch_ownership(c->P, cur, c->pc, lists(c), 0, c->P.nblocks, dc, di,
+                         df, c->flags, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(count, dc, N * sizeof(int), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess)
@@ -644,6 +645,41 @@ vlb_status vlb_read_ownership(vlb_ctx* c, int32_t* count, int32_t* ids,
   if (df) (void)hipFree(df);
   if (e != hipSuccess) return hip_fail(c, e, "read ownership");
   return VLB_OK;
+}
+
+// ---- ownership read-out that allocates nothing ---------------------------
+//
+// The staging buffer lives in a file-scope device array.  Its name is a
+// host-side stand-in in host code; the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current and
+// kept in g_scratch_ptr.  Only that pointer is handed to kernels and copies.
+constexpr size_t kScratchInts = (size_t)4 << 20;   // 16 MiB
+static __device__ __align__(256) int scratch[kScratchInts];
+
+constexpr int kMaxDevices = 64;
+static int* g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static hipError_t scratch_for_device(int dev, int** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return e;
+    if (prev != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != dev) {
+      const hipError_t e2 = hipSetDevice(prev);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = (int*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 // Checkpoint layout: header, then f and g (current copies, storage form),
@@ -750,6 +786,45 @@ vlb_status vlb_load(vlb_ctx* c, const void* buf, size_t len) {
   c->have_partials = hd.have_partials;
   c->step = hd.step;
   c->initialized = true;
+  return VLB_OK;
+}
+
+vlb_status vlb_read_ownership_noalloc(vlb_ctx* c, int32_t* count,
+                                      int32_t* ids, int32_t* full) {
+  if (!c || !count || !ids || !full) return VLB_EINVAL;
+  if (!c->initialized) return fail(c, VLB_ESTATE, "no valid state to read");
+  int* base = nullptr;
+  HIP_TRY(c, scratch_for_device(c->device, &base));
+  const size_t K = (size_t)c->P.kmax;
+  // tiles per chunk: count, ids and full of every cell of a tile in scratch
+  const size_t per_tile = (size_t)kBlock * (1 + 2 * K);
+  const int chunk = (int)(kScratchInts / per_tile);
+  if (chunk < 1)
+    return fail(c, VLB_EINVAL, "ownership scratch too small for kmax");
+  PState cur = c->ps[c->pcur];
+  if (!c->P.scan)   // the lists of the current positions, as the step reads
+    HIP_TRY(c, launch_particles(c->P, cur, cur, c->pc, bin_lists(c),
+                                c->partial[c->pp], 0, kModeBinOnly, c->flags,
+                                c->stream));
+  const size_t N = (size_t)c->P.N;
+  for (int t0 = 0; t0 < c->P.nblocks; t0 += chunk) {
+    const int nt = c->P.nblocks - t0 < chunk ? c->P.nblocks - t0 : chunk;
+    const size_t c0 = (size_t)t0 * kBlock;
+    const size_t cend = c0 + (size_t)nt * kBlock < N ? c0 + (size_t)nt * kBlock : N;
+    const size_t nc = cend - c0;
+    int* dc = base;
+    int* di = base + (size_t)nt * kBlock;
+    int* df = di + (size_t)nt * kBlock * K;
+    HIP_TRY(c, launch_ownership(c->P, cur, c->pc, lists(c), t0, nt, dc, di, df,
+                                c->flags, c->stream));
+    const hipMemcpyKind D2H = hipMemcpyDeviceToHost;
+    HIP_TRY(c, hipMemcpyAsync(count + c0, dc, nc * sizeof(int), D2H, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(ids + c0 * K, di, nc * K * sizeof(int), D2H,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(full + c0 * K, df, nc * K * sizeof(int), D2H,
+                              c->stream));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return VLB_OK;
 }
 

@@ -951,16 +951,16 @@ __device__ __forceinline__ void particle_motion(const Params& P, double Xp,
   usy = Uy + Om * rx;
 }
 
+// The particles reaching tile b (scan or list form).
 template <bool SCAN>
 __device__ __forceinline__ void gather_particles(
-    BlockParticles& bp, int* tmp, const Params& P, PState cur, PState next,
-    PConst pc, Lists L, const double* partial, int have, bool advance,
-    int* flags) {
+    BlockParticles& bp, int* tmp, const Params& P, int b, PState cur,
+    PState next, PConst pc, Lists L, const double* partial, int have,
+    bool advance, int* flags) {
   if (SCAN)
-    scan_block(bp, P, blockIdx.x, cur, next, pc, partial, have, advance,
-               flags);
+    scan_block(bp, P, b, cur, next, pc, partial, have, advance, flags);
   else
-    load_block_list(bp, tmp, L, blockIdx.x, advance ? next : cur, pc, flags);
+    load_block_list(bp, tmp, L, b, advance ? next : cur, pc, flags);
 }
 
 // -------------------------------------------------------------------------

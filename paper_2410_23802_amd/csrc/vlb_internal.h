@@ -209,9 +209,11 @@ hipError_t launch_tile_counts(const Params& P, PState cur, PConst pc,
 hipError_t launch_particle_sums(const Params& P, PState ps, PConst pc,
                                 const double* macro, double* out4,
                                 hipStream_t s);
+// Ownership of the cells of tiles [tile0, tile0 + ntiles); count, ids and
+// full are indexed from the first cell of tile0.
 hipError_t launch_ownership(const Params& P, PState ps, PConst pc, Lists L,
-                            int* count, int* ids, int* full, int* flags,
-                            hipStream_t s);
+                            int tile0, int ntiles, int* count, int* ids,
+                            int* full, int* flags, hipStream_t s);
 // The step's memory pattern without its arithmetic (fi -> fo, gi -> go,
 // hin -> hout of B; the state in fi, gi, hin is left as it was).
 hipError_t launch_stream_probe(int prec, const Params& P, const StepBufs& B,

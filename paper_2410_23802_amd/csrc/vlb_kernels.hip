@@ -70,7 +70,8 @@ __global__ __launch_bounds__(kBlock) void k_init(
   typedef typename T::C C;
   __shared__ BlockParticles bp;
   __shared__ int tmp[kListCap];
-  gather_particles<SCAN>(bp, tmp, P, ps, ps, pc, L, nullptr, 0, false, flags);
+  gather_particles<SCAN>(bp, tmp, P, blockIdx.x, ps, ps, pc, L, nullptr, 0,
+                         false, flags);
   const int c = blockIdx.x * kBlock + threadIdx.x;
   if (c >= P.N) return;
   const int y = c / P.nx, x = c - y * P.nx;
@@ -528,18 +529,25 @@ __global__ __launch_bounds__(256) void k_particle_sums(
 
 template <bool SCAN>
 __global__ __launch_bounds__(kBlock) void k_ownership(
-    const Params P, PState ps, PConst pc, Lists L, int* count, int* ids,
-    int* full, int* flags) {
+    const Params P, PState ps, PConst pc, Lists L, int tile0, int* count,
+    int* ids, int* full, int* flags) {
   __shared__ BlockParticles bp;
   __shared__ int tmp[kListCap];
-  gather_particles<SCAN>(bp, tmp, P, ps, ps, pc, L, nullptr, 0, false, flags);
-  const int c = blockIdx.x * kBlock + threadIdx.x;
+  const int tile = tile0 + blockIdx.x;
+  gather_particles<SCAN>(bp, tmp, P, tile, ps, ps, pc, L, nullptr, 0, false,
+                         flags);
+  const int c = tile * kBlock + threadIdx.x;
   if (c >= P.N) return;
   const int y = c / P.nx, x = c - y * P.nx;
+  // outputs are indexed from the first cell of tile0
+  const int o = c - tile0 * kBlock;
+  count += o;
+  ids += (size_t)o * P.kmax;
+  full += (size_t)o * P.kmax;
   int n = 0;
   for (int k = 0; k < P.kmax; ++k) {
-    ids[(size_t)c * P.kmax + k] = -1;
-    full[(size_t)c * P.kmax + k] = 0;
+    ids[k] = -1;
+    full[k] = 0;
   }
   for (int s = 0; s < bp.cnt; ++s) {
     const double xn = x + 0.5, yn = y + 0.5;
@@ -547,13 +555,13 @@ __global__ __launch_bounds__(kBlock) void k_ownership(
     const double Y = near_copy(bp.Y[s], yn, (double)P.ny, P.pery);
     if (!owns_cell(X, Y, bp.R[s], x, y)) continue;
     if (n < P.kmax) {
-      ids[(size_t)c * P.kmax + n] = bp.pid[s];
-      full[(size_t)c * P.kmax + n] = cell_within(X, Y, bp.R[s], x, y) ? 1 : 0;
+      ids[n] = bp.pid[s];
+      full[n] = cell_within(X, Y, bp.R[s], x, y) ? 1 : 0;
     }
     ++n;
   }
   if (n > P.kmax) atomicOr(flags, kFlagOverlap);
-  count[c] = n < P.kmax ? n : P.kmax;
+  count[0] = n < P.kmax ? n : P.kmax;
 }
 
 // Memory-pattern probe: the step kernel's global-memory traffic without its
@@ -712,14 +720,16 @@ hipError_t launch_particle_sums(const Params& P, PState ps, PConst pc,
 }
 
 hipError_t launch_ownership(const Params& P, PState ps, PConst pc, Lists L,
-                            int* count, int* ids, int* full, int* flags,
-                            hipStream_t s) {
+                            int tile0, int ntiles, int* count, int* ids,
+                            int* full, int* flags, hipStream_t s) {
+  if (tile0 < 0 || ntiles <= 0 || tile0 + ntiles > P.nblocks)
+    return hipErrorInvalidValue;
   if (P.scan)
-    hipLaunchKernelGGL(k_ownership<true>, dim3(P.nblocks), dim3(kBlock), 0, s,
-                       P, ps, pc, L, count, ids, full, flags);
+    hipLaunchKernelGGL(k_ownership<true>, dim3(ntiles), dim3(kBlock), 0, s,
+                       P, ps, pc, L, tile0, count, ids, full, flags);
   else
-    hipLaunchKernelGGL(k_ownership<false>, dim3(P.nblocks), dim3(kBlock), 0, s,
-                       P, ps, pc, L, count, ids, full, flags);
+    hipLaunchKernelGGL(k_ownership<false>, dim3(ntiles), dim3(kBlock), 0, s,
+                       P, ps, pc, L, tile0, count, ids, full, flags);
   return hipGetLastError();
 }
 

@@ -112,6 +112,7 @@ def lib():
         "vlb_read_particles": ([vp, i32, ctypes.POINTER(vlb_particle_state)],
                                ctypes.c_int),
         "vlb_read_ownership": ([vp, vp, vp, vp], ctypes.c_int),
+        "vlb_read_ownership_noalloc": ([vp, vp, vp, vp], ctypes.c_int),
         "vlb_save": ([vp, vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "vlb_load": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
         "vlb_step_count": ([vp], i64),
@@ -264,6 +265,18 @@ def vlb_read_ownership(h, nx, ny, kmax):
     full = np.zeros((ny, nx, kmax), np.int32)
     _check(lib().vlb_read_ownership(h, cnt.ctypes.data, ids.ctypes.data,
                                     full.ctypes.data), "vlb_read_ownership", h)
+    return cnt, ids, full
+
+
+def vlb_read_ownership_noalloc(h, nx, ny, kmax):
+    """vlb_read_ownership through the entry point that allocates no device
+    memory (the library's static staging array)."""
+    cnt = np.zeros((ny, nx), np.int32)
+    ids = np.zeros((ny, nx, kmax), np.int32)
+    full = np.zeros((ny, nx, kmax), np.int32)
+    _check(lib().vlb_read_ownership_noalloc(
+        h, cnt.ctypes.data, ids.ctypes.data, full.ctypes.data),
+        "vlb_read_ownership_noalloc", h)
     return cnt, ids, full
 
 
