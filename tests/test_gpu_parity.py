@@ -701,3 +701,44 @@ def test_step_before_init_is_state_error(vlb):
     with pytest.raises(vlb.VlbError) as ei:
         g.step(1)
     assert ei.value.status == vlb.VLB_ESTATE
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_list_form_reads_between_steps_keep_the_bits(vlb, prec):
+    """List form: each step kernel also runs the next step's particle pass,
+    in the tails of the tiles that complete a particle's partials.  A read
+    of the ownership between steps gives that state up and the next step
+    runs the particle pass as a kernel of its own; both routes run the same
+    pass, so the fields and particles must agree bit for bit with a run
+    that never reads, and with a run that reads after every step."""
+    rng = np.random.default_rng(21)
+    d = W.walls(W.domain(400, 300, tau_f=0.7, lambda_f=0.05, R_lambda=3.0,
+                         R_cv=1.5, gravity=(0.0, -4e-5), beta=0.1,
+                         init_T=1.0, coll_range=2.0, coll_stiff_pp=2e-3,
+                         coll_stiff_pw=4e-3), thermal="adiabatic")
+    pts = W.rsa_disks(300, 3.5, (0.0, 0.0, 400.0, 300.0), 1.0, seed=8)
+    ps = [W.particle(x, y, 3.5, rho_s=rng.uniform(1.2, 2.0), T_init=0.3,
+                     ux=rng.uniform(-0.01, 0.01), uy=rng.uniform(-0.01, 0.01))
+          for x, y in pts]
+    say(f"case: list form, reads between steps, {prec}")
+    a = vlb.Domain(d, ps, prec).init().step(30)
+    b = vlb.Domain(d, ps, prec).init()
+    for k in range(30):
+        b.step(1)
+        if k % 3 == 0:
+            b.ownership()
+    c = vlb.Domain(d, ps, prec).init()
+    for k in range(30):
+        c.step(1)
+        c.ownership()
+        c.particles()
+    for n in ("f", "g", "T", "ux", "dfs"):
+        fa = a.field(n)
+        assert np.array_equal(fa, b.field(n)), n
+        assert np.array_equal(fa, c.field(n)), n
+    pa, pb, pc = a.particles(), b.particles(), c.particles()
+    for k in pa.dtype.names:
+        assert np.array_equal(pa[k], pb[k]), k
+        assert np.array_equal(pa[k], pc[k]), k
+    for x in (a, b, c):
+        x.close()
