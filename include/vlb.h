@@ -238,6 +238,11 @@ size_t vlb_device_bytes(const vlb_ctx* ctx);
 /* Message for the last failing call on ctx (or on creation when ctx is NULL). */
 const char* vlb_last_error(const vlb_ctx* ctx);
 
+/* The hash of the sources the library was built from (16 hex digits, a
+ * static string): a caller can check that the binary it loaded matches the
+ * sources it expects. */
+const char* vlb_build_hash(void);
+
 /* Free the context and its device memory (NULL is ignored). */
 void vlb_destroy(vlb_ctx* ctx);
 

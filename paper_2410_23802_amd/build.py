@@ -1,6 +1,7 @@
 """Build the HIP library libvlb.so for gfx950 in the package directory."""
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -22,6 +23,21 @@ SOURCES = {
     "vlb_api.hip": [],
     "vlb_batch.hip": [],
 }
+
+
+def source_hash() -> str:
+    """SHA-256 (first 16 hex digits) of everything the library is built
+    from: the HIP sources, the private headers, the public header and the
+    compile flags.  The library carries it (vlb_build_hash), and the binding
+    refuses a library whose hash differs from the sources beside it."""
+    h = hashlib.sha256()
+    files = sorted(os.listdir(CSRC)) + ["../../include/vlb.h"]
+    for name in files:
+        path = os.path.normpath(os.path.join(CSRC, name))
+        with open(path, "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read() + b"\0")
+    h.update(repr(sorted(SOURCES.items())).encode())
+    return h.hexdigest()[:16]
 
 
 def hipcc() -> str:
@@ -47,6 +63,7 @@ def build(verbose: bool = False, arch: str = "gfx950") -> str:
     """Compile every HIP source into one shared library (always rebuilds)."""
     common = [hipcc(), f"--offload-arch={arch}", "-O3", "-std=c++17", "-fPIC",
               "-Wall", "-Wno-unused-function",
+              f"-DVLB_SOURCE_HASH=\"{source_hash()}\"",
               # no packed FP32 instructions in generated code
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-I", os.path.join(ROOT, "include"), "-I", CSRC]
@@ -63,5 +80,24 @@ def build(verbose: bool = False, arch: str = "gfx950") -> str:
     return LIB
 
 
+EXAMPLE_SRC = os.path.join(HERE, "examples", "vlb_c_run.c")
+EXAMPLE = os.path.join(HERE, "examples", "vlb_c_run")
+
+
+def build_example(verbose: bool = False) -> str:
+    """Compile the plain C caller of the ABI (examples/vlb_c_run.c) with the
+    host C compiler, linked against libvlb.so (found beside it at run time
+    through its run path)."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        raise RuntimeError("no C compiler for the C-ABI example")
+    _run([cc, "-std=c11", "-O2", "-Wall", "-I", os.path.join(ROOT, "include"),
+          EXAMPLE_SRC, "-L", HERE, "-lvlb", "-Wl,-rpath,$ORIGIN/..",
+          "-o", EXAMPLE + ".tmp"], verbose)
+    os.replace(EXAMPLE + ".tmp", EXAMPLE)
+    return EXAMPLE
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_example(verbose=True))

@@ -12,6 +12,10 @@
 
 #include "vlb_context.h"
 
+#ifndef VLB_SOURCE_HASH
+#error "build with -DVLB_SOURCE_HASH (paper_2410_23802_amd/build.py sets it)"
+#endif
+
 using namespace vlb;
 
 static std::string g_create_error;
@@ -884,6 +888,8 @@ size_t vlb_device_bytes(const vlb_ctx* c) { return c ? c->dev_bytes : 0; }
 const char* vlb_last_error(const vlb_ctx* c) {
   return c ? c->err.c_str() : g_create_error.c_str();
 }
+
+const char* vlb_build_hash(void) { return VLB_SOURCE_HASH; }
 
 void vlb_destroy(vlb_ctx* c) {
   if (!c) return;

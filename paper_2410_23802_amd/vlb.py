@@ -36,6 +36,10 @@ class VlbLibraryMissing(RuntimeError):
     pass
 
 
+class VlbLibraryStale(RuntimeError):
+    """The built library does not match the sources beside it."""
+
+
 class VlbError(RuntimeError):
     def __init__(self, status: int, where: str, msg: str):
         super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
@@ -100,6 +104,15 @@ def lib():
     # the library's HIP and HSA dependencies resolve to torch's copies.
     import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
+    # the binary must come from the sources beside it
+    from . import build as _build
+    L.vlb_build_hash.restype = ctypes.c_char_p
+    L.vlb_build_hash.argtypes = []
+    built, want = L.vlb_build_hash().decode(), _build.source_hash()
+    if built != want:
+        raise VlbLibraryStale(
+            f"{LIB_PATH} was built from other sources (hash {built}, sources "
+            f"{want}); run paper_2410_23802_amd.build.build()")
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     sig = {
         "vlb_create": ([ctypes.POINTER(vlb_domain_desc), vp,
@@ -123,6 +136,7 @@ def lib():
                              ctypes.c_int),
         "vlb_device_bytes": ([vp], ctypes.c_size_t),
         "vlb_last_error": ([vp], ctypes.c_char_p),
+        "vlb_build_hash": ([], ctypes.c_char_p),
         "vlb_destroy": ([vp], None),
         "vlb_batch_create": ([i32, ctypes.POINTER(vlb_domain_desc),
                               ctypes.POINTER(i32),

@@ -102,3 +102,36 @@ def test_batch_create_rejects_bad_arguments(vlb):
     assert h.value is None
     assert L.vlb_batch_step(None, 1) == vlb.VLB_EINVAL
     L.vlb_batch_destroy(None)
+
+
+def test_library_carries_the_hash_of_its_sources(vlb):
+    from paper_2410_23802_amd import build as hb
+    assert vlb.lib().vlb_build_hash().decode() == hb.source_hash()
+
+
+def test_stale_library_is_refused(vlb, monkeypatch):
+    """A library built from other sources than those beside it does not
+    load: the binding compares the hash the library carries with the
+    sources'."""
+    from paper_2410_23802_amd import build as hb
+    saved = vlb._lib
+    try:
+        vlb._lib = None
+        monkeypatch.setattr(hb, "source_hash", lambda: "0" * 16)
+        with pytest.raises(vlb.VlbLibraryStale):
+            vlb.lib()
+    finally:
+        vlb._lib = saved
+
+
+def test_c_example_is_built_and_checks_its_arguments():
+    """The plain C caller of the ABI is built beside the library; without
+    its three arguments it prints its usage and exits 2 (before any GPU
+    call)."""
+    import subprocess
+    from paper_2410_23802_amd import build as hb
+    if not os.path.exists(hb.EXAMPLE):
+        hb.build_example()
+    r = subprocess.run([hb.EXAMPLE], capture_output=True, text=True,
+                       timeout=60)
+    assert r.returncode == 2 and "usage" in r.stderr
