@@ -71,8 +71,8 @@ class _Domain(ctypes.Structure):
 class _Particle(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("x", "y", "theta", "ux", "uy", "omega", "radius", "rho_s",
-                 "T_init")] + [("fixed", ctypes.c_int32),
-                               ("hold_T", ctypes.c_int32)]
+                 "T_init", "radius_minor")] + [("fixed", ctypes.c_int32),
+                                               ("hold_T", ctypes.c_int32)]
 
 
 class _PState(ctypes.Structure):
@@ -125,6 +125,8 @@ def lib(variant: str = "plain"):
         L.or_overlap_count.argtypes = [vp]
         L.or_disk_cell_area.argtypes = [ctypes.c_double] * 5
         L.or_disk_cell_area.restype = ctypes.c_double
+        L.or_ellipse_cell_area.argtypes = [ctypes.c_double] * 7
+        L.or_ellipse_cell_area.restype = ctypes.c_double
         L.or_cell_in_band.argtypes = [ctypes.c_double] * 3 + [i32, i32]
         L.or_cell_inside.argtypes = [ctypes.c_double] * 3 + [i32, i32]
         L.or_collision_force.argtypes = [vp, i32, dptr, dptr]
@@ -163,6 +165,7 @@ def _particles_struct(ps):
         for name in ("x", "y", "theta", "ux", "uy", "omega", "radius", "rho_s",
                      "T_init"):
             setattr(arr[k], name, float(p[name]))
+        arr[k].radius_minor = float(p.get("radius_minor", 0.0))
         arr[k].fixed = int(p["fixed"])
         arr[k].hold_T = int(p.get("hold_T", 0))
     return arr
@@ -280,6 +283,11 @@ class Oracle:
 def disk_cell_area(cx, cy, R, x0, y0) -> float:
     return lib().or_disk_cell_area(float(cx), float(cy), float(R), float(x0),
                                    float(y0))
+
+
+def ellipse_cell_area(cx, cy, a, b, th, x0, y0) -> float:
+    return lib().or_ellipse_cell_area(float(cx), float(cy), float(a), float(b),
+                                      float(th), float(x0), float(y0))
 
 
 def cell_in_band(X, Y, R, i, j) -> bool:

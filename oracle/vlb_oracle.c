@@ -80,6 +80,7 @@ struct or_state {
    * step's velocities for the backward differences of Sec. 2.3 */
   double *X, *Y, *th, *Ux, *Uy, *Om, *Uxp, *Uyp, *Omp;
   double *R, *rhos, *Tp0;
+  double *Rb;  /* minor semi-axis: R for a disk, < R for an ellipse */
   int *fixed;
   int *hold;  /* 1: temperature held at Tp0 (stage 5b) */
   double *Fx, *Fy, *Tz; /* momentum-exchange force/torque, current step */
@@ -237,6 +238,104 @@ double or_disk_cell_area(double cx, double cy, double R, double x0,
   return A;
 }
 
+/* ------------------------------------------------------------------ */
+/* geometry: exact area of an ellipse intersected with a unit cell      */
+
+/* For the ellipse of semi-axes a (along (c, s) = (cos th, sin th)) and b
+ * centred at the origin, the points on the vertical line x = t have
+ *   y in [k t - h(t), k t + h(t)],  h(t) = g(t) / A,  g(t) = sqrt(A - m^2 t^2),
+ * with A = s^2/a^2 + c^2/b^2, k = c s (1/b^2 - 1/a^2) / A and m = 1/(a b):
+ * the quadratic form (x.(c,s))^2/a^2 + (x.(-s,c))^2/b^2 <= 1 solved for y.
+ * The line meets the ellipse for |t| <= W = sqrt(A)/m. */
+typedef struct {
+  double A, k, m, sA, W;
+} or_ellipse;
+
+static or_ellipse ellipse_of(double a, double b, double th) {
+  or_ellipse e;
+  double c = cos(th), s = sin(th);
+  e.A = s * s / (a * a) + c * c / (b * b);
+  e.k = c * s * (1.0 / (b * b) - 1.0 / (a * a)) / e.A;
+  e.m = 1.0 / (a * b);
+  e.sA = sqrt(e.A);
+  e.W = e.sA / e.m;
+  return e;
+}
+
+/* g(t), as a product so it stays accurate near |t| = W. */
+static double ellipse_g(const or_ellipse* e, double t) {
+  double mt = e->m * t;
+  if (mt <= -e->sA || mt >= e->sA) return 0.0;
+  return sqrt((e->sA - mt) * (e->sA + mt));
+}
+
+/* Integral of h(t) over [u, v] within [-W, W]:
+ *   [ (v g(v) - u g(u))/2 + A/(2m) (asin(v/W) - asin(u/W)) ] / A,
+ * the angle difference taken from its sine and cosine. */
+static double ellipse_h_integral(const or_ellipse* e, double u, double v) {
+  double gu = ellipse_g(e, u), gv = ellipse_g(e, v);
+  double ang = atan2(e->m * (v * gu - u * gv), gu * gv + e->m * e->m * u * v);
+  return (0.5 * (v * gv - u * gu) + 0.5 * e->A / e->m * ang) / e->A;
+}
+
+/* Solid fraction of the cell [x0, x0+1] x [y0, y0+1] covered by the
+ * ellipse of semi-axes a (major, at angle th to the x axis) and b centred
+ * at (cx, cy): the volume percentage of Sec. 2 for an elliptical particle
+ * (Sec. 3.2).  Reading: the exact area, integrated column by column as for
+ * the disk: A = int l(t) dt with l(t) = min(q1, k t + h) - max(q0, k t - h)
+ * clipped at zero, [t0, t1] split where k t +- h(t) crosses q0 or q1 (the
+ * roots of (A^2 k^2 + m^2) t^2 - 2 A^2 k q t + A^2 q^2 - A = 0). */
+double or_ellipse_cell_area(double cx, double cy, double a, double b,
+                            double th, double x0, double y0) {
+  or_ellipse e = ellipse_of(a, b, th);
+  double t0 = x0 - cx, t1 = (x0 + 1.0) - cx;
+  double q0 = y0 - cy, q1 = (y0 + 1.0) - cy;
+  double lo = t0 > -e.W ? t0 : -e.W, hi = t1 < e.W ? t1 : e.W;
+  if (!(lo < hi)) return 0.0;
+  double bp[6];
+  int n = 0;
+  bp[n++] = lo;
+  double qs[2] = {q0, q1};
+  double qa = e.A * e.A * e.k * e.k + e.m * e.m;
+  for (int r = 0; r < 2; ++r) {
+    double qb = -2.0 * e.A * e.A * e.k * qs[r];
+    double qc = e.A * e.A * qs[r] * qs[r] - e.A;
+    double disc = qb * qb - 4.0 * qa * qc;
+    if (!(disc > 0.0)) continue;
+    double sd = sqrt(disc);
+    double ra = (-qb - sd) / (2.0 * qa), rb = (-qb + sd) / (2.0 * qa);
+    if (ra > lo && ra < hi) bp[n++] = ra;
+    if (rb > lo && rb < hi) bp[n++] = rb;
+  }
+  bp[n++] = hi;
+  for (int u = 1; u < n; ++u) /* insertion sort of at most six points */
+    for (int w = u; w > 0 && bp[w - 1] > bp[w]; --w) {
+      double t = bp[w];
+      bp[w] = bp[w - 1];
+      bp[w - 1] = t;
+    }
+  double S = 0.0;
+  for (int r = 0; r + 1 < n; ++r) {
+    double u = bp[r], v = bp[r + 1];
+    if (!(u < v)) continue;
+    double tm = 0.5 * (u + v);
+    double hm = ellipse_g(&e, tm) / e.A;
+    double up = e.k * tm + hm, dn = e.k * tm - hm;
+    double top = q1 < up ? q1 : up, bot = q0 > dn ? q0 : dn;
+    if (!(top > bot)) continue; /* the strip misses the ellipse here */
+    double lin = 0.5 * e.k * (v * v - u * u), hint = ellipse_h_integral(&e, u, v);
+    double piece = 0.0;
+    if (q1 < up) piece += q1 * (v - u);      /* upper limit: y = q1 */
+    else piece += lin + hint;                /* upper limit: ellipse */
+    if (q0 > dn) piece -= q0 * (v - u);      /* lower limit: y = q0 */
+    else piece -= lin - hint;                /* lower limit: ellipse */
+    S += piece;
+  }
+  if (S < 0.0) S = 0.0;
+  if (S > 1.0) S = 1.0;
+  return S;
+}
+
 /* Ownership predicate (integer work; no fused operations): the closed cell
  * [i, i+1] x [j, j+1] meets the open disk, i.e. the point of the cell
  * nearest to the centre lies strictly inside the circle. */
@@ -308,7 +407,7 @@ static void* zalloc(size_t n) { return calloc(n ? n : 1, 1); }
 void or_destroy(or_state* s) {
   if (!s) return;
   double* dp[] = {s->X,    s->Y,   s->th,  s->Ux,  s->Uy,    s->Om,
-                  s->Uxp,  s->Uyp, s->Omp, s->R,   s->rhos,  s->Tp0,
+                  s->Uxp,  s->Uyp, s->Omp, s->R,   s->rhos,  s->Tp0, s->Rb,
                   s->Fx,   s->Fy,  s->Tz,  s->Tmean, s->Tmin, s->E,
                   s->fssum, s->Fabs, s->f, s->g, s->fst, s->gst, s->dfs,
                   s->fs,   s->fs_next, s->rho, s->ux, s->uy, s->T,
@@ -336,6 +435,8 @@ int or_create(const or_domain* d, int32_t np, const or_particle* p,
     return OR_EINVAL;
   for (int k = 0; k < np; ++k) {
     if (!(p[k].radius > 0.0) || !(p[k].rho_s > 0.0)) return OR_EINVAL;
+    if (!(p[k].radius_minor >= 0.0) || p[k].radius_minor > p[k].radius)
+      return OR_EINVAL;
     if (d->face_flow[0] == OR_PERIODIC && !(d->nx > 2.0 * p[k].radius + 4.0))
       return OR_EINVAL;
     if (d->face_flow[2] == OR_PERIODIC && !(d->ny > 2.0 * p[k].radius + 4.0))
@@ -350,7 +451,7 @@ int or_create(const or_domain* d, int32_t np, const or_particle* p,
   size_t nc = (size_t)d->nx * d->ny, K = (size_t)d->kmax, n = (size_t)np;
   double** dp[] = {&s->X,   &s->Y,    &s->th,  &s->Ux,    &s->Uy,
                    &s->Om,  &s->Uxp,  &s->Uyp, &s->Omp,   &s->R,
-                   &s->rhos, &s->Tp0, &s->Fx,  &s->Fy,    &s->Tz,
+                   &s->rhos, &s->Tp0, &s->Rb,  &s->Fx,    &s->Fy,  &s->Tz,
                    &s->Tmean, &s->Tmin, &s->E, &s->fssum, &s->Fabs};
   for (size_t k = 0; k < sizeof(dp) / sizeof(dp[0]); ++k)
     *dp[k] = (double*)zalloc(sizeof(double) * n);
@@ -383,6 +484,7 @@ int or_create(const or_domain* d, int32_t np, const or_particle* p,
     s->Uy[k] = p[k].uy;
     s->Om[k] = p[k].omega;
     s->R[k] = p[k].radius;
+    s->Rb[k] = p[k].radius_minor > 0.0 ? p[k].radius_minor : p[k].radius;
     s->rhos[k] = p[k].rho_s;
     s->Tp0[k] = p[k].T_init;
     s->fixed[k] = p[k].fixed;
@@ -493,9 +595,12 @@ static void particle_update(or_state* s) {
   for (int i = 0; i < np; ++i)
     or_collision_force(s, i, &nFx[i], &nFy[i]); /* from positions at n */
   for (int i = 0; i < np; ++i) {
-    double R = s->R[i];
-    double V = M_PI * R * R;
-    double Mp = s->rhos[i] * V, Ip = 0.5 * Mp * R * R;
+    double R = s->R[i], Rb = s->Rb[i];
+    double V = M_PI * R * Rb;  /* disk: pi R^2; ellipse: pi a b */
+    double Mp = s->rhos[i] * V;
+    /* moment of inertia about the centre: M R^2/2 for a disk, M (a^2 +
+     * b^2)/4 for an ellipse of semi-axes a, b */
+    double Ip = Rb == R ? 0.5 * Mp * R * R : 0.25 * Mp * (R * R + Rb * Rb);
     double Min = d->rho_f * Mp / s->rhos[i]; /* M_in = rho_f M / rho_s */
     double Iin = d->rho_f * Ip / s->rhos[i];
     double Ux = s->Ux[i], Uy = s->Uy[i], Om = s->Om[i];
@@ -571,9 +676,17 @@ static int geometry(or_state* s, double* fs_out) {
         }
         size_t slot = c * K + (size_t)n;
         s->ids[slot] = p;
-        int inside = or_cell_inside(Xi, Yi, R, i, j);
+        /* Reading for an ellipse (semi-axes R > Rb): its band is that of
+         * the circumscribed disk (radius R) and a cell is wholly inside
+         * when it lies in the inscribed disk (radius Rb), which keeps both
+         * integer decisions free of the orientation; the share is the
+         * exact area (zero for band cells the ellipse misses). */
+        double Rb = s->Rb[p];
+        int inside = or_cell_inside(Xi, Yi, Rb, i, j);
         s->full[slot] = inside;
-        s->fsp[slot] = inside ? 1.0 : or_disk_cell_area(Xi, Yi, R, i, j);
+        s->fsp[slot] = inside ? 1.0
+                       : Rb == R ? or_disk_cell_area(Xi, Yi, R, i, j)
+                       : or_ellipse_cell_area(Xi, Yi, R, Rb, s->th[p], i, j);
         /* u_s = U_c + Omega_c x (x - X_c), x the node (eq. us) */
         double rx = (i + 0.5) - Xi, ry = (j + 0.5) - Yi;
         s->usx[slot] = s->Ux[p] - s->Om[p] * ry;

@@ -56,6 +56,9 @@ typedef struct {
 
 typedef struct {
   double x, y, theta, ux, uy, omega, radius, rho_s, T_init;
+  double radius_minor;       /* 0 or radius: a disk; 0 < radius_minor <
+                                radius: an ellipse of semi-axes radius and
+                                radius_minor, its major axis at theta        */
   int32_t fixed;             /* 1: velocity prescribed (not integrated)      */
   int32_t hold_T;            /* 1: temperature held at T_init (stage 5b)     */
 } or_particle;
@@ -113,6 +116,8 @@ int  or_overlap_count(const or_state* s);
 
 /* Geometry primitives, exposed for the geometry pins. */
 double or_disk_cell_area(double cx, double cy, double R, double x0, double y0);
+double or_ellipse_cell_area(double cx, double cy, double a, double b,
+                            double th, double x0, double y0);
 int    or_cell_in_band(double X, double Y, double R, int32_t i, int32_t j);
 int    or_cell_inside(double X, double Y, double R, int32_t i, int32_t j);
 

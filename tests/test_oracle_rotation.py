@@ -18,6 +18,7 @@ outputs, against what the mathematics fixes:
 import math
 
 import numpy as np
+import pytest
 
 import workloads as W
 
@@ -60,20 +61,25 @@ def exchange(fs, fst, X, Y, U, V, Om):
         (np.abs(dpx) + np.abs(dpy)).sum()
 
 
-def test_spinning_disk_first_steps_closed_form(oracle_mod):
-    """A disk released spinning and translating in fluid at rest (no
-    gravity, no fluid force).  Step 1: the forces of the start are zero and
-    U^{-1} = U^0, so U^1 = U^0, Omega^1 = Omega^0, X^1 = X^0 + U^0; the
+@pytest.mark.parametrize("Rb", [0.0, 3.9])
+def test_spinning_disk_first_steps_closed_form(oracle_mod, Rb):
+    """A disk (or an ellipse of semi-axes R and Rb, Sec. 3.2) released
+    spinning and translating in fluid at rest (no gravity, no fluid force).
+    Step 1: the forces of the start are zero and U^{-1} = U^0, so U^1 = U^0,
+    Omega^1 = Omega^0, X^1 = X^0 + U^0, theta^1 = theta^0 + Omega^0; the
     momentum exchange of step 1 is that of the streamed equilibrium start.
     Step 2: U^2 = U^1 + F^1 / M, Omega^2 = Omega^1 + T^1 / I with
-    I = M R^2 / 2 (the inside-fluid terms vanish, U^1 = U^0).  Step 3: the
+    V = pi R Rb, I = M R^2 / 2 for a disk and M (R^2 + Rb^2) / 4 for an
+    ellipse (the inside-fluid terms vanish, U^1 = U^0).  Step 3: the
     inside-fluid terms of eq. inside.fluid enter with M_in = rho_f V and
-    I_in = M_in R^2 / 2."""
+    I_in = (rho_f / rho_s) I."""
     O = oracle_mod
     nx, ny, R, rho_s = 48, 44, 7.3, 1.6
-    X0, Y0, U0, V0, Om0 = 23.7, 21.2, 0.012, -0.007, 0.004
+    X0, Y0, U0, V0, Om0, th0 = 23.7, 21.2, 0.012, -0.007, 0.004, 0.7
     d = W.domain(nx, ny, tau_f=0.7, R_cv=2.0, R_lambda=3.0)
-    ps = [W.particle(X0, Y0, R, rho_s=rho_s, ux=U0, uy=V0, omega=Om0)]
+    ps = [W.particle(X0, Y0, R, rho_s=rho_s, ux=U0, uy=V0, omega=Om0,
+                     theta=th0, radius_minor=Rb)]
+    Rb = Rb or R
     o = O.Oracle(d, ps).init()
     fs0 = o.field("fs")
     xn, yn = nodes(nx, ny)
@@ -88,6 +94,8 @@ def test_spinning_disk_first_steps_closed_form(oracle_mod):
     X1, Y1 = X0 + U0, Y0 + V0
     assert p1["ux"] == U0 and p1["uy"] == V0 and p1["omega"] == Om0
     assert abs(p1["x"] - X1) < 1e-14 and abs(p1["y"] - Y1) < 1e-14
+    assert p1["theta"] == th0 + Om0
+    assert abs(p1["fs_sum"] - math.pi * R * Rb) < 1e-11
     Fx, Fy, Tz, Fabs = exchange(o.field("fs"), stream_periodic(f0), X1, Y1,
                                 U0, V0, Om0)
     assert abs(Tz) > 1e-4 * Fabs * R      # the rotation is felt
@@ -97,8 +105,8 @@ def test_spinning_disk_first_steps_closed_form(oracle_mod):
     # the fluid opposes the spin
     assert Tz * Om0 < 0
 
-    M = rho_s * math.pi * R * R
-    I = 0.5 * M * R * R
+    M = rho_s * math.pi * R * Rb
+    I = 0.25 * M * (R * R + Rb * Rb)
     o.step(1)
     p2 = o.particles()[0]
     assert abs(p2["omega"] - (Om0 + Tz / I)) < 1e-17
@@ -107,8 +115,8 @@ def test_spinning_disk_first_steps_closed_form(oracle_mod):
 
     o.step(1)
     p3 = o.particles()[0]
-    Min = 1.0 * math.pi * R * R
-    Iin = 0.5 * Min * R * R
+    Min = 1.0 * math.pi * R * Rb
+    Iin = I / rho_s
     Om3 = p2["omega"] + (p2["Tz"] + Iin * (p2["omega"] - Om0)) / I
     U3 = p2["ux"] + (p2["Fx"] + Min * (p2["ux"] - U0)) / M
     assert abs(p3["omega"] - Om3) < 1e-17

@@ -81,11 +81,14 @@ def walls(d: dict, which=(XLO, XHI, YLO, YHI), thermal="adiabatic",
 
 
 def particle(x, y, radius, rho_s=1.0, T_init=0.0, ux=0.0, uy=0.0, omega=0.0,
-             theta=0.0, fixed=False, hold_T=False) -> dict:
+             theta=0.0, fixed=False, hold_T=False, radius_minor=0.0) -> dict:
+    """A disk of the given radius, or (radius_minor in (0, radius)) an
+    ellipse of semi-axes radius and radius_minor whose major axis makes the
+    angle theta with the x axis."""
     return dict(x=float(x), y=float(y), theta=float(theta), ux=float(ux),
                 uy=float(uy), omega=float(omega), radius=float(radius),
                 rho_s=float(rho_s), T_init=float(T_init), fixed=int(bool(fixed)),
-                hold_T=int(bool(hold_T)))
+                hold_T=int(bool(hold_T)), radius_minor=float(radius_minor))
 
 
 def collision_params(rho_r: float, radius: float, g: float, zeta=2.0,
