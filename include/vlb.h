@@ -105,11 +105,20 @@ typedef struct {
 
 typedef struct {
   double x, y;               /* centre                                        */
-  double theta;              /* orientation (integrated, not used by a disk)  */
+  double theta;              /* orientation: the major axis's angle to the x
+                                axis (integrated; not used by a disk)        */
   double ux, uy, omega;      /* initial velocity and angular velocity         */
   double radius;             /* 0 < radius <= 28                              */
   double rho_s;              /* solid density                                 */
   double T_init;             /* initial particle temperature                  */
+  double radius_minor;       /* 0 (or radius): a disk of the given radius;
+                                0 < radius_minor < radius: an ellipse of
+                                semi-axes radius and radius_minor whose major
+                                axis makes the angle theta with the x axis
+                                (Sec. 3.2).  An ellipse's band of cells is
+                                that of its circumscribed disk, and a cell is
+                                wholly inside when its inscribed disk holds
+                                it; its share of a cell is the exact area     */
   int32_t fixed;             /* 1: velocity held (prescribed motion)          */
   int32_t hold_T;            /* 1: temperature held at T_init (a particle of
                                 fixed temperature, Sec. 3.3; the rule that
@@ -271,7 +280,8 @@ typedef struct {
 } vlb_batch_tuning;
 
 /* Create ncases domains: descs[ncases] (copied), nparticles[ncases] in
- * 0..64 and the particles of all domains back to back in `particles`
+ * 0..64 disks (no ellipses) and the particles of all domains back to back
+ * in `particles`
  * (host memory, copied; may be NULL when every count is 0).  VLB_EINVAL for
  * a bad descriptor (the message names the domain) or mixed precisions,
  * VLB_ENOMEM when the device memory does not suffice. */

@@ -373,6 +373,9 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
       return fail(c, VLB_EINVAL, "particle radius must be in (0, 28]");
     if (!(p[k].rho_s > 0.0))
       return fail(c, VLB_EINVAL, "particle density must be > 0");
+    if (!(p[k].radius_minor >= 0.0) || p[k].radius_minor > p[k].radius)
+      return fail(c, VLB_EINVAL,
+                  "radius_minor must be 0 (a disk) or in (0, radius]");
     if (c->P.perx && !(c->d.nx > 2.0 * p[k].radius + 4.0))
       return fail(c, VLB_EINVAL, "particle wider than the periodic x axis");
     if (c->P.pery && !(c->d.ny > 2.0 * p[k].radius + 4.0))
@@ -399,6 +402,11 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
   c->P.maxr = (int)(((int64_t)rows * c->d.nx + kBlock - 1) / kBlock) + 3;
   c->P.nfirst = c->P.scan ? (n * c->P.maxr + 7) / 8 * 8 : 0;
   set_stream_groups(c->P, n > 0 && !c->P.scan, c->prec);
+  c->P.ellipses = 0;
+  for (int k = 0; k < n; ++k)
+    if (p[k].radius_minor > 0.0 && p[k].radius_minor < p[k].radius)
+      c->P.ellipses = 1;
+  if (c->P.ellipses) c->P.pair_tiles = 0;
   const size_t part_slots =
       c->P.scan ? (size_t)n * c->P.nblocks : (size_t)n * c->maxb;
   c->initialized = false;
@@ -408,7 +416,7 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
     ok = ok && dalloc(c, (void**)&c->pmem[k], 12 * (size_t)n * sizeof(double));
     ok = ok && dalloc(c, (void**)&c->pslot[k], (size_t)n * sizeof(int));
   }
-  ok = ok && dalloc(c, (void**)&c->pconst, 3 * (size_t)n * sizeof(double));
+  ok = ok && dalloc(c, (void**)&c->pconst, 4 * (size_t)n * sizeof(double));
   ok = ok && dalloc(c, (void**)&c->pfixed, (size_t)n * sizeof(int));
   for (int k = 0; k < 2; ++k)
     ok = ok && dalloc(c, (void**)&c->partial[k],
@@ -420,6 +428,7 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
     c->P.np = 0;
     c->P.scan = 0;
     c->P.nfirst = 0;
+    c->P.ellipses = 0;
     set_stream_groups(c->P, false, c->prec);
     return fail(c, VLB_ENOMEM, "particle allocation failed");
   }
@@ -434,6 +443,7 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
   c->pc.R = c->pconst;
   c->pc.rhos = c->pconst + n;
   c->pc.Tinit = c->pconst + 2 * n;
+  c->pc.Rb = c->pconst + 3 * n;
   c->pc.fixed = c->pfixed;
   return VLB_OK;
 }
@@ -460,7 +470,7 @@ vlb_status vlb_init(vlb_ctx* c) {
   c->have_partials = 0;
   c->step = 0;
   if (n > 0) {
-    std::vector<double> host(12 * (size_t)n, 0.0), cst(3 * (size_t)n);
+    std::vector<double> host(12 * (size_t)n, 0.0), cst(4 * (size_t)n);
     std::vector<int> fx(n);
     for (int k = 0; k < n; ++k) {
       const vlb_particle_desc& p = c->parts[k];
@@ -476,6 +486,7 @@ vlb_status vlb_init(vlb_ctx* c) {
       cst[k] = p.radius;
       cst[n + k] = p.rho_s;
       cst[2 * n + k] = p.T_init;
+      cst[3 * n + k] = p.radius_minor > 0.0 ? p.radius_minor : p.radius;
       fx[k] = (p.fixed ? 1 : 0) | (p.hold_T ? 2 : 0);
     }
     HIP_TRY(c, hipMemcpyAsync(c->pmem[0], host.data(), host.size() * 8,
@@ -765,12 +776,15 @@ vlb_status vlb_load(vlb_ctx* c, const void* buf, size_t len) {
   HIP_TRY(c, hipMemcpyAsync(c->macro, o, 6 * N * 8, H2D, c->stream)); o += 6 * N * 8;
   if (c->np > 0) {
     const size_t n = (size_t)c->np;
-    std::vector<double> cst(3 * n);
+    std::vector<double> cst(4 * n);
     std::vector<int> fx(n);
     for (size_t k = 0; k < n; ++k) {
       cst[k] = c->parts[k].radius;
       cst[n + k] = c->parts[k].rho_s;
       cst[2 * n + k] = c->parts[k].T_init;
+      cst[3 * n + k] = c->parts[k].radius_minor > 0.0
+                           ? c->parts[k].radius_minor
+                           : c->parts[k].radius;
       fx[k] = (c->parts[k].fixed ? 1 : 0) | (c->parts[k].hold_T ? 2 : 0);
     }
     HIP_TRY(c, hipMemcpyAsync(c->pmem[0], o, 12 * n * 8, H2D, c->stream)); o += 12 * n * 8;

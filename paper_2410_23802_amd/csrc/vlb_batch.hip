@@ -154,6 +154,7 @@ static StepBufs to_offsets(StepBufs b, const char* a) {
   b.pc.R = arena_offset(b.pc.R, a);
   b.pc.rhos = arena_offset(b.pc.rhos, a);
   b.pc.Tinit = arena_offset(b.pc.Tinit, a);
+  b.pc.Rb = arena_offset(b.pc.Rb, a);
   b.pc.fixed = arena_offset(b.pc.fixed, a);
   b.L.cnt = arena_offset(b.L.cnt, a);
   b.L.ent = arena_offset(b.L.ent, a);
@@ -299,6 +300,9 @@ vlb_status vlb_batch_create(int32_t ncases, const vlb_domain_desc* descs,
     if (nparticles[i] > 0 && !c->P.scan)
       return give_up(VLB_EINVAL, "domain " + std::to_string(i) +
                                      ": too large for the batch form");
+    if (c->P.ellipses)   // the batch kernel carries the disk geometry only
+      return give_up(VLB_EINVAL, "domain " + std::to_string(i) +
+                                     ": batches hold disks only");
     off += nparticles[i];
     b->cells += c->P.N;
   }

@@ -42,9 +42,15 @@ __device__ __forceinline__ PState rebase_state(char* a, PState s) {
   return s;
 }
 
+// Every pointer of the two structures is rebased; a field added to either
+// must be added here too (the sizes below catch one that is not).
+static_assert(sizeof(PConst) == 5 * sizeof(void*), "rebase every PConst field");
+static_assert(sizeof(PState) == 13 * sizeof(void*), "rebase every PState field");
+
 __device__ __forceinline__ PConst rebase_const(char* a, PConst c) {
   c.R = rebase(a, c.R); c.rhos = rebase(a, c.rhos);
   c.Tinit = rebase(a, c.Tinit); c.fixed = rebase(a, c.fixed);
+  c.Rb = rebase(a, c.Rb);
   return c;
 }
 

@@ -214,6 +214,36 @@ __device__ __forceinline__ void tri_disk_parts(double px, double py,
   if (s2 < 1.0) sector_factor(bx, by, qx, qy, zr, zi);
 }
 
+// Area of the disk of radius R centred at the origin intersected with the
+// convex quadrilateral (u[k], v[k]), k = 0..3 counter-clockwise, by Green's
+// theorem over its edges: triangles from the centre to the parts of the
+// edges inside the circle, circular sectors for the parts outside.  When
+// the centre lies outside the closed quadrilateral the latter subtends less
+// than pi from it, so the sectors' net angle is in (-pi, pi) and one atan2
+// of the product of their complex factors gives it; otherwise (a disk
+// narrower than the cell) each sector is evaluated on its own.
+__device__ __forceinline__ double quad_disk_area(const double* u,
+                                                 const double* v, double R) {
+  bool inside = true;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int n = (k + 1) & 3;
+    inside = inside && (u[n] - u[k]) * -v[k] - (v[n] - v[k]) * -u[k] >= 0.0;
+  }
+  if (inside) {
+    double A = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      A += tri_disk_area(u[k], v[k], u[(k + 1) & 3], v[(k + 1) & 3], R);
+    return A;
+  }
+  double tri = 0.0, zr = 1.0, zi = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    tri_disk_parts(u[k], v[k], u[(k + 1) & 3], v[(k + 1) & 3], R, tri, zr, zi);
+  return tri + 0.5 * R * R * atan2(zi, zr);
+}
+
 // Exact share of cell (i, j) covered by the disk (centre X, Y, radius R),
 // by Green's theorem over the four edges of the square taken
 // counter-clockwise: triangles from the centre to the parts of the edges
@@ -238,6 +268,54 @@ __device__ double covered_share(double X, double Y, double R, int i, int j) {
     A = tri + 0.5 * R * R * atan2(zi, zr);
   }
   return fmin(fmax(A, 0.0), 1.0);
+}
+
+// Exact share of cell (i, j) covered by the ellipse of semi-axes a (the
+// major one, along (c, s) = (cos theta, sin theta)) and b centred at
+// (X, Y) (Sec. 3.2).  The map x -> ((c, s).x / a, (-s, c).x / b) takes the
+// ellipse to the unit disk and the cell to a parallelogram, still
+// counter-clockwise (the map's determinant is 1/(a b) > 0), whose
+// intersection with the unit disk is quad_disk_area's; areas scale by a b.
+__device__ __forceinline__ double ellipse_share(double X, double Y, double a,
+                                                double b, double c, double s,
+                                                int i, int j) {
+  const double x0 = (double)i - X, x1 = (double)(i + 1) - X;
+  const double y0 = (double)j - Y, y1 = (double)(j + 1) - Y;
+  const double cx[4] = {x0, x1, x1, x0}, cy[4] = {y0, y0, y1, y1};
+  const double ia = 1.0 / a, ib = 1.0 / b;
+  double u[4], v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    u[k] = (c * cx[k] + s * cy[k]) * ia;
+    v[k] = (c * cy[k] - s * cx[k]) * ib;
+  }
+  return fmin(fmax(a * b * quad_disk_area(u, v, 1.0), 0.0), 1.0);
+}
+
+// The share of cell (i, j) covered by a particle: a disk of radius R when
+// Rb == R, else the ellipse of semi-axes R and Rb at the angle whose cosine
+// and sine are (c, s).  ELL = false (no ellipse in the domain): the disk
+// only, so that the kernels of disk domains carry none of the ellipse's
+// code or registers (the step kernel of the 32-bit forms otherwise spills).
+template <bool ELL>
+__device__ __forceinline__ double shape_share(double X, double Y, double R,
+                                              double Rb, double c, double s,
+                                              int i, int j) {
+  if constexpr (ELL) {
+    if (Rb != R) return ellipse_share(X, Y, R, Rb, c, s, i, j);
+  }
+  return covered_share(X, Y, R, i, j);
+}
+
+// cos and sin of a particle's orientation (unused for a disk).
+__device__ __forceinline__ void orientation(double R, double Rb, double th,
+                                            double& c, double& s) {
+  if (Rb == R) {
+    c = 1.0;
+    s = 0.0;
+  } else {
+    sincos(th, &s, &c);
+  }
 }
 
 // -------------------------------------------------------------------------
@@ -609,7 +687,7 @@ struct PUpd {
 
 // One particle's stored state and constants, in registers.
 struct POne {
-  double X, Y, th, Ux, Uy, Om, Uxp, Uyp, Omp, R, rhos, Tinit;
+  double X, Y, th, Ux, Uy, Om, Uxp, Uyp, Omp, R, rhos, Tinit, Rb;
   int fixed;
 };
 
@@ -620,6 +698,7 @@ __device__ __forceinline__ POne load_one(const PState& s, const PConst& pc,
   o.Ux = s.Ux[p]; o.Uy = s.Uy[p]; o.Om = s.Om[p];
   o.Uxp = s.Uxp[p]; o.Uyp = s.Uyp[p]; o.Omp = s.Omp[p];
   o.R = pc.R[p]; o.rhos = pc.rhos[p]; o.Tinit = pc.Tinit[p];
+  o.Rb = pc.Rb[p];
   o.fixed = pc.fixed[p];
   return o;
 }
@@ -635,6 +714,7 @@ __device__ __forceinline__ POne lane_one(const POne& v, int src) {
   o.Omp = lane_value(v.Omp, src);
   o.R = lane_value(v.R, src); o.rhos = lane_value(v.rhos, src);
   o.Tinit = lane_value(v.Tinit, src);
+  o.Rb = lane_value(v.Rb, src);
   o.fixed = __builtin_amdgcn_readlane(v.fixed, src);
   return o;
 }
@@ -650,8 +730,12 @@ __device__ PUpd particle_update_one(const Params& P, const POne& s,
                                     double cx, double cy) {
   PUpd u;
   const double R = s.R, rs = s.rhos;
-  const double V = M_PI * R * R;
-  const double M = rs * V, I = 0.5 * M * R * R;
+  // a disk (Rb == R): V = pi R^2, I = M R^2 / 2; an ellipse of semi-axes
+  // R and Rb (Sec. 3.2): V = pi R Rb, I = M (R^2 + Rb^2) / 4
+  const double V = M_PI * R * s.Rb;
+  const double M = rs * V;
+  const double I = s.Rb == R ? 0.5 * M * R * R
+                             : 0.25 * M * (R * R + s.Rb * s.Rb);
   const double Min = P.rho_f * M / rs, Iin = P.rho_f * I / rs;
   const double Ux = s.Ux, Uy = s.Uy, Om = s.Om;
   u.Ux = Ux;
@@ -710,6 +794,9 @@ struct BlockParticles {
   int held[kListCap];   // 1: the particle's temperature is held (at Tp)
   double X[kListCap], Y[kListCap], R[kListCap];
   double Ux[kListCap], Uy[kListCap], Om[kListCap], Tp[kListCap];
+  // the shape: minor semi-axis (R for a disk) and the orientation's cosine
+  // and sine (1, 0 for a disk)
+  double Rb[kListCap], cth[kListCap], sth[kListCap];
 };
 
 __device__ __forceinline__ void load_block_list(BlockParticles& bp, int* tmp,
@@ -746,6 +833,9 @@ __device__ __forceinline__ void load_block_list(BlockParticles& bp, int* tmp,
     bp.Uy[rank] = pn.Uy[e.x];
     bp.Om[rank] = pn.Om[e.x];
     bp.Tp[rank] = pc.Tinit[e.x];
+    bp.Rb[rank] = pc.Rb[e.x];
+    orientation(bp.R[rank], bp.Rb[rank], pn.th[e.x], bp.cth[rank],
+                bp.sth[rank]);
     bp.held[rank] = (pc.fixed[e.x] >> 1) & 1;
     if (bp.held[rank]) atomicAdd(&bp.nheld, 1);
   }
@@ -787,6 +877,9 @@ __device__ __forceinline__ void load_block_list_known(BlockParticles& bp,
     bp.Uy[rank] = pn.Uy[e.x];
     bp.Om[rank] = pn.Om[e.x];
     bp.Tp[rank] = pc.Tinit[e.x];
+    bp.Rb[rank] = pc.Rb[e.x];
+    orientation(bp.R[rank], bp.Rb[rank], pn.th[e.x], bp.cth[rank],
+                bp.sth[rank]);
     bp.held[rank] = (pc.fixed[e.x] >> 1) & 1;
     if (bp.held[rank]) atomicAdd(&bp.nheld, 1);
   }
@@ -807,10 +900,11 @@ __device__ __forceinline__ bool slot_geometry(const BlockParticles& bp, int s,
   double xn = (double)i + 0.5, yn = (double)j + 0.5;
   double X = near_copy(bp.X[s], xn, (double)P.nx, P.perx);
   double Y = near_copy(bp.Y[s], yn, (double)P.ny, P.pery);
-  double R = bp.R[s];
+  double R = bp.R[s], Rb = bp.Rb[s];
   if (!owns_cell(X, Y, R, i, j)) return false;
-  g.full = cell_within(X, Y, R, i, j);
-  g.fs = g.full ? 1.0 : covered_share(X, Y, R, i, j);
+  g.full = cell_within(X, Y, Rb, i, j);
+  g.fs = g.full ? 1.0
+                : shape_share<true>(X, Y, R, Rb, bp.cth[s], bp.sth[s], i, j);
   g.rx = xn - X;
   g.ry = yn - Y;
   g.usx = bp.Ux[s] - bp.Om[s] * g.ry;
@@ -859,6 +953,10 @@ __device__ void scan_block(BlockParticles& bp, const Params& P, int b,
       bp.Y[rank] = Y;
       bp.R[rank] = own.R;
       bp.Tp[rank] = own.Tinit;
+      bp.Rb[rank] = own.Rb;
+      // theta^{n+1} = theta^n + Omega^n (forward Euler, Sec. 2.3)
+      orientation(own.R, own.Rb, advance ? own.th + own.Om : own.th,
+                  bp.cth[rank], bp.sth[rank]);
       bp.held[rank] = (own.fixed >> 1) & 1;
     }
     const unsigned long long mw = __ballot(cand || store);
@@ -918,17 +1016,19 @@ __device__ void scan_block(BlockParticles& bp, const Params& P, int b,
 // Geometry of a particle (centre X, Y, radius R, velocity U, Omega) for the
 // cell (i, j): covered share and solid velocity u_s = U + Omega x (x - X) at
 // the node (eq. us).  False when the particle does not reach the cell.
+template <bool ELL>
 __device__ __forceinline__ bool particle_geometry(const Params& P, double Xp,
                                                   double Yp, double R,
-                                                  double Ux, double Uy,
-                                                  double Om, int i, int j,
-                                                  SlotGeom& g) {
+                                                  double Rb, double cth,
+                                                  double sth, double Ux,
+                                                  double Uy, double Om, int i,
+                                                  int j, SlotGeom& g) {
   const double xn = (double)i + 0.5, yn = (double)j + 0.5;
   const double X = near_copy(Xp, xn, (double)P.nx, P.perx);
   const double Y = near_copy(Yp, yn, (double)P.ny, P.pery);
   if (!owns_cell(X, Y, R, i, j)) return false;
-  g.full = cell_within(X, Y, R, i, j);
-  g.fs = g.full ? 1.0 : covered_share(X, Y, R, i, j);
+  g.full = cell_within(X, Y, Rb, i, j);
+  g.fs = g.full ? 1.0 : shape_share<ELL>(X, Y, R, Rb, cth, sth, i, j);
   g.rx = xn - X;
   g.ry = yn - Y;
   g.usx = Ux - Om * g.ry;
@@ -1490,7 +1590,8 @@ __device__ __forceinline__ unsigned long long wave_particle_mask(
 // blocks filled (the same advanced positions and band boxes); otherwise
 // (a batch) they test them, one particle per lane.  List form: each tile
 // in the role its block count gives.
-template <int PREC, bool OUT, bool SCAN, bool COUNTED = false>
+template <int PREC, bool OUT, bool SCAN, bool COUNTED = false,
+          bool ELL = false>
 __device__ __forceinline__ void step_task(
     const Params& P, const Hot<typename Prec<PREC>::C>& H, const StepBufs& B,
     int have, int tile, bool ptile, TileShared<typename Prec<PREC>::C>& sh,
@@ -1552,7 +1653,7 @@ __device__ __forceinline__ void step_task(
       if (!owns_cell(X, Y, R, cx, cy)) continue;
       if (nin < kShareCache) {
         sh.slot[nin][t] = (unsigned char)k;
-        if (cell_within(X, Y, R, cx, cy))
+        if (cell_within(X, Y, sh.bp.Rb[k], cx, cy))
           sh.share[nin][t] = (C)1;
         else
           cut |= 1u << nin;
@@ -1569,7 +1670,9 @@ __device__ __forceinline__ void step_task(
         const int k = sh.slot[0][t];
         const double X = near_copy(sh.bp.X[k], xn, (double)P.nx, P.perx);
         const double Y = near_copy(sh.bp.Y[k], yn, (double)P.ny, P.pery);
-        sh.share[0][t] = (C)covered_share(X, Y, sh.bp.R[k], cx, cy);
+        sh.share[0][t] = (C)shape_share<ELL>(X, Y, sh.bp.R[k], sh.bp.Rb[k],
+                                             sh.bp.cth[k], sh.bp.sth[k], cx,
+                                             cy);
       }
     } else {
       const int mine = __popc(cut);
@@ -1596,7 +1699,9 @@ __device__ __forceinline__ void step_task(
             near_copy(sh.bp.X[k], (double)i + 0.5, (double)P.nx, P.perx);
         const double Y =
             near_copy(sh.bp.Y[k], (double)j + 0.5, (double)P.ny, P.pery);
-        sh.share[e][tt] = (C)covered_share(X, Y, sh.bp.R[k], i, j);
+        sh.share[e][tt] = (C)shape_share<ELL>(X, Y, sh.bp.R[k], sh.bp.Rb[k],
+                                              sh.bp.cth[k], sh.bp.sth[k], i,
+                                              j);
       }
       __syncthreads();
     }
@@ -1627,7 +1732,8 @@ __device__ __forceinline__ void step_task(
       for (int k = sh.slot[kShareCache - 1][t] + 1; k < cnt; ++k) {
         if (!((wmask >> k) & 1ull)) continue;
         SlotGeom sg;
-        if (particle_geometry(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.R[k],
+        if (particle_geometry<ELL>(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.R[k],
+                              sh.bp.Rb[k], sh.bp.cth[k], sh.bp.sth[k],
                               sh.bp.Ux[k], sh.bp.Uy[k], sh.bp.Om[k], cx, cy,
                               sg)) {
           const C a = (C)sg.fs, ux = (C)sg.usx, uy = (C)sg.usy;
@@ -1757,7 +1863,8 @@ __device__ __forceinline__ void step_task(
         ++e;
       } else if (e == kShareCache && nreach > kShareCache) {
         SlotGeom sg;                 // past the cache: recompute
-        if (particle_geometry(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.R[k],
+        if (particle_geometry<ELL>(P, sh.bp.X[k], sh.bp.Y[k], sh.bp.R[k],
+                              sh.bp.Rb[k], sh.bp.cth[k], sh.bp.sth[k],
                               sh.bp.Ux[k], sh.bp.Uy[k], sh.bp.Om[k], cx, cy,
                               sg)) {
           a = (C)sg.fs;

@@ -61,6 +61,8 @@ struct Params {
                       // (0: the XCD groups)
   int pair_tiles;     // step kernel, 16-bit forms: two plain tiles per
                       // streaming block (never in the list form)
+  int ellipses;       // some particle is an ellipse (its kernels carry the
+                      // ellipse geometry; no paired tiles)
 };
 
 // The constants the per-cell arithmetic uses, in the compute precision C
@@ -105,6 +107,7 @@ struct PState {
 
 struct PConst {
   const double *R, *rhos, *Tinit;
+  const double* Rb;   // minor semi-axis: R for a disk, < R for an ellipse
   const int* fixed;   // bit 0: velocity held; bit 1: temperature held at Tinit
 };
 

@@ -14,7 +14,7 @@ namespace vlb {
 // (and the LDS of a particle tile caps a CU at 7 blocks).  PAIR (16-bit
 // forms, where the host sets pair_tiles): the streaming blocks take two
 // tiles each; a kernel of its own, so that the one-tile path keeps its code.
-template <int PREC, bool OUT, bool SCAN, bool PAIR>
+template <int PREC, bool OUT, bool SCAN, bool PAIR, bool ELL>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 5))) void k_step(
     const Params P, const Hot<typename Prec<PREC>::C> H, const StepBufs B,
@@ -53,7 +53,7 @@ __attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 5))) void k_step(
     lcnt = B.L.cnt[tile];                                // uniform
     ptile = lcnt != 0;
   }
-  step_task<PREC, OUT, SCAN, SCAN && counted_tiles(PREC, PAIR)>(
+  step_task<PREC, OUT, SCAN, SCAN && counted_tiles(PREC, PAIR), ELL>(
       P, H, B, have, tile, ptile, sh, lcnt, lent);
 }
 
@@ -475,7 +475,9 @@ __global__ __launch_bounds__(256) void k_particle_sums(
     const Params P, PState ps, PConst pc, const double* __restrict__ macro,
     double* __restrict__ out4) {
   const int p = blockIdx.x;
-  const double X0 = ps.X[p], Y0 = ps.Y[p], R = pc.R[p];
+  const double X0 = ps.X[p], Y0 = ps.Y[p], R = pc.R[p], Rb = pc.Rb[p];
+  double cth, sth;
+  orientation(R, Rb, ps.th[p], cth, sth);
   int i0 = 0, i1 = -1, j0 = 0, j1 = -1;
   if (centre_ok(P, X0, Y0)) band_box(P, X0, Y0, R, i0, i1, j0, j1);
   const int w = max(i1 - i0 + 1, 0), h = max(j1 - j0 + 1, 0);
@@ -489,8 +491,9 @@ __global__ __launch_bounds__(256) void k_particle_sums(
     const double X = near_copy(X0, xn, (double)P.nx, P.perx);
     const double Y = near_copy(Y0, yn, (double)P.ny, P.pery);
     if (!owns_cell(X, Y, R, i, j)) continue;
-    const bool full = cell_within(X, Y, R, i, j);
-    const double a = full ? 1.0 : covered_share(X, Y, R, i, j);
+    const bool full = cell_within(X, Y, Rb, i, j);
+    const double a =
+        full ? 1.0 : shape_share<true>(X, Y, R, Rb, cth, sth, i, j);
     const double Tc = Tf[(size_t)j * P.nx + i];
     s0 += a;
     s1 += a * Tc;
@@ -556,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_ownership(
     if (!owns_cell(X, Y, bp.R[s], x, y)) continue;
     if (n < P.kmax) {
       ids[n] = bp.pid[s];
-      full[n] = cell_within(X, Y, bp.R[s], x, y) ? 1 : 0;
+      full[n] = cell_within(X, Y, bp.Rb[s], x, y) ? 1 : 0;
     }
     ++n;
   }
@@ -632,7 +635,7 @@ hipError_t launch_particles(const Params& P, PState cur, PState next,
   return hipGetLastError();
 }
 
-template <int PREC, bool OUT, bool SCAN, bool PAIR>
+template <int PREC, bool OUT, bool SCAN, bool PAIR, bool ELL>
 static hipError_t step_t(const StepLaunch& a, hipStream_t s) {
   const Params& P = *a.P;
   // the host keeps the tile counts exactly where this kernel reads them
@@ -641,26 +644,33 @@ static hipError_t step_t(const StepLaunch& a, hipStream_t s) {
     return hipErrorInvalidValue;
   const Hot<typename Prec<PREC>::C> H = make_hot<typename Prec<PREC>::C>(P);
   const unsigned grid = (unsigned)(P.nfirst + stream_grid(P, PAIR));
-  hipExtLaunchKernelGGL((k_step<PREC, OUT, SCAN, PAIR>), dim3(grid),
+  hipExtLaunchKernelGGL((k_step<PREC, OUT, SCAN, PAIR, ELL>), dim3(grid),
                         dim3(kBlock), 0, s, a.ev_start, a.ev_stop, 0, P, H,
                         a.B, a.have);
   return hipGetLastError();
 }
 
-template <int PREC, bool PAIR>
+template <int PREC, bool PAIR, bool ELL>
 static hipError_t step_q(const StepLaunch& a, hipStream_t s) {
   if (a.P->scan)
-    return a.out ? step_t<PREC, true, true, PAIR>(a, s)
-                 : step_t<PREC, false, true, PAIR>(a, s);
-  return a.out ? step_t<PREC, true, false, PAIR>(a, s)
-               : step_t<PREC, false, false, PAIR>(a, s);
+    return a.out ? step_t<PREC, true, true, PAIR, ELL>(a, s)
+                 : step_t<PREC, false, true, PAIR, ELL>(a, s);
+  return a.out ? step_t<PREC, true, false, PAIR, ELL>(a, s)
+               : step_t<PREC, false, false, PAIR, ELL>(a, s);
 }
 
+// A domain holding ellipses runs the step kernel built with their geometry
+// (never with paired tiles, which the host turns off for it); disk domains
+// run kernels without it.
 template <int PREC>
 static hipError_t step_p(const StepLaunch& a, hipStream_t s) {
+  if (a.P->ellipses) {
+    if (a.P->pair_tiles) return hipErrorInvalidValue;
+    return step_q<PREC, false, true>(a, s);
+  }
   if constexpr (kPairedTiles<PREC>)
-    if (a.P->pair_tiles) return step_q<PREC, true>(a, s);
-  return step_q<PREC, false>(a, s);
+    if (a.P->pair_tiles) return step_q<PREC, true, false>(a, s);
+  return step_q<PREC, false, false>(a, s);
 }
 
 hipError_t launch_step(int prec, const StepLaunch& a, hipStream_t s) {

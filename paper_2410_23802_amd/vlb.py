@@ -72,8 +72,8 @@ class vlb_domain_desc(ctypes.Structure):
 class vlb_particle_desc(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("x", "y", "theta", "ux", "uy", "omega", "radius", "rho_s",
-                 "T_init")] + [("fixed", ctypes.c_int32),
-                               ("hold_T", ctypes.c_int32)]
+                 "T_init", "radius_minor")] + [("fixed", ctypes.c_int32),
+                                               ("hold_T", ctypes.c_int32)]
 
 
 class vlb_batch_tuning(ctypes.Structure):
@@ -208,6 +208,7 @@ def make_particles(ps) -> ctypes.Array:
         for name in ("x", "y", "theta", "ux", "uy", "omega", "radius", "rho_s",
                      "T_init"):
             setattr(arr[k], name, float(p[name]))
+        arr[k].radius_minor = float(p.get("radius_minor", 0.0))
         arr[k].fixed = int(p["fixed"])
         arr[k].hold_T = int(p.get("hold_T", 0))
     return arr

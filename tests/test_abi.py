@@ -37,15 +37,14 @@ def test_descriptor_mirror_matches_header_field_order(vlb):
 
 def test_particle_mirror_matches_header(vlb):
     """The ctypes mirror of vlb_particle_desc lists the header's members in
-    order, and the struct keeps its 80-byte size (hold_T fills the padding
-    after fixed)."""
+    order, and the struct is ten doubles and two int32 (88 bytes)."""
     import re
     with open(vlb.HEADER) as fh:
         txt = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
     body = re.search(r"typedef struct \{([^}]*)\} vlb_particle_desc;", txt)
     decl = re.findall(r"\b([A-Za-z_]\w*)\s*(?:\[[^\]]*\])*\s*[,;]", body.group(1))
     assert decl == [f[0] for f in vlb.vlb_particle_desc._fields_]
-    assert ctypes.sizeof(vlb.vlb_particle_desc) == 80
+    assert ctypes.sizeof(vlb.vlb_particle_desc) == 88
 
 
 @pytest.mark.parametrize("patch,msg", [

@@ -742,3 +742,67 @@ def test_list_form_reads_between_steps_keep_the_bits(vlb, prec):
         assert np.array_equal(pa[k], pc[k]), k
     for x in (a, b, c):
         x.close()
+
+
+# --------------------------------------------------------------------------
+# elliptical particles (Sec. 3.2)
+
+
+def test_ellipse_scan_form_fp64(vlb, oracle_mod):
+    """One ellipse (semi-axes 7.5 and 3.2), spinning and translating in a
+    periodic box with gravity and buoyancy: its shares (exact ellipse-cell
+    areas at the advanced orientation), the flow and temperature fields and
+    its state, torque included, against the oracle after 60 steps."""
+    d = W.domain(64, 60, tau_f=0.7, lambda_f=0.05, R_lambda=4.0, R_cv=2.0,
+                 gravity=(0.0, -2e-5), beta=0.4, init_T=1.0)
+    ps = [W.particle(30.3, 28.9, 7.5, radius_minor=3.2, theta=0.6,
+                     rho_s=1.3, T_init=0.2, ux=0.01, uy=-0.004, omega=0.006)]
+    say("case: ellipse scan form fp64 60 steps")
+    g, o = run_pair(vlb, oracle_mod, d, ps, 60)
+    e = field_errors(g, o)
+    keys = ("x", "y", "ux", "uy", "omega", "Fx", "Fy", "Tz")
+    e.update(particle_errors(g, o, keys))
+    pa, pb = g.particles()[0], o.particles()[0]
+    e["theta"] = abs(pa["theta"] - pb["theta"])
+    for k in ("T_mean", "T_min", "E_solid", "fs_sum"):
+        e[k] = abs(pa[k] - pb[k]) / max(abs(pb[k]), 1e-300)
+    check(e, 60, twin=twin_errors(oracle_mod, d, ps, 60, o, pkeys=keys))
+
+
+def test_ellipse_scan_form_fp32(vlb, oracle_mod):
+    d = W.domain(64, 60, tau_f=0.7, lambda_f=0.05, R_lambda=4.0, R_cv=2.0,
+                 gravity=(0.0, -2e-5), beta=0.4, init_T=1.0)
+    ps = [W.particle(30.3, 28.9, 7.5, radius_minor=3.2, theta=0.6,
+                     rho_s=1.3, T_init=0.2, ux=0.01, uy=-0.004, omega=0.006)]
+    say("case: ellipse scan form fp32 60 steps")
+    g, o = run_pair(vlb, oracle_mod, d, ps, 60, "fp32")
+    e = field_errors(g, o)
+    e.update(particle_errors(g, o, ("x", "y", "ux", "uy", "omega")))
+    say(f"  fp32 ellipse errors: {e}")
+    bad = {k: v for k, v in e.items() if v >= FP32_BAR.get(k, 1e-5)}
+    assert not bad, (bad, e)
+
+
+def test_ellipses_list_form_fp64(vlb, oracle_mod):
+    """80 ellipses of random orientation and aspect ratio in a walled box
+    (the list form), settling and colliding: against the oracle."""
+    rng = np.random.default_rng(31)
+    d = W.walls(W.domain(240, 200, tau_f=0.7, lambda_f=0.05, R_lambda=3.0,
+                         R_cv=1.5, gravity=(0.0, -4e-5), beta=0.1,
+                         init_T=1.0, coll_range=2.0, coll_stiff_pp=2e-3,
+                         coll_stiff_pw=4e-3), thermal="adiabatic")
+    pts = W.rsa_disks(80, 6.0, (0.0, 0.0, 240.0, 200.0), 1.0, seed=9)
+    ps = [W.particle(x, y, 6.0, radius_minor=rng.uniform(2.0, 5.5),
+                     theta=rng.uniform(0, np.pi), rho_s=rng.uniform(1.2, 2.0),
+                     T_init=0.3, omega=rng.uniform(-0.01, 0.01))
+          for x, y in pts]
+    say("case: 80 ellipses list form fp64 30 steps")
+    g, o = run_pair(vlb, oracle_mod, d, ps, 30)
+    e = field_errors(g, o)
+    keys = ("x", "y", "ux", "uy", "omega", "Fx", "Fy", "Tz")
+    e.update(particle_errors(g, o, keys))
+    check(e, 30, twin=twin_errors(oracle_mod, d, ps, 30, o, pkeys=keys))
+    gc, gi, gf = g.ownership()
+    oc, oi, of = o.ownership()
+    assert np.array_equal(gc, oc) and np.array_equal(gi, oi)
+    assert np.array_equal(gf, of)

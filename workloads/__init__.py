@@ -167,6 +167,33 @@ def e5_held_channel(Gr, length_D=180, start_D=5, D=20.0) -> tuple[dict, list]:
     return d, [p]
 
 
+def e4_ellipse_channel(tau_f=0.6, fluid_gravity=0, length_L=30, start_L=3,
+                       theta=math.pi / 4) -> tuple[dict, list]:
+    """The isothermal sedimentation of an ellipse (Sec. 3.2): semi-axes
+    a = 0.05 cm and b = 0.025 cm in a channel of width L = 0.4 cm resolved
+    by 104 cells (dx = 1/260 cm), so a = 13 and b = 6.5 cells;
+    rho_s / rho_f = 1.1, nu = 0.01 cm^2/s, |g| = 980 cm/s^2.  tau_f fixes
+    dt through nu = (tau_f - 1/2) dx^2 / (3 dt), and |g| = 980 dt^2 / dx in
+    lattice units.  The channel is 30 L long with no-slip walls at both
+    ends (the paper's top is a no-flow wall and its bottom an outflow that
+    the particle does not reach); the ellipse starts on the centre line
+    3 L below the top with its major axis at theta = pi/4.  Isothermal: no
+    buoyancy.  fluid_gravity = 1 is situation II (the fluid carries its
+    weight, from a hydrostatic start)."""
+    L, a, b = 104, 13.0, 6.5
+    dx = 0.4 / L
+    dt = (tau_f - 0.5) / 3.0 * dx * dx / 0.01
+    g = 980.0 * dt * dt / dx
+    ny = int(length_L * L)
+    d = domain(L, ny, tau_f=tau_f, lambda_f=0.1, gravity=(0.0, -g),
+               fluid_gravity=fluid_gravity, init_T=1.0, T_ref=1.0,
+               **collision_params(1.1, a, g))
+    d = walls(d, thermal="adiabatic")
+    p = particle(L / 2.0, ny - start_L * L, a, radius_minor=b, theta=theta,
+                 rho_s=1.1, T_init=1.0)
+    return d, [p]
+
+
 def e6_cht_channel(R_lambda=1.0, R_cv=1.0, length_D=60, start_D=10,
                    D=20.0) -> tuple[dict, list]:
     """The paper's sedimentation of one cold particle with conjugate heat
