@@ -49,12 +49,17 @@ steady on the centre line (100), periodic about it (564), settling near one
 wall (1000, 2000: x* = 2.91 and 2.74, other methods 2.76-2.91 and
 2.62-2.74), steady on the centre line again (2500), and periodic about it
 with a large amplitude (4500: 1.27).  Here: 100, 564, 1000, 2000 and 2500
-give the first four regimes (x* = 2.85 and 2.85 near the wall), but at
-4500 the oscillation dies out and the large-amplitude regime appears at
-Gr = 6000 (x* swinging between 0.6 and 3.1; half-range 1.12 over the last
-40 % of the run): the held-temperature rule cools the
-fluid as a somewhat lower Gr would (its interface cells are held only in
-proportion to their covered share), and the paper does not give its rule.
+give the first four regimes (x* = 2.84 and 2.85 near the wall), but at
+4500 the oscillation dies out (half-range 0.016), a failing replay kept as
+a strict expected failure; the large-amplitude regime appears at Gr = 6000
+instead (half-range 1.12 over the last 40 % of the run).  Other readings of
+the unstated rules were run on the GPU (Gr = 1000 / 2000 / 4500 / 6000):
+every touched cell held fully gives x* = 2.78 / 2.80 and half-range 0.015 /
+1.37; the cells whose node lies inside held fully, 2.78 / 2.87 and 0.024 /
+0.99; the buoyancy applied inside the disk too (no (1 - f_s) weight), a
+large amplitude at 4500 (0.93) but x* = 1.98 / 2.05, no wall regime.  The
+reading kept (share-weighted hold, weighted force) is the closest on the
+printed wall positions.
 """
 import json
 import math
@@ -212,14 +217,13 @@ def test_dense_cavity_replay(vlb):
 
 
 E5_GATES = {
-    # Gr: (regime, printed x* or amplitude, gate)
+    # Gr: (regime, printed x* or amplitude, gate); Gr = 4500 has its own
+    # test below (a failing replay under this library's readings)
     100.0: ("centre", None, None),
     564.0: ("centre_periodic", None, None),
     1000.0: ("wall", 2.91, 0.12),
     2000.0: ("wall", 2.74, 0.15),
     2500.0: ("centre", None, None),
-    4500.0: ("reported", 1.27, None),
-    6000.0: ("large_amplitude", 1.27, None),
 }
 
 
@@ -264,8 +268,22 @@ def test_fixed_temperature_regimes(vlb):
         elif regime == "wall":
             assert r["amplitude"] < 0.1, (Gr, r)
             assert abs(off - (printed - 2.0)) < gate, (Gr, r, printed)
-        elif regime == "large_amplitude":
-            assert r["amplitude"] > 0.8, (Gr, r)
+
+
+@pytest.mark.xfail(strict=True, reason=(
+    "Table 4's large-amplitude regime at Gr = 4500 (amplitude 1.27) is not "
+    "reproduced: the oscillation dies out (half-range 0.016) and appears at "
+    "Gr = 6000 instead.  Holding every touched cell fully, or the cells "
+    "whose node lies inside, changes neither; applying the buoyancy inside "
+    "the disk too brings it back at 4500 (0.93) but loses the wall regimes "
+    "of Gr = 1000 and 2000.  The paper does not give its hold rule."))
+def test_fixed_temperature_large_amplitude_at_printed_gr(vlb):
+    """Sec. 3.3, Table 4: at Gr = 4500 the particle oscillates about the
+    centre line with the amplitude 1.27 (x* = x / D)."""
+    r = held_run(vlb, 4500.0)
+    print(f"Gr = 4500: late x* mean {r['x_late_mean']:.3f}, amplitude "
+          f"{r['amplitude']:.3f} (printed 1.27)", flush=True)
+    assert abs(r["amplitude"] - 1.27) < 0.3, r
 
 
 # --------------------------------------------------------------------------
