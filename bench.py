@@ -215,6 +215,12 @@ def run_batch(vlb, steps, warmup):
             "ms_per_step_batched": round(batch_s * 1e3 / steps, 4),
             "mlups_one_at_a_time": round(single, 1),
             "speedup": round(batched / single, 3),
+            # algorithmic bytes (every cell's populations read and written
+            # once) over the batched step time, against 8 TB/s
+            "achieved_GBs": round(cells * BYTES_PER_CELL["fp32"] * steps
+                                  / batch_s / 1e9, 1),
+            "frac_hbm": round(cells * BYTES_PER_CELL["fp32"] * steps
+                              / batch_s / 1e9 / HBM_PEAK_GBS, 4),
             "tuning": {k: (round(v, 2) if isinstance(v, float) else v)
                        for k, v in tune.items()}}
 

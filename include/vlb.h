@@ -271,11 +271,19 @@ typedef struct vlb_batch vlb_batch;
  * multiple of 8 (0: one block per task).  order 0: tiles listed domain by
  * domain; 1: tiles dealt to the 8 XCDs in contiguous bands.  use_graph:
  * replay steady-state steps from a captured two-step hipGraph.
+ * pair_min_tiles: the tiling of each domain -- a domain of at least this
+ * many tiles streams its particle-free tiles two per block (512 cells, two
+ * per lane), a smaller one one per block (256 cells); 0 pairs every
+ * domain, -1 none.  waves: the occupancy the step kernel is built for, 4
+ * waves per SIMD, or 5 for the 32- and 16-bit forms (0: 4 for FP64, 5 for
+ * the others).
  * us_per_step: the time vlb_batch_autotune measured for the choice. */
 typedef struct {
   int32_t grid_blocks;
   int32_t order;
   int32_t use_graph;
+  int32_t pair_min_tiles;
+  int32_t waves;
   double  us_per_step;
 } vlb_batch_tuning;
 
@@ -298,10 +306,14 @@ vlb_status vlb_batch_init(vlb_batch* b);
  * then be initialised again. */
 vlb_status vlb_batch_step(vlb_batch* b, int64_t nsteps);
 
-/* Time every candidate launch shape (grid_blocks 4, 8 and 16 per compute
- * unit and one block per task, both orders) over `steps` steps, keep the
- * fastest (with use_graph = 1) and initialise the batch again.  Only on a
- * freshly initialised batch (VLB_ESTATE otherwise).  chosen may be NULL. */
+/* Time every candidate tuning over `steps` steps -- grid_blocks 4, 8 and
+ * 16 per compute unit and one block per task; both orders; pair_min_tiles
+ * -1 (no pairs), the median tile count of the domains (the larger half
+ * paired) and 0 (all); waves 4 and 5 (FP64: 4) -- keep the fastest (with
+ * use_graph = 1) and initialise the batch again.  Only on a freshly
+ * initialised batch (VLB_ESTATE otherwise).  chosen may be NULL.
+ * vlb_batch_set_tuning rejects values outside the ranges above
+ * (VLB_EINVAL). */
 vlb_status vlb_batch_autotune(vlb_batch* b, int32_t steps,
                               vlb_batch_tuning* chosen);
 vlb_status vlb_batch_set_tuning(vlb_batch* b, const vlb_batch_tuning* t);

@@ -5,10 +5,11 @@
 // device memory, created, initialised and read through the single-domain
 // code.  Stepping is different: one launch of k_batch_step advances every
 // domain, its persistent blocks walking a task table that lists all
-// domains' particle-tile tasks and then all their tiles.  The launch shape
-// (number of persistent blocks) and the table order are chosen by
-// vlb_batch_autotune from measured candidates; steady-state steps are
-// replayed from a captured two-step hipGraph.
+// domains' particle-tile tasks and then all their tiles, one or two tiles
+// per task.  The launch shape (number of persistent blocks), the table
+// order, which domains stream their tiles in pairs and the kernel's
+// occupancy are chosen by vlb_batch_autotune from measured candidates;
+// steady-state steps are replayed from a captured two-step hipGraph.
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <string.h>
@@ -82,7 +83,15 @@ static std::vector<BatchTask> spread(const std::vector<BatchTask>& tiles,
   return out;
 }
 
-static std::vector<BatchTask> build_tasks(const vlb_batch* b, int order) {
+// A domain of at least pair_min_tiles tiles (>= 0) streams tiles t and
+// t + 1 (t even) in one task.
+static bool paired(const vlb_batch_tuning& t, const Params& P) {
+  return t.pair_min_tiles >= 0 && P.nblocks >= t.pair_min_tiles;
+}
+
+static std::vector<BatchTask> build_tasks(const vlb_batch* b,
+                                          const vlb_batch_tuning& tune) {
+  const int order = tune.order;
   std::vector<BatchTask> part, tiles;
   for (size_t i = 0; i < b->cases.size(); ++i) {
     const Params& P = b->cases[i]->P;
@@ -91,8 +100,12 @@ static std::vector<BatchTask> build_tasks(const vlb_batch* b, int order) {
   }
   for (size_t i = 0; i < b->cases.size(); ++i) {
     const Params& P = b->cases[i]->P;
-    for (int t = 0; t < P.nblocks; ++t)
-      tiles.push_back(make_int2((int)i, P.nfirst + t));
+    if (paired(tune, P))
+      for (int t = 0; t < P.nblocks; t += 2)
+        tiles.push_back(make_int2((int)i, kPairTask | t));
+    else
+      for (int t = 0; t < P.nblocks; ++t)
+        tiles.push_back(make_int2((int)i, P.nfirst + t));
   }
   if (order == 0) return spread(tiles, part);
   // order 1: one queue per XCD (its band of tiles and every 8th particle
@@ -115,7 +128,7 @@ static std::vector<BatchTask> build_tasks(const vlb_batch* b, int order) {
 }
 
 static vlb_status upload_tasks(vlb_batch* b) {
-  std::vector<BatchTask> t = build_tasks(b, b->tune.order);
+  std::vector<BatchTask> t = build_tasks(b, b->tune);
   if (t.size() > b->tasks_cap) {
     if (b->dtasks) (void)hipFree(b->dtasks);
     b->dtasks = nullptr;
@@ -171,10 +184,25 @@ static int grid_of(const vlb_batch* b) {
   return std::max(1, std::min(g, b->ntasks));
 }
 
+// The occupancy of the kernel variant: the tuning's, else 4 waves per
+// SIMD for FP64 (128 registers, no spill) and 5 for the narrower forms.
+static int waves_of(const vlb_batch* b) {
+  if (b->tune.waves) return b->tune.waves;
+  return b->prec == VLB_FP64 ? 4 : 5;
+}
+
 static hipError_t launch_one(vlb_batch* b, bool out) {
-  hipError_t e = launch_batch_step(b->prec, out, b->dcases, b->dtasks,
-                                   (char*)b->dcases, b->ntasks, grid_of(b),
-                                   b->parity, b->have, b->stream);
+  BatchLaunch a;
+  a.cases = b->dcases;
+  a.tasks = b->dtasks;
+  a.arena = (char*)b->dcases;
+  a.ntasks = b->ntasks;
+  a.grid = grid_of(b);
+  a.parity = b->parity;
+  a.have = b->have;
+  a.waves = waves_of(b);
+  a.pair = b->tune.pair_min_tiles >= 0;
+  hipError_t e = launch_batch_step(b->prec, out, a, b->stream);
   b->parity ^= 1;
   b->have = 1;
   return e;
@@ -279,6 +307,8 @@ vlb_status vlb_batch_create(int32_t ncases, const vlb_domain_desc* descs,
   b->tune.grid_blocks = 4 * b->cus;   // one wave of resident blocks
   b->tune.order = 1;
   b->tune.use_graph = 1;
+  b->tune.pair_min_tiles = -1;
+  b->tune.waves = 0;
   b->tune.us_per_step = 0.0;
   auto give_up = [&](vlb_status s, const std::string& m) {
     vlb_batch_destroy(b);
@@ -371,14 +401,20 @@ vlb_status vlb_batch_step(vlb_batch* b, int64_t nsteps) {
 vlb_status vlb_batch_set_tuning(vlb_batch* b, const vlb_batch_tuning* t) {
   if (!b || !t) return VLB_EINVAL;
   if (t->grid_blocks < 0 || (t->grid_blocks % 8) != 0 || t->order < 0 ||
-      t->order > 1)
+      t->order > 1 || t->pair_min_tiles < -1 ||
+      (t->waves != 0 && t->waves != 4 &&
+       (t->waves != 5 || b->prec == VLB_FP64)))
     return bfail(b, VLB_EINVAL,
                  "grid_blocks must be a multiple of 8 (0: one per task), "
-                 "order 0 or 1");
+                 "order 0 or 1, pair_min_tiles >= -1, waves 0 or 4 (or 5 "
+                 "for the 32- and 16-bit forms)");
   b->tune.grid_blocks = t->grid_blocks;
   b->tune.use_graph = t->use_graph ? 1 : 0;
-  if (t->order != b->tune.order) {
+  b->tune.waves = t->waves;
+  if (t->order != b->tune.order ||
+      t->pair_min_tiles != b->tune.pair_min_tiles) {
     b->tune.order = t->order;
+    b->tune.pair_min_tiles = t->pair_min_tiles;
     return upload_tasks(b);
   }
   if (b->graph) {
@@ -402,37 +438,48 @@ vlb_status vlb_batch_autotune(vlb_batch* b, int32_t steps,
   if (b->step != 0)
     return bfail(b, VLB_ESTATE, "autotune a freshly initialised batch");
   const int grids[] = {4 * b->cus, 8 * b->cus, 16 * b->cus, 0};
+  // pairing thresholds: none, the larger half of the domains, all
+  std::vector<int> counts;
+  for (const vlb_ctx* c : b->cases) counts.push_back(c->P.nblocks);
+  std::nth_element(counts.begin(), counts.begin() + counts.size() / 2,
+                   counts.end());
+  const int pairs[] = {-1, counts[counts.size() / 2], 0};
+  const int waves[] = {4, 5};
+  const int nwaves = b->prec == VLB_FP64 ? 1 : 2;
   hipEvent_t e0, e1;
   BHIP(b, hipEventCreate(&e0));
   BHIP(b, hipEventCreate(&e1));
   vlb_batch_tuning best = b->tune;
   double best_us = 1e300;
   vlb_status st = VLB_OK;
-  for (int order = 0; order < 2 && st == VLB_OK; ++order) {
-    for (int gi = 0; gi < 4 && st == VLB_OK; ++gi) {
-      vlb_batch_tuning t;
-      t.grid_blocks = grids[gi];
-      t.order = order;
-      t.use_graph = 0;
-      t.us_per_step = 0.0;
-      st = vlb_batch_set_tuning(b, &t);
-      if (st != VLB_OK) break;
-      hipError_t e = launch_one(b, false);            // warm-up
-      if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-      for (int k = 0; k < steps && e == hipSuccess; ++k) e = launch_one(b, false);
-      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        st = bfail(b, VLB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
-        break;
-      }
-      const double us = 1e3 * ms / steps;
-      if (us < best_us) {
-        best_us = us;
-        best = t;
-      }
+  for (int pi = 0; pi < 3 && st == VLB_OK; ++pi)
+  for (int order = 0; order < 2 && st == VLB_OK; ++order)
+  for (int wi = 0; wi < nwaves && st == VLB_OK; ++wi)
+  for (int gi = 0; gi < 4 && st == VLB_OK; ++gi) {
+    vlb_batch_tuning t;
+    t.grid_blocks = grids[gi];
+    t.order = order;
+    t.use_graph = 0;
+    t.pair_min_tiles = pairs[pi];
+    t.waves = waves[wi];
+    t.us_per_step = 0.0;
+    st = vlb_batch_set_tuning(b, &t);
+    if (st != VLB_OK) break;
+    hipError_t e = launch_one(b, false);              // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+    for (int k = 0; k < steps && e == hipSuccess; ++k) e = launch_one(b, false);
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      st = bfail(b, VLB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+      break;
+    }
+    const double us = 1e3 * ms / steps;
+    if (us < best_us) {
+      best_us = us;
+      best = t;
     }
   }
   (void)hipEventDestroy(e0);

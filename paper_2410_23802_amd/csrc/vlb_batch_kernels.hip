@@ -74,14 +74,19 @@ __device__ __forceinline__ StepBufs rebase_bufs(char* a, const StepBufs& b) {
 // One step of every domain of a batch (all in the scan form or without
 // particles).  A fixed set of persistent blocks walks the task table: block
 // b takes tasks b, b + grid, b + 2 grid, ...  The table lists every
-// domain's particle-tile tasks first, then its tiles; its order (chosen by
-// the autotuner) decides which XCD streams which tiles.  Every task is one
-// call of step_task, exactly as in k_step, so a domain's results do not
-// depend on the batch around it or on the table order.  Occupancy targets
-// as for k_step.
-template <int PREC, bool OUT>
+// domain's particle-tile tasks, then its tiles, one or two per task (two
+// adjacent tiles streamed by one block, each lane loading its cell in both
+// before it computes either, as pair_task describes); the autotuner chooses
+// which domains stream in pairs, the table order (which XCD streams which
+// tiles) and the occupancy WAVES (waves per SIMD the registers are held to).
+// PAIR: the table holds pair tasks -- a kernel of its own, since the pair
+// path's two cells per lane raise the register peak of the whole kernel
+// (FP64: from 128 registers without spills to 54 spilled).  Every tile is
+// updated by the same update_cell arithmetic, alone or in a pair, so a
+// domain's results do not depend on the batch around it or on the tuning.
+template <int PREC, bool OUT, int WAVES, bool PAIR>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 5))) void k_batch_step(
+__attribute__((amdgpu_waves_per_eu(WAVES))) void k_batch_step(
     const BatchCase* __restrict__ cases, const BatchTask* __restrict__ tasks,
     char* __restrict__ arena, int ntasks, int parity, int have) {
   typedef typename Prec<PREC>::C C;
@@ -91,18 +96,23 @@ __attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 5))) void k_batch_step
     if (tk.x >= 0) {
       const BatchCase& bc = cases[tk.x];
       const StepBufs B = rebase_bufs(arena, bc.B[parity]);
-      int tile;
-      bool ptile;
-      if (tk.y < bc.P.nfirst) {
-        tile = scan_task_tile(bc.P, B.cur, B.pc, tk.y);
-        ptile = true;
+      if (PAIR && (tk.y & kPairTask)) {
+        const int tA = tk.y & ~kPairTask;
+        pair_task<PREC, OUT, true>(bc.P, hot_of<C>(bc), B, tA, tA + 1);
       } else {
-        tile = tk.y - bc.P.nfirst;
-        ptile = false;
+        int tile;
+        bool ptile;
+        if (tk.y < bc.P.nfirst) {
+          tile = scan_task_tile(bc.P, B.cur, B.pc, tk.y);
+          ptile = true;
+        } else {
+          tile = tk.y - bc.P.nfirst;
+          ptile = false;
+        }
+        if (tile >= 0)
+          step_task<PREC, OUT, true>(bc.P, hot_of<C>(bc), B, have, tile,
+                                     ptile, sh);
       }
-      if (tile >= 0)
-        step_task<PREC, OUT, true>(bc.P, hot_of<C>(bc), B, have, tile, ptile,
-                                   sh);
     }
     __syncthreads();   // the LDS of this task is free for the next
   }
@@ -119,28 +129,40 @@ __global__ void k_gather_flags(const BatchCase* __restrict__ cases,
 // -------------------------------------------------------------------------
 // Launchers
 
-template <int PREC>
-static hipError_t batch_p(bool out, const BatchCase* cases,
-                          const BatchTask* tasks, char* arena, int ntasks,
-                          int grid, int parity, int have, hipStream_t s) {
+template <int PREC, int WAVES, bool PAIR>
+static hipError_t batch_w(bool out, const BatchLaunch& a, hipStream_t s) {
   if (out)
-    hipLaunchKernelGGL((k_batch_step<PREC, true>), dim3(grid), dim3(kBlock),
-                       0, s, cases, tasks, arena, ntasks, parity, have);
+    hipLaunchKernelGGL((k_batch_step<PREC, true, WAVES, PAIR>), dim3(a.grid),
+                       dim3(kBlock), 0, s, a.cases, a.tasks, a.arena,
+                       a.ntasks, a.parity, a.have);
   else
-    hipLaunchKernelGGL((k_batch_step<PREC, false>), dim3(grid), dim3(kBlock),
-                       0, s, cases, tasks, arena, ntasks, parity, have);
+    hipLaunchKernelGGL((k_batch_step<PREC, false, WAVES, PAIR>), dim3(a.grid),
+                       dim3(kBlock), 0, s, a.cases, a.tasks, a.arena,
+                       a.ntasks, a.parity, a.have);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_step(int prec, bool out, const BatchCase* cases,
-                             const BatchTask* tasks, char* arena, int ntasks,
-                             int grid, int parity, int have, hipStream_t s) {
-  if (ntasks <= 0 || grid <= 0) return hipSuccess;
+// FP64 only at 4 waves (128 registers): at 5 it spills heavily.
+template <int PREC>
+static hipError_t batch_p(bool out, const BatchLaunch& a, hipStream_t s) {
+  if (a.waves == 4)
+    return a.pair ? batch_w<PREC, 4, true>(out, a, s)
+                  : batch_w<PREC, 4, false>(out, a, s);
+  if constexpr (PREC != VLB_FP64)
+    if (a.waves == 5)
+      return a.pair ? batch_w<PREC, 5, true>(out, a, s)
+                    : batch_w<PREC, 5, false>(out, a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_step(int prec, bool out, const BatchLaunch& a,
+                             hipStream_t s) {
+  if (a.ntasks <= 0 || a.grid <= 0) return hipSuccess;
   switch (prec) {
-    case VLB_FP64: return batch_p<VLB_FP64>(out, cases, tasks, arena, ntasks, grid, parity, have, s);
-    case VLB_FP32: return batch_p<VLB_FP32>(out, cases, tasks, arena, ntasks, grid, parity, have, s);
-    case VLB_FP16_SHIFT: return batch_p<VLB_FP16_SHIFT>(out, cases, tasks, arena, ntasks, grid, parity, have, s);
-    case VLB_BF16_SHIFT: return batch_p<VLB_BF16_SHIFT>(out, cases, tasks, arena, ntasks, grid, parity, have, s);
+    case VLB_FP64: return batch_p<VLB_FP64>(out, a, s);
+    case VLB_FP32: return batch_p<VLB_FP32>(out, a, s);
+    case VLB_FP16_SHIFT: return batch_p<VLB_FP16_SHIFT>(out, a, s);
+    case VLB_BF16_SHIFT: return batch_p<VLB_BF16_SHIFT>(out, a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -184,9 +184,11 @@ struct BatchCase {
 };
 
 // A task of the batch step kernel: (domain, k); k < P.nfirst is the k-th
-// particle-tile task of the domain, else tile k - P.nfirst.  Domain -1: no
-// work (padding).
+// particle-tile task of the domain, k | kPairTask the tiles k and k + 1
+// streamed by one block (two cells per lane), else tile k - P.nfirst.
+// Domain -1: no work (padding).
 typedef int2 BatchTask;
+constexpr int kPairTask = 1 << 30;
 
 // Launchers (defined in vlb_kernels.hip).  All run on `s`.
 hipError_t launch_particles(const Params& P, PState cur, PState next,
@@ -196,10 +198,18 @@ hipError_t launch_particles(const Params& P, PState cur, PState next,
 // k_step: the lattice step over every cell (events, if given, bracket it)
 hipError_t launch_step(int prec, const StepLaunch& a, hipStream_t s);
 // k_batch_step: one step of every domain of a batch; `grid` persistent
-// blocks walk the task table in steps of `grid`.
-hipError_t launch_batch_step(int prec, bool out, const BatchCase* cases,
-                             const BatchTask* tasks, char* arena, int ntasks,
-                             int grid, int parity, int have, hipStream_t s);
+// blocks walk the task table in steps of `grid`.  The variant: `waves`, the
+// occupancy (waves per SIMD: 4, or 5 for the 32- and 16-bit forms), and
+// `pair`, whether the table holds pair tasks.
+struct BatchLaunch {
+  const BatchCase* cases;
+  const BatchTask* tasks;
+  char* arena;
+  int ntasks, grid, parity, have, waves;
+  bool pair;
+};
+hipError_t launch_batch_step(int prec, bool out, const BatchLaunch& a,
+                             hipStream_t s);
 // out[i] = the error flags of domain i
 hipError_t launch_gather_flags(const BatchCase* cases, char* arena, int n,
                                int* out, hipStream_t s);

@@ -78,7 +78,9 @@ class vlb_particle_desc(ctypes.Structure):
 
 class vlb_batch_tuning(ctypes.Structure):
     _fields_ = [("grid_blocks", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("us_per_step", ctypes.c_double)]
+                ("use_graph", ctypes.c_int32),
+                ("pair_min_tiles", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("us_per_step", ctypes.c_double)]
 
 
 class vlb_particle_state(ctypes.Structure):
@@ -499,9 +501,10 @@ class Batch:
                 "vlb_batch_get_tuning", self.h)
         return {k: getattr(t, k) for k, _ in vlb_batch_tuning._fields_}
 
-    def set_tuning(self, grid_blocks: int, order: int, use_graph: bool = True):
+    def set_tuning(self, grid_blocks: int, order: int, use_graph: bool = True,
+                   pair_min_tiles: int = -1, waves: int = 0):
         t = vlb_batch_tuning(int(grid_blocks), int(order), int(bool(use_graph)),
-                             0.0)
+                             int(pair_min_tiles), int(waves), 0.0)
         _bcheck(lib().vlb_batch_set_tuning(self.h, ctypes.byref(t)),
                 "vlb_batch_set_tuning", self.h)
         return self

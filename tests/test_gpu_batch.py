@@ -137,30 +137,67 @@ def test_batch_matches_oracle_and_single_path_fp64(vlb, oracle_mod):
     b.close()
 
 
-def test_batch_results_independent_of_tuning(vlb):
-    """Launch shape, task order and graph replay change nothing: every
-    task is the same tile computation and partial sums are reduced in slot
-    order."""
-    cases = ragged_cases()
-    n = 9     # first step single, then graph pairs, then the last single
-    ref = None
-    for grid, order, graph in ((0, 0, False), (1024, 1, True), (16, 0, True),
-                               (8, 1, False)):
-        say(f"tuning grid={grid} order={order} graph={graph}")
-        b = vlb.Batch(cases, "fp32").init()
-        b.set_tuning(grid, order, graph)
+def run_tunings(vlb, cases, prec, tunings, n):
+    """Fields and particles of every domain after n steps under each
+    tuning (grid, order, graph, pair_min_tiles, waves)."""
+    out = []
+    for t in tunings:
+        say(f"{prec} tuning grid={t[0]} order={t[1]} graph={t[2]} "
+            f"pair_min_tiles={t[3]} waves={t[4]}")
+        b = vlb.Batch(cases, prec).init()
+        b.set_tuning(*t)
+        got = b.tuning()
+        assert (got["pair_min_tiles"], got["waves"]) == (t[3], t[4])
         b.step(n)
-        got = [batch_state(b, i, ps) for i, (d, ps) in enumerate(cases)]
+        out.append([batch_state(b, i, ps) for i, (d, ps) in enumerate(cases)])
         b.close()
-        if ref is None:
-            ref = got
-            continue
+    return out
+
+
+def assert_same(runs, tunings):
+    ref = runs[0]
+    for got, t in zip(runs[1:], tunings[1:]):
         for i, ((f, p), (rf, rp)) in enumerate(zip(got, ref)):
             for k in FIELDS:
-                assert np.array_equal(f[k], rf[k]), (grid, order, graph, i, k)
+                assert np.array_equal(f[k], rf[k]), (t, i, k)
             if p is not None:
                 for k in ("x", "y", "ux", "uy", "omega"):
-                    assert np.array_equal(p[k], rp[k]), (i, k)
+                    assert np.array_equal(p[k], rp[k]), (t, i, k)
+
+
+def test_batch_results_independent_of_tuning(vlb):
+    """Launch shape, task order, per-domain tiling (one or two tiles per
+    block), occupancy and graph replay change nothing: every tile is the
+    same update_cell computation and partial sums are reduced in slot
+    order.  The tile counts are 10, 16, 24, 32, 33 (odd: its last pair
+    has one tile) and 58; pair_min_tiles 32 pairs the larger three."""
+    cases = ragged_cases()
+    n = 9     # first step single, then graph pairs, then the last single
+    tunings = ((0, 0, False, -1, 0), (1024, 1, True, -1, 4),
+               (16, 0, True, -1, 5), (8, 1, False, 0, 4),
+               (1024, 1, True, 0, 5), (2048, 0, True, 32, 5),
+               (0, 1, True, 33, 4))
+    assert_same(run_tunings(vlb, cases, "fp32", tunings, n), tunings)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16s"])
+def test_batch_tilings_agree_in_other_forms(vlb, prec):
+    """Paired and single tiles give the same bits in FP64 (whose paired
+    kernel spills) and in a 16-bit form."""
+    cases = ragged_cases()
+    tunings = ((1024, 1, True, -1, 0), (1024, 1, True, 0, 4),
+               (0, 0, True, 32, 0))
+    assert_same(run_tunings(vlb, cases, prec, tunings, 7), tunings)
+
+
+def test_batch_tuning_rejects_bad_values(vlb):
+    cases = ragged_cases()[:2]
+    b = vlb.Batch(cases, "fp64").init()
+    for t in ((12, 0, True, -1, 0), (0, 2, True, -1, 0), (0, 0, True, -2, 0),
+              (0, 0, True, -1, 3), (0, 0, True, -1, 5)):   # FP64: 4 waves
+        with pytest.raises(vlb.VlbError):
+            b.set_tuning(*t)
+    b.close()
 
 
 def test_batch_graph_replays_with_eager_work_between(vlb):
@@ -194,6 +231,7 @@ def test_c5_batch_autotuned_sample_matches_oracle(vlb, oracle_mod):
     t = b.autotune(3)
     say(f"autotune: {t}")
     assert t["grid_blocks"] % 8 == 0 and t["order"] in (0, 1)
+    assert t["waves"] in (4, 5) and t["pair_min_tiles"] >= -1
     n = 10
     b.step(n)
     rng = np.random.default_rng(7)
