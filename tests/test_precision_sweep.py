@@ -1,6 +1,6 @@
 """Precision sweep: every storage form of the GPU step against the FP64
 oracle after a long run (20000 steps of the channel and of the dense
-cavity).
+cavity, and the channel's whole run of 100000 steps).
 
 The reference (tests/golden/sweep_<workload>_<steps>.npz) was written by
 tests/golden/make_sweep_reference.py, which runs only the oracle: u and T on
@@ -27,8 +27,11 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 FORMS = ("fp64", "fp32", "fp16s", "bf16s")
-REFS = {"c2_channel": "sweep_c2_channel_20000.npz",
-        "c3_dense": "sweep_c3_dense_20000.npz"}
+# case id -> (workload, reference file)
+REFS = {"c2_channel": ("c2_channel", "sweep_c2_channel_20000.npz"),
+        "c3_dense": ("c3_dense", "sweep_c3_dense_20000.npz"),
+        # the channel's whole run (the disk falls about 40 diameters)
+        "c2_channel_full": ("c2_channel", "sweep_c2_channel_100000.npz")}
 
 # gates: (rel-L2 u, rel-L2 T, trajectory error / D).  FP64 and FP32 are
 # held to parity bars; the 16-bit forms only to staying physical (finite,
@@ -40,6 +43,15 @@ REFS = {"c2_channel": "sweep_c2_channel_20000.npz",
 # channel.
 GATES = {"fp64": (1e-8, 1e-10, 1e-8), "fp32": (5e-3, 1e-4, 1e-3),
          "fp16s": (2.0, 0.2, 5.0), "bf16s": (2.0, 0.2, 5.0)}
+# Over the channel's whole run the FP32 velocity field is gated by what the
+# trajectory bar allows: it is the field of a disk displaced by the FP32
+# path's offset (3.9e-4 D = 0.008 cells after 100000 steps gives rel-L2 u
+# 7.1e-3, the steep near-disk gradients dominating), so a disk displaced by
+# the 1e-3 D bar gives about 1.8e-2.  The 16-bit forms drift by up to 8 D
+# over the run (BF16) and are held to staying finite and in the channel.
+CASE_GATES = {"c2_channel_full": {"fp32": (2e-2, 1e-4, 1e-3),
+                                  "fp16s": (3.0, 0.2, 20.0),
+                                  "bf16s": (3.0, 0.2, 20.0)}}
 
 
 @pytest.fixture(scope="module")
@@ -89,14 +101,15 @@ def run_form(vlb, name, prec, ref):
 
 @pytest.mark.parametrize("name", sorted(REFS))
 def test_precision_sweep(vlb, name):
-    path = os.path.join(HERE, "golden", REFS[name])
+    workload, fname = REFS[name]
+    path = os.path.join(HERE, "golden", fname)
     if not os.path.exists(path):
-        pytest.skip(f"oracle reference {REFS[name]} not generated")
+        pytest.skip(f"oracle reference {fname} not generated")
     ref = dict(np.load(path))
     rows = []
     for prec in FORMS:
         print(f"sweep {name} {prec}: {int(ref['steps'])} steps", flush=True)
-        r = run_form(vlb, name, prec, ref)
+        r = run_form(vlb, workload, prec, ref)
         rows.append(r)
         print("  " + json.dumps(r), flush=True)
     out = os.environ.get("VLB_SWEEP_OUT")
@@ -106,7 +119,7 @@ def test_precision_sweep(vlb, name):
             json.dump({"workload": name, "steps": int(ref["steps"]),
                        "rows": rows}, fh, indent=1)
     for r in rows:
-        gu, gT, gx = GATES[r["form"]]
+        gu, gT, gx = CASE_GATES.get(name, {}).get(r["form"], GATES[r["form"]])
         assert r["finite"], r
         assert r["rel_l2_u"] <= gu, r
         assert r["rel_l2_T"] <= gT, r
