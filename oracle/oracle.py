@@ -19,6 +19,10 @@ LIB = os.path.join(HERE, "liboracle_vlb.so")
 # implementation that differs from the first only in rounding.  The gap
 # between the two measures how closely FP64 can reproduce a result at all.
 LIB_FMA = os.path.join(HERE, "liboracle_vlb_fma.so")
+# The three-dimensional oracle (vlb3_oracle.c; it uses the disk-cell area of
+# vlb_oracle.c for the sections of a sphere).
+SRC3 = os.path.join(HERE, "vlb3_oracle.c")
+LIB3 = os.path.join(HERE, "liboracle_vlb3.so")
 
 FACE_FLOW = {"periodic": 0, "wall": 1}
 FACE_THERMAL = {"adiabatic": 0, "dirichlet": 1}
@@ -35,6 +39,12 @@ def build(verbose: bool = False) -> str:
             print(" ".join(cmd))
         subprocess.run(cmd, check=True)
         os.replace(out + ".tmp", out)
+    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
+           "-shared", "-Wall", "-o", LIB3 + ".tmp", SRC3, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB3 + ".tmp", LIB3)
     return LIB
 
 

@@ -24,3 +24,12 @@ def oracle_mod():
     if not os.path.exists(O.LIB):
         O.build()
     return O
+
+
+@pytest.fixture(scope="session")
+def oracle3_mod():
+    from oracle import oracle as O
+    from oracle import oracle3 as O3
+    if not os.path.exists(O.LIB3):
+        O.build()
+    return O3

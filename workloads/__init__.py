@@ -334,3 +334,62 @@ WORKLOADS = {
     "c2_channel": c2_channel,
     "c3_dense": c3_dense,
 }
+
+
+# --------------------------------------------------------------------------
+# Three dimensions (D3Q19 flow, D3Q7 energy, spheres)
+
+ZLO, ZHI = 4, 5
+
+
+def domain3(nx: int, ny: int, nz: int, **kw) -> dict:
+    """A three-dimensional descriptor with defaults: periodic box,
+    tau_f = 0.8, unit fluid properties, no forces, fluid at rest at
+    T = 1."""
+    d = dict(
+        nx=int(nx), ny=int(ny), nz=int(nz),
+        face_flow=["periodic"] * 6,
+        u_wall=[(0.0, 0.0, 0.0)] * 6,
+        face_thermal=["adiabatic"] * 6,
+        T_wall=[0.0] * 6,
+        tau_f=0.8, rho_f=1.0, cv_f=1.0, lambda_f=0.1,
+        R_lambda=1.0, R_cv=1.0,
+        body_force=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), beta=0.0,
+        T_ref=1.0, sigma_rule=0,
+        coll_range=0.0, coll_stiff_pp=0.0, coll_stiff_pw=0.0,
+        init_rho=1.0, init_u=(0.0, 0.0, 0.0), init_T=1.0,
+        kmax=4,
+    )
+    for k, v in kw.items():
+        if k not in d:
+            raise KeyError(f"unknown descriptor key {k!r}")
+        d[k] = v
+    d["face_flow"] = list(d["face_flow"])
+    d["u_wall"] = [tuple(map(float, u)) for u in d["u_wall"]]
+    d["face_thermal"] = list(d["face_thermal"])
+    d["T_wall"] = [float(t) for t in d["T_wall"]]
+    return d
+
+
+def walls3(d: dict, which=(XLO, XHI, YLO, YHI, ZLO, ZHI),
+           thermal="adiabatic", T_wall=None) -> dict:
+    """Turn the listed faces of a three-dimensional descriptor into no-slip
+    walls with the given thermal condition."""
+    d = dict(d)
+    ff, ft, tw = list(d["face_flow"]), list(d["face_thermal"]), list(d["T_wall"])
+    for k in which:
+        ff[k] = "wall"
+        ft[k] = thermal
+        if T_wall is not None:
+            tw[k] = float(T_wall if np.isscalar(T_wall) else T_wall[k])
+    d["face_flow"], d["face_thermal"], d["T_wall"] = ff, ft, tw
+    return d
+
+
+def sphere(x, y, z, radius, rho_s=1.0, T_init=0.0, u=(0.0, 0.0, 0.0),
+           omega=(0.0, 0.0, 0.0), fixed=False) -> dict:
+    return dict(x=float(x), y=float(y), z=float(z), ux=float(u[0]),
+                uy=float(u[1]), uz=float(u[2]), ox=float(omega[0]),
+                oy=float(omega[1]), oz=float(omega[2]), radius=float(radius),
+                rho_s=float(rho_s), T_init=float(T_init),
+                fixed=int(bool(fixed)))
