@@ -225,6 +225,55 @@ def run_batch(vlb, steps, warmup):
                        for k, v in tune.items()}}
 
 
+# Algorithmic bytes per cell and step in three dimensions (FP64): the 19
+# flow and 7 energy populations read once and written once, and the
+# [df_s/dt] carrier read and written once.
+BYTES_PER_CELL3 = 2 * (19 + 7) * 8 + 2 * 8
+WORKLOADS3 = {
+    "c6_sphere_channel3": "80 x 80 x 320 channel, one cold sphere of D = 16 "
+                          "settling (D3Q19 flow, D3Q7 energy, FP64)",
+    "c7_spheres_box3": "96^3 box, 64 cold spheres of D = 12 settling "
+                       "(D3Q19 flow, D3Q7 energy, FP64)",
+}
+
+
+def run_3d(vlb, steps, warmup):
+    """The three-dimensional path on both workloads: whole-step MLUPS and
+    the lattice step kernel's event-timed duration against its algorithmic
+    bytes."""
+    import torch
+    import workloads as W
+    out = {}
+    for name, what in WORKLOADS3.items():
+        d, ps = getattr(W, name)()
+        cells = d["nx"] * d["ny"] * d["nz"]
+        dom = vlb.Domain3(d, ps).init()
+        dom.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dom.step(steps)
+        wall = time.perf_counter() - t0
+        dom.timing(True)
+        dom.timing_read()
+        dom.step(steps)
+        ms, n = dom.timing_read()
+        dom.timing(False)
+        dom.close()
+        k_ms = ms / max(n, 1)
+        gbs = BYTES_PER_CELL3 * cells / (k_ms * 1e-3) / 1e9
+        out[name] = {"workload": what, "cells": cells, "spheres": len(ps),
+                     "mlups": round(cells * steps / wall / 1e6, 1),
+                     "ms_per_step": round(wall * 1e3 / steps, 4),
+                     "k3_step_us": round(k_ms * 1e3, 2),
+                     "achieved_GBs": round(gbs, 1),
+                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                     "bytes_per_cell": BYTES_PER_CELL3}
+        print(f"# 3-D {name}: {out[name]['mlups']} MLUPS, k3_step "
+              f"{k_ms * 1e3:.1f} us -> {gbs:.0f} GB/s", file=sys.stderr,
+              flush=True)
+    return out
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -314,6 +363,8 @@ def main():
                     help="skip the 200 x 4000 channel measurement")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 16 M-cell channel measurement")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="skip the three-dimensional measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -398,6 +449,8 @@ def main():
                          **forms_block(r3, precs)}
     if not args.no_batch:
         line["batch"] = run_batch(vlb, min(args.steps, 100), 4)
+    if not args.no_3d:
+        line["three_d"] = run_3d(vlb, min(args.steps, 100), 4)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(d, ps, workload)
     print(json.dumps(line), flush=True)

@@ -22,6 +22,8 @@ SOURCES = {
     "vlb_batch_kernels.hip": ["-mllvm", "-disable-machine-licm"],
     "vlb_api.hip": [],
     "vlb_batch.hip": [],
+    "vlb3_kernels.hip": [],
+    "vlb3_api.hip": [],
 }
 
 
@@ -31,7 +33,8 @@ def source_hash() -> str:
     compile flags.  The library carries it (vlb_build_hash), and the binding
     refuses a library whose hash differs from the sources beside it."""
     h = hashlib.sha256()
-    files = sorted(os.listdir(CSRC)) + ["../../include/vlb.h"]
+    files = sorted(os.listdir(CSRC)) + ["../../include/vlb.h",
+                                        "../../include/vlb3.h"]
     for name in files:
         path = os.path.normpath(os.path.join(CSRC, name))
         with open(path, "rb") as fh:

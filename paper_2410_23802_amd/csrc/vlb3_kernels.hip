@@ -1,0 +1,1076 @@
+// vlb3_kernels.hip -- gfx950 kernels of the three-dimensional step: the
+// sphere pass (momentum-exchange sums, Newton-Euler update), the lattice
+// step (geometry, D3Q19 flow, D3Q7 energy, per-tile partial sums), the
+// initial state and the per-sphere thermal outputs.
+//
+// Layout: every population is a plane of N doubles (structure of arrays,
+// f[q][k][j][i]), pulled by one thread per cell; a tile is 256 consecutive
+// cells.  The spheres (at most 64, one per lane) are tested against each
+// tile's bounding box by every wave, which keeps the candidates of a tile
+// as a wave-uniform bit mask; the per-(sphere, tile) sums are reduced over
+// the block in a fixed order and summed by the sphere pass in tile order.
+#include <utility>
+
+#include "vlb3_internal.h"
+#include "vlb_device.h"   // covered_share: exact disk-cell area
+
+namespace vlb3 {
+
+// ---------------------------------------------------------------------------
+// Lattices
+
+__host__ __device__ constexpr int ex(int q) {
+  constexpr int t[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1,
+                         1, -1, 1, -1, 0, 0, 0, 0};
+  return t[q];
+}
+__host__ __device__ constexpr int ey(int q) {
+  constexpr int t[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1,
+                         0, 0, 0, 0, 1, -1, 1, -1};
+  return t[q];
+}
+__host__ __device__ constexpr int ez(int q) {
+  constexpr int t[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0,
+                         1, -1, -1, 1, 1, -1, -1, 1};
+  return t[q];
+}
+// opposite directions come in consecutive pairs (1, 2), (3, 4), ...
+__host__ __device__ constexpr int opp(int q) {
+  return q == 0 ? 0 : (q & 1) ? q + 1 : q - 1;
+}
+__host__ __device__ constexpr double wq(int q) {
+  return q == 0 ? 1.0 / 3.0 : q < 7 ? 1.0 / 18.0 : 1.0 / 36.0;
+}
+// energy lattice (D3Q7): w_0 = 1/4, w_i = 1/8, c_s^2 = 1/4
+constexpr double kW0G = 0.25, kW1G = 0.125, kCs2G = 0.25;
+
+// The orthogonal D3Q19 moment basis: row k evaluated at velocity q.
+__host__ __device__ constexpr double mrow(int k, int q) {
+  const double x = ex(q), y = ey(q), z = ez(q), c2 = x * x + y * y + z * z;
+  switch (k) {
+    case 0: return 1.0;
+    case 1: return 19.0 * c2 - 30.0;
+    case 2: return (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+    case 3: return x;
+    case 4: return (5.0 * c2 - 9.0) * x;
+    case 5: return y;
+    case 6: return (5.0 * c2 - 9.0) * y;
+    case 7: return z;
+    case 8: return (5.0 * c2 - 9.0) * z;
+    case 9: return 3.0 * x * x - c2;
+    case 10: return (3.0 * c2 - 5.0) * (3.0 * x * x - c2);
+    case 11: return y * y - z * z;
+    case 12: return (3.0 * c2 - 5.0) * (y * y - z * z);
+    case 13: return x * y;
+    case 14: return y * z;
+    case 15: return x * z;
+    case 16: return (y * y - z * z) * x;
+    case 17: return (z * z - x * x) * y;
+    default: return (x * x - y * y) * z;
+  }
+}
+__host__ __device__ constexpr double mnorm(int k) {
+  double s = 0.0;
+  for (int q = 0; q < kQ; ++q) s += mrow(k, q) * mrow(k, q);
+  return s;
+}
+
+// The transforms with every entry a compile-time constant: row K of M
+// dotted with a (zero entries skipped), and column Q of M^T dotted with b.
+template <int K, int Q>
+struct Basis {
+  static constexpr double v = mrow(K, Q);
+};
+
+template <int K, int Q = 0>
+__device__ __forceinline__ double row_dot(const double (&a)[kQ]) {
+  if constexpr (Q == kQ) {
+    return 0.0;
+  } else if constexpr (Basis<K, Q>::v == 0.0) {
+    return row_dot<K, Q + 1>(a);
+  } else {
+    return Basis<K, Q>::v * a[Q] + row_dot<K, Q + 1>(a);
+  }
+}
+
+template <int Q, int K = 0>
+__device__ __forceinline__ double col_dot(const double (&b)[kQ]) {
+  if constexpr (K == kQ) {
+    return 0.0;
+  } else if constexpr (Basis<K, Q>::v == 0.0) {
+    return col_dot<Q, K + 1>(b);
+  } else {
+    return Basis<K, Q>::v * b[K] + col_dot<Q, K + 1>(b);
+  }
+}
+
+// Relaxation rate of moment K: the conserved moments (rho, j) 1; the
+// energy-like even moments (e, epsilon, pi_xx, pi_ww) 1.25; the shear
+// moments s_nu; the odd moments (q, m) s_q.
+template <int K>
+__device__ __forceinline__ double rate(double snu, double sq) {
+  if constexpr (K == 0 || K == 3 || K == 5 || K == 7) return 1.0;
+  else if constexpr (K == 4 || K == 6 || K == 8 || K >= 16) return sq;
+  else if constexpr (K == 9 || K == 11 || (K >= 13 && K <= 15)) return snu;
+  else return 1.25;
+}
+
+// dm_K = -s_K (M a)_K / |row K|^2, so that M^-1 diag(-s) M a = M^T dm
+template <size_t... K>
+__device__ __forceinline__ void relax_moments(const double (&a)[kQ],
+                                              double (&dm)[kQ], double snu,
+                                              double sq,
+                                              std::index_sequence<K...>) {
+  ((dm[K] = -rate<(int)K>(snu, sq) * row_dot<(int)K>(a) *
+            (1.0 / mnorm((int)K))),
+   ...);
+}
+
+// f'_Q = (base of Q) + (M^T dm)_Q, stored as each is formed (no array of
+// 19 results held)
+template <class Base, size_t... Q>
+__device__ __forceinline__ void back_transform_store(
+    const double (&dm)[kQ], Base base, double* __restrict__ out, size_t N,
+    size_t c, std::index_sequence<Q...>) {
+  ((out[Q * N + c] = base((int)Q) + col_dot<(int)Q>(dm)), ...);
+}
+
+// ---------------------------------------------------------------------------
+// Geometry (integer decisions without fused operations, as the oracle's)
+
+__device__ __forceinline__ double near_copy(double Xp, double node, double L,
+                                            int per) {
+  if (!per) return Xp;
+  if (node - Xp > 0.5 * L) return Xp + L;
+  if (Xp - node > 0.5 * L) return Xp - L;
+  return Xp;
+}
+
+// the closed cell meets the open ball
+__device__ __noinline__ bool in_band(double X, double Y, double Z, double R,
+                                     int i, int j, int k) {
+#pragma clang fp contract(off)
+  const double P[3] = {X, Y, Z};
+  const int lo[3] = {i, j, k};
+  double s = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    double d = 0.0;
+    const double e = (double)lo[a] - P[a], f = P[a] - (double)(lo[a] + 1);
+    if (e > d) d = e;
+    if (f > d) d = f;
+    s += d * d;
+  }
+  return s < R * R;
+}
+
+// the whole cell lies in the closed ball
+__device__ __noinline__ bool wholly_inside(double X, double Y, double Z,
+                                           double R, int i, int j, int k) {
+#pragma clang fp contract(off)
+  const double P[3] = {X, Y, Z};
+  const int lo[3] = {i, j, k};
+  double s = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double e = P[a] - (double)lo[a], f = (double)(lo[a] + 1) - P[a];
+    const double d = e > f ? e : f;
+    s += d * d;
+  }
+  return s <= R * R;
+}
+
+// Gauss-Legendre rule on [0, 1] (host-computed)
+constexpr int kGL = 16;
+__constant__ double gl_x[kGL], gl_w[kGL];
+
+// Volume of the sphere (centre X, Y, Z, radius R) inside cell (i, j, k):
+// the exact cross-sectional area (a disk of radius sqrt(R^2 - z^2) in the
+// cell's square) integrated over z.  The area is analytic in z except
+// where the section's circle passes a line or a corner of the square or
+// shrinks to a point (z* = +-sqrt(R^2 - d^2), +-R), where it has
+// half-integer powers.  [k, k+1] is split at the z* inside it; on a piece
+// the substitution z - z* ~ t^2 at an end that is such a point makes the
+// integrand smooth in t; a z* just outside a piece (closer than half its
+// length) is met by geometric grading of the sub-intervals towards it, so
+// that each is at least its own length away; 16-point Gauss-Legendre on
+// every sub-interval.  Deterministic: about 140 area evaluations per cell,
+// 3e-15 from the exact volume in tests.
+__device__ __forceinline__ double section_area(double X, double Y, double R,
+                                               int i, int j, double z) {
+  const double r2 = (R - z) * (R + z);
+  return r2 > 0.0 ? vlb::covered_share(X, Y, sqrt(r2), i, j) : 0.0;
+}
+
+// one Gauss-Legendre sub-interval [p, q] (nodes g0, g0 + gs, ... of the
+// rule); sp / sq: p / q is a singular end
+__device__ __forceinline__ double gl_piece(double X, double Y, double R, int i,
+                                           int j, double p, double q, bool sp,
+                                           bool sq, int g0, int gs) {
+  const double L = q - p;
+  double sum = 0.0;
+  for (int g = g0; g < kGL; g += gs) {
+    const double t = gl_x[g];
+    double z, dz;
+    if (sp && sq) {
+      z = p + L * (t * t * (3.0 - 2.0 * t));
+      dz = 6.0 * t * (1.0 - t) * L;
+    } else if (sp) {
+      z = p + L * t * t;
+      dz = 2.0 * t * L;
+    } else if (sq) {
+      const double s = 1.0 - t;
+      z = q - L * s * s;
+      dz = 2.0 * s * L;
+    } else {
+      z = p + L * t;
+      dz = L;
+    }
+    sum += gl_w[g] * section_area(X, Y, R, i, j, z) * dz;
+  }
+  return sum;
+}
+
+// The nodes g0, g0 + gs, ... of every sub-interval's rule (all of them for
+// gs = 1; a group of gs lanes splits them and adds its parts).
+__device__ __forceinline__ double volume_nodes(double X, double Y, double Z,
+                                               double R, int i, int j, int k,
+                                               int g0, int gs) {
+  constexpr double kNone = 1e300;
+  const double a0 = (double)i - X, a1 = a0 + 1.0;
+  const double b0 = (double)j - Y, b1 = b0 + 1.0;
+  const double lo = fmax((double)k - Z, -R), hi = fmin((double)(k + 1) - Z, R);
+  if (!(lo < hi)) return 0.0;
+  // the points where the area is not analytic (absent ones: kNone); the
+  // arrays are fixed-size and fully unrolled, so they stay in registers
+  const double d2[8] = {a0 * a0, a1 * a1, b0 * b0, b1 * b1,
+                        a0 * a0 + b0 * b0, a0 * a0 + b1 * b1,
+                        a1 * a1 + b0 * b0, a1 * a1 + b1 * b1};
+  double zs[18];
+  zs[0] = R;
+  zs[1] = -R;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const bool in = d2[m] < R * R;
+    const double zb = in ? sqrt(R * R - d2[m]) : kNone;
+    zs[2 + 2 * m] = zb;
+    zs[3 + 2 * m] = in ? -zb : kNone;
+  }
+  // breakpoints: lo, hi and the z* between them, sorted by a fixed
+  // compare-exchange network (absent ones sort to the end)
+  double bp[20];
+  bp[0] = lo;
+  bp[1] = hi;
+#pragma unroll
+  for (int m = 0; m < 18; ++m)
+    bp[2 + m] = zs[m] > lo && zs[m] < hi ? zs[m] : kNone;
+#pragma unroll
+  for (int a = 0; a < 19; ++a)
+#pragma unroll
+    for (int b = 0; b < 19 - a; ++b) {
+      const double x = bp[b], y = bp[b + 1];
+      bp[b] = fmin(x, y);
+      bp[b + 1] = fmax(x, y);
+    }
+  double V = 0.0;
+  for (int m = 0; m < 19; ++m) {        // pieces [bp[0], bp[1]], shifting
+    const double u = bp[0], v = bp[1], L = v - u;
+#pragma unroll
+    for (int e = 0; e < 19; ++e) bp[e] = bp[e + 1];
+    bp[19] = kNone;
+    if (!(v < kNone)) break;
+    if (!(u < v)) continue;
+    // the nearest z* beyond each end, if closer than half the piece
+    double db = kNone, da = kNone;
+#pragma unroll
+    for (int e = 0; e < 18; ++e) {
+      if (zs[e] < u) db = fmin(db, u - zs[e]);
+      if (zs[e] > v && zs[e] < kNone) da = fmin(da, zs[e] - v);
+    }
+    // The ends of the piece are singular where they are z* (not a face);
+    // a z* within 1e-9 of the piece's length from an end counts as at it
+    // (the substitution then meets it; grading would take ~30 halvings).
+    bool su = u != (double)k - Z, sv = v != (double)(k + 1) - Z;
+    if (db <= 1e-9 * L) su = true;
+    if (da <= 1e-9 * L) sv = true;
+    double cur = u;
+    bool cur_sing = su;
+    if (db > 1e-9 * L && db < 0.5 * L)      // graded towards u
+      for (double s = db; s < 0.5 * L; s = 2.0 * s + db) {
+        V += gl_piece(X, Y, R, i, j, cur, u + s, cur_sing, false, g0, gs);
+        cur = u + s;
+        cur_sing = false;
+      }
+    if (da > 1e-9 * L && da < 0.5 * L) {    // graded towards v
+      int K = 0;
+      for (double s = da; s < 0.5 * L; s = 2.0 * s + da) ++K;
+      for (int kk = K; kk >= 1; --kk) {
+        const double s = da * (exp2((double)kk) - 1.0);
+        V += gl_piece(X, Y, R, i, j, cur, v - s, cur_sing, false, g0, gs);
+        cur = v - s;
+        cur_sing = false;
+      }
+    }
+    V += gl_piece(X, Y, R, i, j, cur, v, cur_sing, sv, g0, gs);
+  }
+  return V;
+}
+
+__device__ __forceinline__ double sphere_cell_volume(double X, double Y,
+                                                     double Z, double R, int i,
+                                                     int j, int k) {
+  return fmin(fmax(volume_nodes(X, Y, Z, R, i, j, k, 0, 1), 0.0), 1.0);
+}
+
+// The box of a tile (cells b*256 .. b*256+255), as cell-coordinate
+// intervals; a tile that wraps a row or a plane takes the whole extent of
+// the axes below.
+__device__ __forceinline__ void tile_box(const Params3& P, int b, int lo[3],
+                                         int hi[3]) {
+  const int c0 = b * kBlock, c1 = min(P.N, c0 + kBlock) - 1;
+  const int nxy = P.nx * P.ny;
+  const int k0 = c0 / nxy, k1 = c1 / nxy;
+  const int j0 = (c0 - k0 * nxy) / P.nx, j1 = (c1 - k1 * nxy) / P.nx;
+  const int i0 = c0 - k0 * nxy - j0 * P.nx, i1 = c1 - k1 * nxy - j1 * P.nx;
+  lo[2] = k0; hi[2] = k1 + 1;
+  if (k0 == k1) {
+    lo[1] = j0; hi[1] = j1 + 1;
+    if (j0 == j1) { lo[0] = i0; hi[0] = i1 + 1; }
+    else { lo[0] = 0; hi[0] = P.nx; }
+  } else {
+    lo[1] = 0; hi[1] = P.ny; lo[0] = 0; hi[0] = P.nx;
+  }
+}
+
+// Distance^2 from a centre to a box, through the nearest periodic copy.
+__device__ __forceinline__ bool sphere_meets_tile(const Params3& P,
+                                                  const double c[3], double R,
+                                                  int b) {
+#pragma clang fp contract(off)
+  int lo[3], hi[3];
+  tile_box(P, b, lo, hi);
+  const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+  double s = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    double best = 1e300;
+    for (int sh = -1; sh <= 1; ++sh) {
+      if (sh != 0 && !P.per[a]) continue;
+      const double x = c[a] + sh * L[a];
+      const double d = fmax(0.0, fmax((double)lo[a] - x, x - (double)hi[a]));
+      best = fmin(best, d);
+    }
+    s += best * best;
+  }
+  return s < R * R;
+}
+
+// Candidate spheres of tile b: bit p set if sphere p may reach it (every
+// wave computes the same mask).
+__device__ __forceinline__ unsigned long long tile_candidates(
+    const Params3& P, const double* __restrict__ S, const double* __restrict__ C,
+    int b) {
+  const int lane = threadIdx.x & 63;
+  bool hit = false;
+  if (lane < P.np) {
+    const double c[3] = {S[fX * P.np + lane], S[fY * P.np + lane],
+                         S[fZ * P.np + lane]};
+    hit = sphere_meets_tile(P, c, C[cR * P.np + lane], b);
+  }
+  return __ballot(hit);
+}
+
+// The spheres reaching cell (i, j, k): ids and shares f_s,p in ascending
+// sphere order (scaled to sum to one where they exceed it), and f_s.
+struct CellGeo {
+  int cnt;
+  int id[kMaxK];
+  double w[kMaxK];
+  double fs;
+};
+
+__device__ __forceinline__ void cell_geometry(const Params3& P,
+                                              const double* __restrict__ S,
+                                              const double* __restrict__ C,
+                                              unsigned long long mask, int i,
+                                              int j, int k, CellGeo& g,
+                                              int* flags) {
+  g.cnt = 0;
+  double sum = 0.0;
+  const double node[3] = {i + 0.5, j + 0.5, k + 0.5};
+  const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+  for (unsigned long long m = mask; m; m &= m - 1) {
+    const int p = __ffsll((long long)m) - 1;
+    const double R = C[cR * P.np + p];
+    double c[3];
+    for (int a = 0; a < 3; ++a)
+      c[a] = near_copy(S[(fX + a) * P.np + p], node[a], L[a], P.per[a]);
+    if (!in_band(c[0], c[1], c[2], R, i, j, k)) continue;
+    if (g.cnt >= P.kmax) {
+      if (flags) atomicOr(flags, kFlagOverlap);
+      continue;
+    }
+    const double w = wholly_inside(c[0], c[1], c[2], R, i, j, k)
+                         ? 1.0
+                         : sphere_cell_volume(c[0], c[1], c[2], R, i, j, k);
+    g.id[g.cnt] = p;
+    g.w[g.cnt] = w;
+    ++g.cnt;
+  }
+  for (int n = 0; n < kMaxK; ++n)
+    if (n < g.cnt) sum += g.w[n];
+  if (sum > 1.0) {
+    for (int n = 0; n < kMaxK; ++n)
+      if (n < g.cnt) g.w[n] /= sum;
+    sum = 1.0;
+  }
+  g.fs = sum;
+}
+
+// u_s = U + Omega x (x - X) at the node, through the nearest copy
+__device__ __forceinline__ void solid_velocity(const Params3& P,
+                                               const double* __restrict__ S,
+                                               int p, int i, int j, int k,
+                                               double us[3], double r[3]) {
+  const double node[3] = {i + 0.5, j + 0.5, k + 0.5};
+  const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+  for (int a = 0; a < 3; ++a)
+    r[a] = node[a] - near_copy(S[(fX + a) * P.np + p], node[a], L[a], P.per[a]);
+  const double Ox = S[fOx * P.np + p], Oy = S[fOy * P.np + p],
+               Oz = S[fOz * P.np + p];
+  us[0] = S[fU * P.np + p] + (Oy * r[2] - Oz * r[1]);
+  us[1] = S[fV * P.np + p] + (Oz * r[0] - Ox * r[2]);
+  us[2] = S[fW * P.np + p] + (Ox * r[1] - Oy * r[0]);
+}
+
+__device__ __forceinline__ double feq_q(int q, double rho, double ux,
+                                        double uy, double uz, double u2) {
+  const double eu = ex(q) * ux + ey(q) * uy + ez(q) * uz;
+  return wq(q) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * u2);
+}
+
+// wave sum of a double (fixed butterfly order: every lane ends with the
+// same value)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Initial state
+
+__global__ __launch_bounds__(kBlock) void k3_init(
+    const Params3 P, double* __restrict__ f, double* __restrict__ g,
+    double* __restrict__ h, double* __restrict__ macro,
+    const double* __restrict__ S, const double* __restrict__ C, int* flags) {
+  const unsigned long long mask = tile_candidates(P, S, C, blockIdx.x);
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= P.N) return;
+  const int nxy = P.nx * P.ny, k = c / nxy, j = (c - k * nxy) / P.nx,
+            i = c - k * nxy - j * P.nx;
+  CellGeo geo;
+  cell_geometry(P, S, C, mask, i, j, k, geo, flags);
+  const double fs = geo.fs;
+  double u[3] = {(1.0 - fs) * P.init_u[0], (1.0 - fs) * P.init_u[1],
+                 (1.0 - fs) * P.init_u[2]};
+  double eps = (1.0 - fs) * P.cv_f * P.init_T;
+  for (int n = 0; n < kMaxK; ++n) {
+    if (n >= geo.cnt) break;
+    double us[3], r[3];
+    solid_velocity(P, S, geo.id[n], i, j, k, us, r);
+    for (int a = 0; a < 3; ++a) u[a] += geo.w[n] * us[a];
+    eps += geo.w[n] * P.cv_s * C[cTinit * P.np + geo.id[n]];
+  }
+  const double cv = (1.0 - fs) * P.cv_f + fs * P.cv_s, T = eps / cv;
+  const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q)
+    f[(size_t)q * P.N + c] = feq_q(q, P.rho0, u[0], u[1], u[2], u2);
+  g[c] = eps - (1.0 - kW0G) * P.cref * T;
+#pragma unroll
+  for (int q = 1; q < kQG; ++q) g[(size_t)q * P.N + c] = kW1G * P.cref * T;
+  h[c] = 2.0 * fs;
+  const double mv[kMacro] = {P.rho0, u[0], u[1], u[2], T, fs, 0.0};
+#pragma unroll
+  for (int m = 0; m < kMacro; ++m) macro[(size_t)m * P.N + c] = mv[m];
+}
+
+// ---------------------------------------------------------------------------
+// Sphere pass: one block per sphere.  The momentum-exchange sums of the
+// last lattice step (tiles thread-strided, then fixed wave and block
+// trees), then (update) the Newton-Euler step of eq. particle with the
+// inside-fluid terms of eq. inside.fluid and the repulsion, into nxt.
+
+__global__ __launch_bounds__(kBlock) void k3_particles(
+    const Params3 P, double* __restrict__ cur, double* __restrict__ nxt,
+    const double* __restrict__ C, const double* __restrict__ partial,
+    const unsigned long long* __restrict__ tmask, int have, int update) {
+  __shared__ double red[kBlock / 64][kPartial];
+  const int p = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int np = P.np;
+  double acc[kPartial] = {0, 0, 0, 0, 0, 0};
+  if (have)   // the tiles whose candidates included the sphere
+    for (int b = t; b < P.nblocks; b += kBlock)
+      if ((tmask[b] >> p) & 1ull)
+        for (int v = 0; v < kPartial; ++v)
+          acc[v] += partial[((size_t)p * P.nblocks + b) * kPartial + v];
+  for (int v = 0; v < kPartial; ++v) {
+    const double s = wave_sum(acc[v]);
+    if (lane == 0) red[wv][v] = s;
+  }
+  __syncthreads();
+  if (t != 0) return;
+  for (int v = 0; v < kPartial; ++v)
+    acc[v] = ((red[0][v] + red[1][v]) + red[2][v]) + red[3][v];
+  // F = -sum f_s,p (f^eq - f*) e, T = -sum (x - X) x [the same]
+  const double F[3] = {-acc[0], -acc[1], -acc[2]};
+  const double T[3] = {-acc[3], -acc[4], -acc[5]};
+  for (int a = 0; a < 3; ++a) {
+    cur[(fFx + a) * np + p] = F[a];
+    cur[(fTx + a) * np + p] = T[a];
+  }
+  if (!update) return;
+  const double R = C[cR * np + p], rs = C[cRho * np + p];
+  const double Vol = 4.0 / 3.0 * M_PI * R * R * R, M = rs * Vol;
+  const double I = 0.4 * M * R * R, Min = P.rho_f * Vol, Iin = P.rho_f * I / rs;
+  const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+  double X[3], U[3], O[3], Up[3], Op[3];
+  for (int a = 0; a < 3; ++a) {
+    X[a] = cur[(fX + a) * np + p];
+    U[a] = cur[(fU + a) * np + p];
+    O[a] = cur[(fOx + a) * np + p];
+    Up[a] = cur[(fUp + a) * np + p];
+    Op[a] = cur[(fOxp + a) * np + p];
+  }
+  // repulsion (positions at n): the other spheres, then the walls
+  double Fr[3] = {0.0, 0.0, 0.0};
+  if (P.zeta > 0.0) {
+    for (int q = 0; q < np; ++q) {
+      if (q == p) continue;
+      double r[3], d2 = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        r[a] = X[a] - near_copy(cur[(fX + a) * np + q], X[a], L[a], P.per[a]);
+        d2 += r[a] * r[a];
+      }
+      const double d = sqrt(d2), reach = R + C[cR * np + q] + P.zeta;
+      if (d < reach && d > 0.0) {
+        const double w = (reach - d) / P.zeta, mag = P.k_pp * w * w;
+        for (int a = 0; a < 3; ++a) Fr[a] += mag * r[a] / d;
+      }
+    }
+    for (int face = 0; face < 6; ++face) {
+      const int a = face / 2;
+      if (P.per[a]) continue;
+      const double gap = (face & 1) ? L[a] - X[a] : X[a];
+      const double d = 2.0 * gap, reach = 2.0 * R + P.zeta;
+      if (d < reach) {
+        const double w = (reach - d) / P.zeta;
+        Fr[a] += ((face & 1) ? -1.0 : 1.0) * P.k_pw * w * w;
+      }
+    }
+  }
+  double nU[3] = {U[0], U[1], U[2]}, nO[3] = {O[0], O[1], O[2]};
+  if (C[cFixed * np + p] == 0.0) {
+    for (int a = 0; a < 3; ++a) {
+      const double Fin = -Min * (U[a] - Up[a]), Tin = -Iin * (O[a] - Op[a]);
+      const double Fc = (F[a] - Fin) + (rs - P.rho_f) * Vol * P.grav[a] + Fr[a];
+      nU[a] = U[a] + Fc / M;
+      nO[a] = O[a] + (T[a] - Tin) / I;
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    double x = X[a] + U[a];
+    if (P.per[a]) {
+      if (x >= L[a]) x -= L[a];
+      if (x < 0.0) x += L[a];
+    }
+    nxt[(fX + a) * np + p] = x;
+    nxt[(fU + a) * np + p] = nU[a];
+    nxt[(fOx + a) * np + p] = nO[a];
+    nxt[(fUp + a) * np + p] = U[a];
+    nxt[(fOxp + a) * np + p] = O[a];
+    nxt[(fFx + a) * np + p] = 0.0;
+    nxt[(fTx + a) * np + p] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Geometry: the spheres' shares of the cells of the tiles they may reach,
+// written to gid (count in bits 0-2, sphere ids in the bytes above) and gw
+// (kMaxK shares), and each tile's candidate mask to tmask.  Kernels of their
+// own, so that the exact-volume quadrature holds no registers in the
+// streaming kernel.
+//   pass A (one block per tile): band tests; a cell a sphere covers wholly
+//     takes share 1, a partly covered one becomes an item of a global list;
+//   pass B (a fixed grid walking the list): each item is integrated by a
+//     group of 16 lanes, one Gauss-Legendre node each.  A tile holds from
+//     none to hundreds of items, so a global list balances the work that
+//     per-tile groups would leave to the busiest tile.
+// The step kernel scales shares that add up to more than one.
+
+constexpr int kGroup = 16;
+static_assert(kGroup == kGL, "one lane per quadrature node");
+
+__global__ __launch_bounds__(kBlock) void k3_geometry_a(
+    const Params3 P, const double* __restrict__ S, const double* __restrict__ C,
+    int* __restrict__ gid, double* __restrict__ gw,
+    unsigned long long* __restrict__ tmask, int* __restrict__ items,
+    int* __restrict__ nitems, int max_items, int* flags) {
+  const unsigned long long mask = tile_candidates(P, S, C, blockIdx.x);
+  if (threadIdx.x == 0) tmask[blockIdx.x] = mask;     // for the step and
+  if (!mask) return;                                  // the sphere pass
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= P.N) return;
+  const int nxy = P.nx * P.ny;
+  const int k = c / nxy, j = (c - k * nxy) / P.nx, i = c - k * nxy - j * P.nx;
+  const double node[3] = {i + 0.5, j + 0.5, k + 0.5};
+  const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+  int cnt = 0, packed = 0;
+  double w[kMaxK] = {0.0, 0.0, 0.0, 0.0};
+  for (unsigned long long m = mask; m; m &= m - 1) {   // ascending spheres
+    const int p = __ffsll((long long)m) - 1;
+    const double R = C[cR * P.np + p];
+    double cp[3];
+    for (int a = 0; a < 3; ++a)
+      cp[a] = near_copy(S[(fX + a) * P.np + p], node[a], L[a], P.per[a]);
+    if (!in_band(cp[0], cp[1], cp[2], R, i, j, k)) continue;
+    if (cnt >= P.kmax) {
+      atomicOr(flags, kFlagOverlap);
+      continue;
+    }
+    packed |= p << (8 * cnt + 8);
+    if (wholly_inside(cp[0], cp[1], cp[2], R, i, j, k)) {
+#pragma unroll
+      for (int s = 0; s < kMaxK; ++s)
+        if (s == cnt) w[s] = 1.0;
+    } else {
+      const int at = atomicAdd(nitems, 1);
+      if (at < max_items) items[at] = c * kMaxK + cnt;
+      else atomicOr(flags, kFlagOverlap);    // cannot happen: room for all
+    }
+    ++cnt;
+  }
+#pragma unroll
+  for (int s = 0; s < kMaxK; ++s) gw[(size_t)c * kMaxK + s] = w[s];
+  gid[c] = packed | cnt;
+}
+
+__global__ __launch_bounds__(kBlock) void k3_geometry_b(
+    const Params3 P, const double* __restrict__ S, const double* __restrict__ C,
+    const int* __restrict__ gid, double* __restrict__ gw,
+    const int* __restrict__ items, const int* __restrict__ nitems) {
+  const int r = threadIdx.x % kGroup;
+  const int groups = gridDim.x * (kBlock / kGroup);
+  const int n = *nitems;
+  const int nxy = P.nx * P.ny;
+  for (int it = blockIdx.x * (kBlock / kGroup) + threadIdx.x / kGroup; it < n;
+       it += groups) {                                 // uniform in a group
+    const int item = items[it];
+    const int c = item / kMaxK, slot = item - c * kMaxK;
+    const int p = (gid[c] >> (8 * slot + 8)) & 255;
+    const int k = c / nxy, j = (c - k * nxy) / P.nx, i = c - k * nxy - j * P.nx;
+    const double node[3] = {i + 0.5, j + 0.5, k + 0.5};
+    const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+    double cp[3];
+    for (int a = 0; a < 3; ++a)
+      cp[a] = near_copy(S[(fX + a) * P.np + p], node[a], L[a], P.per[a]);
+    double v = volume_nodes(cp[0], cp[1], cp[2], C[cR * P.np + p], i, j, k, r,
+                            kGroup);
+#pragma unroll
+    for (int o = kGroup / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, kGroup);
+    if (r == 0) gw[(size_t)c * kMaxK + slot] = fmin(fmax(v, 0.0), 1.0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The lattice step
+
+template <bool OUT>
+__global__ __launch_bounds__(kBlock) void k3_step(
+    const Params3 P, const double* __restrict__ fin, double* __restrict__ fout,
+    const double* __restrict__ gin, double* __restrict__ gout,
+    const double* __restrict__ hin, double* __restrict__ hout,
+    const double* __restrict__ S, const double* __restrict__ C,
+    const int* __restrict__ gid, const double* __restrict__ gw,
+    const unsigned long long* __restrict__ tmask, double* __restrict__ partial,
+    double* __restrict__ macro, int* flags) {
+  __shared__ double red[kBlock / 64][kPartial];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  // the candidate spheres of the tile, as the geometry pass found them
+  const unsigned long long mask = P.np > 0 ? tmask[blockIdx.x] : 0ull;
+  const int c = blockIdx.x * kBlock + t;
+  const bool act = c < P.N;
+  const int cc = act ? c : P.N - 1;
+  const int nxy = P.nx * P.ny, k = cc / nxy, j = (cc - k * nxy) / P.nx,
+            i = cc - k * nxy - j * P.nx;
+
+  // pull streaming: every load is issued first (a population whose
+  // upstream cell lies beyond a wall loads the cell's own value, replaced
+  // below), then the wall rules fix those populations
+  double fst[kQ], g[kQG];
+  unsigned long long wall_of = 0ull;   // 3 bits per population: face + 1
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    int si = i - ex(q), sj = j - ey(q), sk = k - ez(q), wall = 0;
+    if (si < 0) { if (P.per[0]) si += P.nx; else wall = 1; }
+    else if (si >= P.nx) { if (P.per[0]) si -= P.nx; else wall = 2; }
+    if (sj < 0) { if (P.per[1]) sj += P.ny; else wall = 3; }
+    else if (sj >= P.ny) { if (P.per[1]) sj -= P.ny; else wall = 4; }
+    if (sk < 0) { if (P.per[2]) sk += P.nz; else wall = 5; }
+    else if (sk >= P.nz) { if (P.per[2]) sk -= P.nz; else wall = 6; }
+    const size_t src = wall ? (size_t)cc
+                            : ((size_t)sk * P.ny + sj) * P.nx + si;
+    fst[q] = fin[(size_t)q * P.N + src];
+    if (q < kQG) g[q] = gin[(size_t)q * P.N + src];
+    wall_of |= (unsigned long long)wall << (3 * q);
+  }
+  const double hold = hin[cc];
+  if (wall_of) {
+#pragma unroll
+    for (int q = 1; q < kQ; ++q) {
+      const int wall = (int)((wall_of >> (3 * q)) & 7ull) - 1;
+      if (wall < 0) continue;
+      // the face's constants, selected without indexing the arguments
+      double uw[3] = {0.0, 0.0, 0.0}, Tw = 0.0;
+      int dir = 0;
+#pragma unroll
+      for (int face = 0; face < 6; ++face)
+        if (face == wall) {
+          uw[0] = P.u_wall[face][0];
+          uw[1] = P.u_wall[face][1];
+          uw[2] = P.u_wall[face][2];
+          Tw = P.T_wall[face];
+          dir = P.wall_dirichlet[face];
+        }
+      const double eu = ex(q) * uw[0] + ey(q) * uw[1] + ez(q) * uw[2];
+      fst[q] = fin[(size_t)opp(q) * P.N + cc] + 6.0 * wq(q) * P.rho0 * eu;
+      if (q < kQG)
+        g[q] = dir ? -gin[(size_t)opp(q) * P.N + cc] + 2.0 * kW1G * P.cref * Tw
+                   : gin[(size_t)opp(q) * P.N + cc];
+    }
+  }
+
+  // the geometry pass's shares at the new positions; [df_s/dt] through the
+  // carrier h = 2 f_s + d (eq. dfs_dt: d' = 2 f_s' - h, h' = 2 f_s' + d')
+  int packed = 0;
+  double w4[kMaxK] = {0.0, 0.0, 0.0, 0.0};
+  if (mask) {
+    packed = gid[cc];
+#pragma unroll
+    for (int n = 0; n < kMaxK; ++n) w4[n] = gw[(size_t)cc * kMaxK + n];
+  }
+  const int cnt = packed & 7;
+  double fs = 0.0;
+#pragma unroll
+  for (int n = 0; n < kMaxK; ++n) fs += n < cnt ? w4[n] : 0.0;
+  if (fs > 1.0) {            // overlapping spheres: shares scaled to sum to 1
+#pragma unroll
+    for (int n = 0; n < kMaxK; ++n) w4[n] /= fs;
+    fs = 1.0;
+  }
+  const double dfs = 2.0 * fs - hold;
+
+  // volumetric no-slip step (eq. fi), sphere by sphere in ascending order;
+  // each sphere's momentum-exchange share is reduced over the block at once
+  double rho = 0.0;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) rho += fst[q];
+  double f[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) f[q] = (1.0 - fs) * fst[q];
+  for (unsigned long long m = mask; m; m &= m - 1) {      // uniform
+    const int p = __ffsll((long long)m) - 1;
+    double part[kPartial] = {0, 0, 0, 0, 0, 0};
+    double w = 0.0;
+    bool mine = false;
+#pragma unroll
+    for (int n = 0; n < kMaxK; ++n)
+      if (n < cnt && ((packed >> (8 * n + 8)) & 255) == p) {
+        w = w4[n];
+        mine = true;
+      }
+    if (act && mine) {
+      double us[3], r[3];
+      solid_velocity(P, S, p, i, j, k, us, r);
+      const double u2 = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
+      double dP[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const double fe = feq_q(q, rho, us[0], us[1], us[2], u2);
+        f[q] += w * fe;
+        const double df = w * (fe - fst[q]);
+        dP[0] += df * ex(q);
+        dP[1] += df * ey(q);
+        dP[2] += df * ez(q);
+      }
+      part[0] = dP[0];
+      part[1] = dP[1];
+      part[2] = dP[2];
+      part[3] = r[1] * dP[2] - r[2] * dP[1];
+      part[4] = r[2] * dP[0] - r[0] * dP[2];
+      part[5] = r[0] * dP[1] - r[1] * dP[0];
+    }
+    for (int v = 0; v < kPartial; ++v) {
+      const double s = wave_sum(part[v]);
+      if (lane == 0) red[wv][v] = s;
+    }
+    __syncthreads();
+    if (t < kPartial)
+      partial[((size_t)p * P.nblocks + blockIdx.x) * kPartial + t] =
+          ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+    __syncthreads();
+  }
+  if (!act) return;
+
+  double jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    jx += ex(q) * f[q];
+    jy += ey(q) * f[q];
+    jz += ez(q) * f[q];
+  }
+  // per-cell properties (Sec. 2.2); lambda/rho_f = c_s^2 c_ref (tau_g - 1/2)
+  const double cv = (1.0 - fs) * P.cv_f + fs * P.cv_s;
+  const double lam = (1.0 - fs) * P.lam_f + fs * P.lam_s;
+  const double tau_g = 0.5 + lam / (P.rho_f * kCs2G * P.cref);
+  const double sj = 1.0 / tau_g;
+  const double se = P.sigma_rule ? 1.0 : 1.0 / (0.5 + 0.25 / (tau_g - 0.5));
+  // macroscopic values and the coupled T-u solve (F = A + B T)
+  double G = 0.0, J[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < kQG; ++q) {
+    G += g[q];
+    J[0] += ex(q) * g[q];
+    J[1] += ey(q) * g[q];
+    J[2] += ez(q) * g[q];
+  }
+  double gT[3];
+  for (int a = 0; a < 3; ++a) gT[a] = -J[a] / (kCs2G * P.cref * tau_g);
+  const double wf = 1.0 - fs, dcv = P.cv_s - P.cv_f;
+  const double jv[3] = {jx, jy, jz};
+  double A[3], B[3], jg = 0.0, bg = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    A[a] = wf * (P.body[a] + P.rho_f * P.beta * P.T_ref * P.grav[a]);
+    B[a] = -wf * P.rho_f * P.beta * P.grav[a];
+    jg += (jv[a] + 0.5 * A[a]) * gT[a];
+    bg += B[a] * gT[a];
+  }
+  const double T = (G - 0.5 * cv * jg / rho) /
+                   (cv - 0.5 * dcv * dfs + 0.25 * cv * bg / rho);
+  double F[3], u[3];
+  for (int a = 0; a < 3; ++a) {
+    F[a] = A[a] + B[a] * T;
+    u[a] = (jv[a] + 0.5 * F[a]) / rho;
+  }
+  const double eps = cv * T;
+  const double qc = -cv * (u[0] * gT[0] + u[1] * gT[1] + u[2] * gT[2]) +
+                    dcv * T * dfs;
+  if (!(rho > 0.0) || !isfinite(T) || !isfinite(u[0]) || !isfinite(u[1]) ||
+      !isfinite(u[2]))
+    atomicOr(flags, kFlagUnstable);
+
+  // energy collision: even part at sigma_e, odd part at sigma_j, the
+  // source on the rest population
+  {
+    const double geq0 = eps - (1.0 - kW0G) * P.cref * T, geqi = kW1G * P.cref * T;
+    gout[c] = g[0] - se * (g[0] - geq0) + (1.0 - 0.5 * se) * qc;
+#pragma unroll
+    for (int q = 1; q < kQG; ++q) {
+      const double ev = 0.5 * (g[q] + g[opp(q)]), od = 0.5 * (g[q] - g[opp(q)]);
+      gout[(size_t)q * P.N + c] = g[q] - se * (ev - geqi) - sj * od;
+    }
+  }
+  // flow MRT collision (eq. lbe.rho.col),
+  //   f' = f + M^-1 [-S M (f - f^eq) + (I - S/2) M F_G],
+  // F_G Guo's term; with a = f - f^eq + F_G/2 this is
+  //   f' = a + f^eq + F_G/2 - M^-1 S M a,
+  // which holds one vector of 19 (a) and its 19 relaxed moments at a time
+  {
+    const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    auto guo = [&](int q) {
+      const double eF = ex(q) * F[0] + ey(q) * F[1] + ez(q) * F[2];
+      const double eu = ex(q) * u[0] + ey(q) * u[1] + ez(q) * u[2];
+      return wq(q) * (3.0 * eF + 9.0 * eu * eF - 3.0 * uF);
+    };
+    double a[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+      a[q] = f[q] - feq_q(q, rho, u[0], u[1], u[2], u2) + 0.5 * guo(q);
+    double dm[kQ];
+    relax_moments(a, dm, P.snu, P.sq, std::make_index_sequence<kQ>{});
+    auto base = [&](int q) {
+      return a[q] + feq_q(q, rho, u[0], u[1], u[2], u2) + 0.5 * guo(q);
+    };
+    back_transform_store(dm, base, fout, (size_t)P.N, (size_t)c,
+                         std::make_index_sequence<kQ>{});
+  }
+  hout[c] = 2.0 * fs + dfs;
+  if (OUT) {
+    const double mv[kMacro] = {rho, u[0], u[1], u[2], T, fs, dfs};
+#pragma unroll
+    for (int m = 0; m < kMacro; ++m) macro[(size_t)m * P.N + c] = mv[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-sphere thermal outputs: one block per sphere over the cells of its
+// bounding box (through the nearest copies); out[p] = {sum f_s,p T,
+// sum f_s,p c_vs T, sum f_s,p, min T over wholly covered cells, min T over
+// all}.
+
+__global__ __launch_bounds__(kBlock) void k3_sphere_sums(
+    const Params3 P, const double* __restrict__ S, const double* __restrict__ C,
+    const double* __restrict__ macro, double* __restrict__ out) {
+  __shared__ double red[kBlock / 64][5];
+  const int p = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int np = P.np;
+  const double R = C[cR * np + p];
+  const double c0[3] = {S[fX * np + p], S[fY * np + p], S[fZ * np + p]};
+  int lo[3], ext[3];
+  const int n3[3] = {P.nx, P.ny, P.nz};
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = (int)floor(c0[a] - R) - 1;
+    ext[a] = (int)floor(c0[a] + R) + 1 - lo[a] + 1;
+  }
+  const long long total = (long long)ext[0] * ext[1] * ext[2];
+  double sT = 0.0, sE = 0.0, sW = 0.0, mFull = INFINITY, mAny = INFINITY;
+  const unsigned long long all = np >= 64 ? ~0ull : ((1ull << np) - 1ull);
+  for (long long e = t; e < total; e += kBlock) {
+    int idx[3] = {(int)(e % ext[0]), (int)((e / ext[0]) % ext[1]),
+                  (int)(e / ((long long)ext[0] * ext[1]))};
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+      idx[a] += lo[a];
+      if (P.per[a]) idx[a] = ((idx[a] % n3[a]) + n3[a]) % n3[a];
+      if (idx[a] < 0 || idx[a] >= n3[a]) ok = false;
+    }
+    if (!ok) continue;
+    CellGeo geo;
+    cell_geometry(P, S, C, all, idx[0], idx[1], idx[2], geo, nullptr);
+    for (int n = 0; n < kMaxK; ++n) {
+      if (n >= geo.cnt || geo.id[n] != p) continue;
+      const size_t c = ((size_t)idx[2] * P.ny + idx[1]) * P.nx + idx[0];
+      const double T = macro[(size_t)mT * P.N + c], w = geo.w[n];
+      sT += w * T;
+      sE += w * P.cv_s * T;
+      sW += w;
+      mAny = fmin(mAny, T);
+      double cp[3];
+      const double node[3] = {idx[0] + 0.5, idx[1] + 0.5, idx[2] + 0.5};
+      const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+      for (int a = 0; a < 3; ++a) cp[a] = near_copy(c0[a], node[a], L[a], P.per[a]);
+      if (wholly_inside(cp[0], cp[1], cp[2], R, idx[0], idx[1], idx[2]))
+        mFull = fmin(mFull, T);
+    }
+  }
+  double v[5] = {wave_sum(sT), wave_sum(sE), wave_sum(sW), mFull, mAny};
+  for (int o = 32; o >= 1; o >>= 1) {
+    v[3] = fmin(v[3], __shfl_xor(v[3], o, 64));
+    v[4] = fmin(v[4], __shfl_xor(v[4], o, 64));
+  }
+  if (lane == 0)
+    for (int m = 0; m < 5; ++m) red[wv][m] = v[m];
+  __syncthreads();
+  if (t == 0) {
+    double r[5] = {0.0, 0.0, 0.0, INFINITY, INFINITY};
+    for (int w = 0; w < kBlock / 64; ++w) {
+      for (int m = 0; m < 3; ++m) r[m] += red[w][m];
+      r[3] = fmin(r[3], red[w][3]);
+      r[4] = fmin(r[4], red[w][4]);
+    }
+    for (int m = 0; m < 5; ++m) out[p * 5 + m] = r[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+
+static unsigned nblocks_of(const Params3& P) { return (unsigned)P.nblocks; }
+
+hipError_t launch_init(const Params3& P, double* f, double* g, double* h,
+                       double* macro, const double* S, const double* C,
+                       int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k3_init, dim3(nblocks_of(P)), dim3(kBlock), 0, s, P, f,
+                     g, h, macro, S, C, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_particles(const Params3& P, double* cur, double* nxt,
+                            const double* C, const double* partial,
+                            const unsigned long long* tmask, int have,
+                            int update, hipStream_t s) {
+  if (P.np == 0) return hipSuccess;
+  hipLaunchKernelGGL(k3_particles, dim3(P.np), dim3(kBlock), 0, s, P, cur, nxt, C,
+                     partial, tmask, have, update);
+  return hipGetLastError();
+}
+
+hipError_t launch_geometry(const Params3& P, const double* S,
+                           const double* C, int* gid, double* gw,
+                           unsigned long long* tmask, int* items, int* nitems,
+                           int max_items, int* flags, hipStream_t s) {
+  if (P.np == 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(nitems, 0, sizeof(int), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k3_geometry_a, dim3(nblocks_of(P)), dim3(kBlock), 0, s,
+                     P, S, C, gid, gw, tmask, items, nitems, max_items, flags);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k3_geometry_b, dim3(2048), dim3(kBlock), 0, s, P, S, C,
+                     gid, gw, items, nitems);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const Params3& P, bool out, const double* fin,
+                       double* fout, const double* gin, double* gout,
+                       const double* hin, double* hout, const double* S,
+                       const double* C, const int* gid, const double* gw,
+                       const unsigned long long* tmask, double* partial,
+                       double* macro, int* flags, hipStream_t s) {
+  if (out)
+    hipLaunchKernelGGL(k3_step<true>, dim3(nblocks_of(P)), dim3(kBlock), 0, s,
+                       P, fin, fout, gin, gout, hin, hout, S, C, gid, gw,
+                       tmask, partial, macro, flags);
+  else
+    hipLaunchKernelGGL(k3_step<false>, dim3(nblocks_of(P)), dim3(kBlock), 0,
+                       s, P, fin, fout, gin, gout, hin, hout, S, C, gid, gw,
+                       tmask, partial, macro, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_sphere_sums(const Params3& P, const double* S,
+                              const double* C, const double* macro,
+                              double* out, hipStream_t s) {
+  if (P.np == 0) return hipSuccess;
+  hipLaunchKernelGGL(k3_sphere_sums, dim3(P.np), dim3(kBlock), 0, s, P, S, C,
+                     macro, out);
+  return hipGetLastError();
+}
+
+// Gauss-Legendre nodes on [0, 1]: roots of P_n by Newton's method from
+// Chebyshev-like starting points, weights 2/((1 - x^2) P_n'(x)^2), mapped
+// from [-1, 1].
+hipError_t upload_quadrature() {
+  double x[kGL], w[kGL];
+  for (int m = 0; m < kGL; ++m) {
+    double z = cos(M_PI * (m + 0.75) / (kGL + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int l = 2; l <= kGL; ++l) {
+        const double p2 = ((2.0 * l - 1.0) * z * p1 - (l - 1.0) * p0) / l;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = kGL * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-17) break;
+    }
+    x[m] = 0.5 * (1.0 - z);
+    w[m] = 1.0 / ((1.0 - z * z) * dp * dp);   // (2/((1-z^2) P'^2)) / 2
+  }
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(gl_x), x, sizeof x);
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(gl_w), w, sizeof w);
+  return e;
+}
+
+}  // namespace vlb3

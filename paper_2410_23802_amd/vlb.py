@@ -19,6 +19,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvlb.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "vlb.h")
+HEADER3 = os.path.join(os.path.dirname(HERE), "include", "vlb3.h")
 
 VLB_OK, VLB_EINVAL, VLB_ENOMEM, VLB_EHIP = 0, -1, -2, -3
 VLB_EUNSTABLE, VLB_EOVERLAP, VLB_ESTATE = -4, -5, -6
@@ -74,6 +75,44 @@ class vlb_particle_desc(ctypes.Structure):
                 ("x", "y", "theta", "ux", "uy", "omega", "radius", "rho_s",
                  "T_init", "radius_minor")] + [("fixed", ctypes.c_int32),
                                                ("hold_T", ctypes.c_int32)]
+
+
+class vlb3_domain_desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("face_flow", ctypes.c_int32 * 6),
+        ("u_wall", (ctypes.c_double * 3) * 6),
+        ("face_thermal", ctypes.c_int32 * 6),
+        ("T_wall", ctypes.c_double * 6),
+        ("tau_f", ctypes.c_double),
+        ("rho_f", ctypes.c_double), ("cv_f", ctypes.c_double),
+        ("lambda_f", ctypes.c_double),
+        ("R_lambda", ctypes.c_double), ("R_cv", ctypes.c_double),
+        ("body_force", ctypes.c_double * 3), ("gravity", ctypes.c_double * 3),
+        ("beta", ctypes.c_double), ("T_ref", ctypes.c_double),
+        ("sigma_rule", ctypes.c_int32),
+        ("coll_range", ctypes.c_double), ("coll_stiff_pp", ctypes.c_double),
+        ("coll_stiff_pw", ctypes.c_double),
+        ("init_rho", ctypes.c_double), ("init_u", ctypes.c_double * 3),
+        ("init_T", ctypes.c_double),
+        ("kmax", ctypes.c_int32), ("precision", ctypes.c_int32),
+    ]
+
+
+class vlb3_sphere_desc(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("x", "y", "z", "ux", "uy", "uz", "ox", "oy", "oz", "radius",
+                 "rho_s", "T_init")] + [("fixed", ctypes.c_int32)]
+
+
+class vlb3_sphere_state(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("x", "y", "z", "ux", "uy", "uz", "ox", "oy", "oz", "Fx", "Fy",
+                 "Fz", "Tx", "Ty", "Tz", "T_mean", "T_min", "E_solid",
+                 "fs_sum")]
+
+
+FIELDS3 = {"rho": 0, "ux": 1, "uy": 2, "uz": 3, "T": 4, "fs": 5, "dfs": 6}
 
 
 class vlb_batch_tuning(ctypes.Structure):
@@ -162,6 +201,22 @@ def lib():
         "vlb_batch_device_bytes": ([vp], ctypes.c_size_t),
         "vlb_batch_last_error": ([vp], ctypes.c_char_p),
         "vlb_batch_destroy": ([vp], None),
+        "vlb3_create": ([ctypes.POINTER(vlb3_domain_desc), i32,
+                         ctypes.POINTER(vlb3_sphere_desc), vp,
+                         ctypes.POINTER(vp)], ctypes.c_int),
+        "vlb3_init": ([vp], ctypes.c_int),
+        "vlb3_step": ([vp, i64], ctypes.c_int),
+        "vlb3_read_field": ([vp, i32, vp, i32], ctypes.c_int),
+        "vlb3_read_populations": ([vp, i32, vp], ctypes.c_int),
+        "vlb3_read_spheres": ([vp, i32, ctypes.POINTER(vlb3_sphere_state)],
+                              ctypes.c_int),
+        "vlb3_timing_enable": ([vp, i32], ctypes.c_int),
+        "vlb3_timing_read": ([vp, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(i64)], ctypes.c_int),
+        "vlb3_step_count": ([vp], i64),
+        "vlb3_device_bytes": ([vp], ctypes.c_size_t),
+        "vlb3_last_error": ([vp], ctypes.c_char_p),
+        "vlb3_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -172,11 +227,13 @@ def lib():
 
 
 def header_functions() -> list[str]:
-    """Names of the functions include/vlb.h declares."""
-    with open(HEADER) as fh:
-        txt = fh.read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(vlb_\w+)\s*\(", txt)))
+    """Names of the functions include/vlb.h and include/vlb3.h declare."""
+    names = set()
+    for path in (HEADER, HEADER3):
+        with open(path) as fh:
+            txt = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        names |= set(re.findall(r"\b(vlb3?_\w+)\s*\(", txt))
+    return sorted(names)
 
 
 def make_domain_desc(d: dict, precision="fp64", shift_rho0=None,
@@ -525,3 +582,119 @@ class Batch:
         _bcheck(lib().vlb_batch_read_particles(self.h, int(i), n, arr),
                 "vlb_batch_read_particles", self.h)
         return _state_array(arr, n)
+
+
+# ---------------------------------------------------------------------------
+# Three dimensions (include/vlb3.h)
+
+def make_domain3_desc(d: dict) -> vlb3_domain_desc:
+    s = vlb3_domain_desc()
+    s.nx, s.ny, s.nz = int(d["nx"]), int(d["ny"]), int(d["nz"])
+    for k in range(6):
+        s.face_flow[k] = FACE_FLOW[d["face_flow"][k]]
+        s.face_thermal[k] = FACE_THERMAL[d["face_thermal"][k]]
+        s.T_wall[k] = float(d["T_wall"][k])
+        for a in range(3):
+            s.u_wall[k][a] = float(d["u_wall"][k][a])
+    for name in ("tau_f", "rho_f", "cv_f", "lambda_f", "R_lambda", "R_cv",
+                 "beta", "T_ref", "coll_range", "coll_stiff_pp",
+                 "coll_stiff_pw", "init_rho", "init_T"):
+        setattr(s, name, float(d[name]))
+    for a in range(3):
+        s.body_force[a] = float(d["body_force"][a])
+        s.gravity[a] = float(d["gravity"][a])
+        s.init_u[a] = float(d["init_u"][a])
+    s.sigma_rule = int(d["sigma_rule"])
+    s.kmax = int(d["kmax"])
+    s.precision = 0
+    return s
+
+
+def make_spheres(ps) -> ctypes.Array:
+    arr = (vlb3_sphere_desc * max(1, len(ps)))()
+    for k, p in enumerate(ps):
+        for n in ("x", "y", "z", "ux", "uy", "uz", "ox", "oy", "oz", "radius",
+                  "rho_s", "T_init"):
+            setattr(arr[k], n, float(p[n]))
+        arr[k].fixed = int(p.get("fixed", 0))
+    return arr
+
+
+def _check3(status: int, where: str, handle=None):
+    if status != VLB_OK:
+        msg = lib().vlb3_last_error(handle)
+        raise VlbError(status, where, msg.decode() if msg else "")
+
+
+class Domain3:
+    """One three-dimensional domain on the GPU (FP64), through the vlb3_*
+    C ABI.  Fields are numpy arrays shaped (nz, ny, nx)."""
+
+    def __init__(self, d: dict, spheres=(), stream=None):
+        self.d = dict(d)
+        self.spheres = list(spheres)
+        self.shape = (int(d["nz"]), int(d["ny"]), int(d["nx"]))
+        desc = make_domain3_desc(d)
+        arr = make_spheres(self.spheres)
+        h = ctypes.c_void_p()
+        _check3(lib().vlb3_create(ctypes.byref(desc), len(self.spheres), arr,
+                                  _stream_handle(stream), ctypes.byref(h)),
+                "vlb3_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vlb3_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def init(self):
+        _check3(lib().vlb3_init(self.h), "vlb3_init", self.h)
+        return self
+
+    def step(self, n: int = 1):
+        _check3(lib().vlb3_step(self.h, int(n)), "vlb3_step", self.h)
+        return self
+
+    def field(self, name: str) -> np.ndarray:
+        out = np.empty(self.shape, np.float64)
+        _check3(lib().vlb3_read_field(self.h, FIELDS3[name], out.ctypes.data,
+                                      0), "vlb3_read_field", self.h)
+        return out
+
+    def populations(self, which: str) -> np.ndarray:
+        q = 19 if which == "f" else 7
+        out = np.empty((q,) + self.shape, np.float64)
+        _check3(lib().vlb3_read_populations(self.h, 0 if which == "f" else 1,
+                                            out.ctypes.data),
+                "vlb3_read_populations", self.h)
+        return out
+
+    def particles(self) -> np.ndarray:
+        n = len(self.spheres)
+        arr = (vlb3_sphere_state * max(1, n))()
+        _check3(lib().vlb3_read_spheres(self.h, n, arr), "vlb3_read_spheres",
+                self.h)
+        names = [f[0] for f in vlb3_sphere_state._fields_]
+        out = np.zeros(n, dtype=[(k, np.float64) for k in names])
+        for i in range(n):
+            for k in names:
+                out[i][k] = getattr(arr[i], k)
+        return out
+
+    def timing(self, on: bool):
+        _check3(lib().vlb3_timing_enable(self.h, int(bool(on))),
+                "vlb3_timing_enable", self.h)
+        return self
+
+    def timing_read(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check3(lib().vlb3_timing_read(self.h, ctypes.byref(ms),
+                                       ctypes.byref(n)), "vlb3_timing_read",
+                self.h)
+        return ms.value, n.value
+
+    @property
+    def device_bytes(self) -> int:
+        return int(lib().vlb3_device_bytes(self.h))

@@ -393,3 +393,46 @@ def sphere(x, y, z, radius, rho_s=1.0, T_init=0.0, u=(0.0, 0.0, 0.0),
                 oy=float(omega[1]), oz=float(omega[2]), radius=float(radius),
                 rho_s=float(rho_s), T_init=float(T_init),
                 fixed=int(bool(fixed)))
+
+
+def c6_sphere_channel3(nx=80, ny=80, nz=320, D=16.0) -> tuple[dict, list]:
+    """The channel's sedimentation in three dimensions: one cold sphere
+    (D = 16, density ratio 1.5, T = 0) settling along z from near the top
+    of an 80 x 80 x 320 box (5 D wide, 20 D long), walls on all faces held
+    at T = 1, fluid at T = 1; tau_f = 0.53, Pr = 0.7, R_lambda = 10,
+    R_cv = 2, |g| = 1e-5, Gr = 1000, the repulsion of the channel case."""
+    tau_f, Pr, rho_r, g, Gr = 0.53, 0.7, 1.5, 1e-5, 1000.0
+    nu = viscosity(tau_f)
+    cp = collision_params(rho_r, D / 2, g)
+    d = domain3(nx, ny, nz, tau_f=tau_f, lambda_f=nu / Pr, R_lambda=10.0,
+                R_cv=2.0, gravity=(0.0, 0.0, -g),
+                beta=beta_from_grashof(Gr, g, 1.0, D, nu), T_ref=1.0,
+                init_T=1.0, **cp)
+    d = walls3(d, thermal="dirichlet", T_wall=1.0)
+    s = sphere(nx / 2.0, ny / 2.0, nz - 2.0 * D, D / 2, rho_s=rho_r,
+               T_init=0.0)
+    return d, [s]
+
+
+def c7_spheres_box3(n=64, L=96, D=12.0, seed=3) -> tuple[dict, list]:
+    """64 cold spheres (D = 12, density ratio 1.5, T = 0) placed by seeded
+    random sequential addition in the upper half of a 96^3 box with
+    adiabatic walls, fluid at T = 1; tau_f = 0.55, Pr = 0.71,
+    R_lambda = 10, R_cv = 2, |g| = 1e-5, Gr = 100 (the dense cavity's
+    parameters in three dimensions)."""
+    tau_f, Pr, rho_r, g, Gr = 0.55, 0.71, 1.5, 1e-5, 100.0
+    nu = viscosity(tau_f)
+    d = domain3(L, L, L, tau_f=tau_f, lambda_f=nu / Pr, R_lambda=10.0,
+                R_cv=2.0, gravity=(0.0, 0.0, -g),
+                beta=beta_from_grashof(Gr, g, 1.0, D, nu), T_ref=1.0,
+                init_T=1.0, sigma_rule=1, **collision_params(rho_r, D / 2, g))
+    d = walls3(d, thermal="adiabatic")
+    rng = np.random.default_rng(seed)
+    R, gap, pts = D / 2, 2.0, []
+    lo = np.array([R + gap, R + gap, L / 2 + R + gap])
+    hi = np.array([L - R - gap, L - R - gap, L - R - gap])
+    while len(pts) < n:
+        p = rng.uniform(lo, hi)
+        if all(np.linalg.norm(p - q) >= D + gap for q in pts):
+            pts.append(p)
+    return d, [sphere(*p, R, rho_s=rho_r, T_init=0.0) for p in pts]
