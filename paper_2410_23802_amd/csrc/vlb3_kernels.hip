@@ -702,49 +702,60 @@ __global__ __launch_bounds__(kBlock) void k3_step(
   const int nxy = P.nx * P.ny, k = cc / nxy, j = (cc - k * nxy) / P.nx,
             i = cc - k * nxy - j * P.nx;
 
-  // pull streaming: every load is issued first (a population whose
-  // upstream cell lies beyond a wall loads the cell's own value, replaced
-  // below), then the wall rules fix those populations
+  // pull streaming.  A population whose upstream cell lies beyond a wall
+  // is read from the cell's own opposite population instead (halfway
+  // bounce-back), so that all 26 loads are independent and issued at once;
+  // the walls' velocity and temperature terms are added afterwards.  Where
+  // the upstream point lies beyond several walls the z wall decides, then
+  // the y wall.
+  const bool bxl = i == 0, bxh = i == P.nx - 1, byl = j == 0,
+             byh = j == P.ny - 1, bzl = k == 0, bzh = k == P.nz - 1;
   double fst[kQ], g[kQG];
-  unsigned long long wall_of = 0ull;   // 3 bits per population: face + 1
+  bool wz_[kQ], wy_[kQ], wx_[kQ];
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    int si = i - ex(q), sj = j - ey(q), sk = k - ez(q), wall = 0;
-    if (si < 0) { if (P.per[0]) si += P.nx; else wall = 1; }
-    else if (si >= P.nx) { if (P.per[0]) si -= P.nx; else wall = 2; }
-    if (sj < 0) { if (P.per[1]) sj += P.ny; else wall = 3; }
-    else if (sj >= P.ny) { if (P.per[1]) sj -= P.ny; else wall = 4; }
-    if (sk < 0) { if (P.per[2]) sk += P.nz; else wall = 5; }
-    else if (sk >= P.nz) { if (P.per[2]) sk -= P.nz; else wall = 6; }
-    const size_t src = wall ? (size_t)cc
-                            : ((size_t)sk * P.ny + sj) * P.nx + si;
-    fst[q] = fin[(size_t)q * P.N + src];
-    if (q < kQG) g[q] = gin[(size_t)q * P.N + src];
-    wall_of |= (unsigned long long)wall << (3 * q);
+    const int exq = ex(q), eyq = ey(q), ezq = ez(q);
+    const bool ox = exq > 0 ? bxl : exq < 0 ? bxh : false;
+    const bool oy = eyq > 0 ? byl : eyq < 0 ? byh : false;
+    const bool oz = ezq > 0 ? bzl : ezq < 0 ? bzh : false;
+    int off = -exq - eyq * P.nx - ezq * nxy;
+    off += ox && P.per[0] ? (exq > 0 ? P.nx : -P.nx) : 0;
+    off += oy && P.per[1] ? (eyq > 0 ? nxy : -nxy) : 0;
+    off += oz && P.per[2] ? (ezq > 0 ? P.N : -P.N) : 0;
+    wx_[q] = ox && !P.per[0];
+    wy_[q] = oy && !P.per[1];
+    wz_[q] = oz && !P.per[2];
+    const bool wall = wx_[q] || wy_[q] || wz_[q];
+    const size_t at = wall ? (size_t)opp(q) * P.N + cc
+                           : (size_t)q * P.N + (size_t)(cc + off);
+    fst[q] = fin[at];
+    if (q < kQG) g[q] = gin[at];
   }
   const double hold = hin[cc];
-  if (wall_of) {
+  if (bxl || bxh || byl || byh || bzl || bzh) {
 #pragma unroll
     for (int q = 1; q < kQ; ++q) {
-      const int wall = (int)((wall_of >> (3 * q)) & 7ull) - 1;
-      if (wall < 0) continue;
-      // the face's constants, selected without indexing the arguments
-      double uw[3] = {0.0, 0.0, 0.0}, Tw = 0.0;
-      int dir = 0;
-#pragma unroll
-      for (int face = 0; face < 6; ++face)
-        if (face == wall) {
-          uw[0] = P.u_wall[face][0];
-          uw[1] = P.u_wall[face][1];
-          uw[2] = P.u_wall[face][2];
-          Tw = P.T_wall[face];
-          dir = P.wall_dirichlet[face];
-        }
-      const double eu = ex(q) * uw[0] + ey(q) * uw[1] + ez(q) * uw[2];
-      fst[q] = fin[(size_t)opp(q) * P.N + cc] + 6.0 * wq(q) * P.rho0 * eu;
-      if (q < kQG)
-        g[q] = dir ? -gin[(size_t)opp(q) * P.N + cc] + 2.0 * kW1G * P.cref * Tw
-                   : gin[(size_t)opp(q) * P.N + cc];
+      const int exq = ex(q), eyq = ey(q), ezq = ez(q);
+      // the deciding face (its index is a constant for each branch)
+      double eu = 0.0;
+      if (wz_[q]) {
+        const int fz = ezq > 0 ? 4 : 5;
+        eu = exq * P.u_wall[fz][0] + eyq * P.u_wall[fz][1] + ezq * P.u_wall[fz][2];
+      } else if (wy_[q]) {
+        const int fy = eyq > 0 ? 2 : 3;
+        eu = exq * P.u_wall[fy][0] + eyq * P.u_wall[fy][1] + ezq * P.u_wall[fy][2];
+      } else if (wx_[q]) {
+        const int fx = exq > 0 ? 0 : 1;
+        eu = exq * P.u_wall[fx][0] + eyq * P.u_wall[fx][1] + ezq * P.u_wall[fx][2];
+      }
+      fst[q] += 6.0 * wq(q) * P.rho0 * eu;
+      if (q < kQG && (wx_[q] || wy_[q] || wz_[q])) {
+        // an axis direction: exactly one face
+        const int fc = exq > 0 ? 0 : exq < 0 ? 1 : eyq > 0 ? 2 : eyq < 0 ? 3
+                     : ezq > 0 ? 4 : 5;
+        if (P.wall_dirichlet[fc])
+          g[q] = -g[q] + 2.0 * kW1G * P.cref * P.T_wall[fc];
+      }
     }
   }
 
