@@ -265,6 +265,10 @@ def run_3d(vlb, steps, warmup):
                      "mlups": round(cells * steps / wall / 1e6, 1),
                      "ms_per_step": round(wall * 1e3 / steps, 4),
                      "k3_step_us": round(k_ms * 1e3, 2),
+                     # the sphere pass and the geometry passes (exact
+                     # sphere-cell volumes, FP64-bound)
+                     "rest_of_step_us": round(wall * 1e6 / steps - k_ms * 1e3,
+                                              2),
                      "achieved_GBs": round(gbs, 1),
                      "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
                      "bytes_per_cell": BYTES_PER_CELL3}

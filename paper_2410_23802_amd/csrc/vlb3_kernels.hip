@@ -614,23 +614,65 @@ __global__ __launch_bounds__(kBlock) void k3_geometry_a(
     int* __restrict__ gid, double* __restrict__ gw,
     unsigned long long* __restrict__ tmask, int* __restrict__ items,
     int* __restrict__ nitems, int max_items, int* flags) {
+  __shared__ double sp[4][kMaxSpheres];   // X, Y, Z, R of every sphere
   const unsigned long long mask = tile_candidates(P, S, C, blockIdx.x);
   if (threadIdx.x == 0) tmask[blockIdx.x] = mask;     // for the step and
   if (!mask) return;                                  // the sphere pass
-  const int c = blockIdx.x * kBlock + threadIdx.x;
-  if (c >= P.N) return;
+  const int t = threadIdx.x, lane = t & 63;
+  if (t < P.np) {
+    sp[0][t] = S[fX * P.np + t];
+    sp[1][t] = S[fY * P.np + t];
+    sp[2][t] = S[fZ * P.np + t];
+    sp[3][t] = C[cR * P.np + t];
+  }
+  __syncthreads();
+  const int c = blockIdx.x * kBlock + t;
   const int nxy = P.nx * P.ny;
-  const int k = c / nxy, j = (c - k * nxy) / P.nx, i = c - k * nxy - j * P.nx;
-  const double node[3] = {i + 0.5, j + 0.5, k + 0.5};
   const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
-  int cnt = 0, packed = 0;
+  // the wave's candidates: spheres meeting the box of its 64 cells (one
+  // sphere per lane), so that each cell tests only those
+  unsigned long long wmask;
+  {
+    const int c0 = min(c - lane, P.N - 1), c1 = min(c - lane + 63, P.N - 1);
+    const int k0 = c0 / nxy, k1 = c1 / nxy;
+    const int j0 = (c0 - k0 * nxy) / P.nx, j1 = (c1 - k1 * nxy) / P.nx;
+    int lo[3], hi[3];
+    lo[2] = k0; hi[2] = k1 + 1;
+    if (k0 == k1) {
+      lo[1] = j0; hi[1] = j1 + 1;
+      if (j0 == j1) { lo[0] = c0 - k0 * nxy - j0 * P.nx; hi[0] = c1 - k1 * nxy - j1 * P.nx + 1; }
+      else { lo[0] = 0; hi[0] = P.nx; }
+    } else {
+      lo[1] = 0; hi[1] = P.ny; lo[0] = 0; hi[0] = P.nx;
+    }
+    bool hit = false;
+    if (lane < P.np && ((mask >> lane) & 1ull)) {
+      double ss = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        double best = 1e300;
+        for (int sh = -1; sh <= 1; ++sh) {
+          if (sh != 0 && !P.per[a]) continue;
+          const double x = sp[a][lane] + sh * L[a];
+          best = fmin(best, fmax(0.0, fmax((double)lo[a] - x, x - (double)hi[a])));
+        }
+        ss += best * best;
+      }
+      hit = ss < sp[3][lane] * sp[3][lane];
+    }
+    wmask = __ballot(hit);
+  }
+  const bool act = c < P.N;
+  const int cc = act ? c : P.N - 1;
+  const int k = cc / nxy, j = (cc - k * nxy) / P.nx, i = cc - k * nxy - j * P.nx;
+  const double node[3] = {i + 0.5, j + 0.5, k + 0.5};
+  int cnt = 0, packed = 0, part = 0;   // part: bit s = slot s partly covered
   double w[kMaxK] = {0.0, 0.0, 0.0, 0.0};
-  for (unsigned long long m = mask; m; m &= m - 1) {   // ascending spheres
-    const int p = __ffsll((long long)m) - 1;
-    const double R = C[cR * P.np + p];
+  for (unsigned long long m = act ? wmask : 0ull; m; m &= m - 1) {
+    const int p = __ffsll((long long)m) - 1;          // ascending spheres
+    const double R = sp[3][p];
     double cp[3];
     for (int a = 0; a < 3; ++a)
-      cp[a] = near_copy(S[(fX + a) * P.np + p], node[a], L[a], P.per[a]);
+      cp[a] = near_copy(sp[a][p], node[a], L[a], P.per[a]);
     if (!in_band(cp[0], cp[1], cp[2], R, i, j, k)) continue;
     if (cnt >= P.kmax) {
       atomicOr(flags, kFlagOverlap);
@@ -639,17 +681,36 @@ __global__ __launch_bounds__(kBlock) void k3_geometry_a(
     packed |= p << (8 * cnt + 8);
     if (wholly_inside(cp[0], cp[1], cp[2], R, i, j, k)) {
 #pragma unroll
-      for (int s = 0; s < kMaxK; ++s)
-        if (s == cnt) w[s] = 1.0;
+      for (int s2 = 0; s2 < kMaxK; ++s2)
+        if (s2 == cnt) w[s2] = 1.0;
     } else {
-      const int at = atomicAdd(nitems, 1);
-      if (at < max_items) items[at] = c * kMaxK + cnt;
-      else atomicOr(flags, kFlagOverlap);    // cannot happen: room for all
+      part |= 1 << cnt;
     }
     ++cnt;
   }
+  // the wave's items: an exclusive prefix sum of the per-lane counts and
+  // one atomic per wave (one per item would queue at a single address)
+  const int mine = __popc(part);
+  int pre = mine;
 #pragma unroll
-  for (int s = 0; s < kMaxK; ++s) gw[(size_t)c * kMaxK + s] = w[s];
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(pre, o, 64);
+    if (lane >= o) pre += v;
+  }
+  const int total = __shfl(pre, 63, 64);
+  int base = 0;
+  if (lane == 0 && total > 0) base = atomicAdd(nitems, total);
+  base = __shfl(base, 0, 64);
+  int at = base + pre - mine;
+  for (int s2 = 0; s2 < kMaxK; ++s2)
+    if ((part >> s2) & 1) {
+      if (at < max_items) items[at] = c * kMaxK + s2;
+      else atomicOr(flags, kFlagOverlap);    // cannot happen: room for all
+      ++at;
+    }
+  if (!act) return;
+#pragma unroll
+  for (int s2 = 0; s2 < kMaxK; ++s2) gw[(size_t)c * kMaxK + s2] = w[s2];
   gid[c] = packed | cnt;
 }
 
