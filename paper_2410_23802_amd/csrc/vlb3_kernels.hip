@@ -194,20 +194,89 @@ __constant__ double gl_x[kGL], gl_w[kGL];
 // that each is at least its own length away; 16-point Gauss-Legendre on
 // every sub-interval.  Deterministic: about 140 area evaluations per cell,
 // 3e-15 from the exact volume in tests.
+//
+// The section is the disk of radius^2 r2 centred at the origin against the
+// unit square [x0, x0 + 1] x [y0, y0 + 1] (coordinates relative to the
+// centre), by Green's theorem over the square's edges taken
+// counter-clockwise: triangles from the centre to the parts of the edges
+// inside the circle, circular sectors for the parts outside.  An edge runs
+// from p along a unit axis d, so the circle meets it at
+// s = -p.d +- sqrt(r2 - h^2) (h the edge line's distance from the centre)
+// with no division, and the sectors' vectors follow from p, d and s.  Each
+// sector of angle arg(conj(u) v) enters as the complex factor u.v + i u x v
+// (rescaled by a power of two, exactly); with the centre outside the closed
+// square the net angle lies in (-pi, pi) and one atan2 of the product
+// gives it, otherwise (the square's column of cells) every sector takes
+// its own.
+struct SecAcc {
+  double tri, zr, zi, ang;
+};
+
+__device__ __forceinline__ void sec_factor(double cr, double ci, bool own,
+                                           SecAcc& a) {
+  if (cr == 0.0 && ci == 0.0) return;
+  if (own) {
+    a.ang += atan2(ci, cr);
+    return;
+  }
+  const double r = a.zr * cr - a.zi * ci, im = a.zr * ci + a.zi * cr;
+  int e;
+  (void)frexp(fmax(fabs(r), fabs(im)), &e);
+  a.zr = ldexp(r, -e);
+  a.zi = ldexp(im, -e);
+}
+
+// edge from p (|p|^2 = pp) along the unit axis d: b = p.d, hh = h^2 =
+// |p|^2 - b^2, cr = p x d
+__device__ __forceinline__ void sec_edge(double b, double hh, double cr,
+                                         double pp, double r2, bool own,
+                                         SecAcc& a) {
+  const double disc = r2 - hh;
+  double s1 = 1.0, s2 = 0.0;
+  if (disc > 0.0) {
+    const double w = sqrt(disc);
+    s1 = fmin(fmax(-b - w, 0.0), 1.0);
+    s2 = fmin(fmax(-b + w, 0.0), 1.0);
+  }
+  if (!(s1 < s2)) {              // the whole edge outside: p -> p + d
+    sec_factor(pp + b, cr, own, a);
+    return;
+  }
+  a.tri += 0.5 * (s2 - s1) * cr;
+  if (s1 > 0.0) sec_factor(pp + s1 * b, s1 * cr, own, a);
+  if (s2 < 1.0) sec_factor(pp + (1.0 + s2) * b + s2, (1.0 - s2) * cr, own, a);
+}
+
+__device__ __forceinline__ double unit_square_section(double x0, double y0,
+                                                      double r2) {
+  const double x1 = x0 + 1.0, y1 = y0 + 1.0;
+  const bool own = x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0;
+  const double xx0 = x0 * x0, xx1 = x1 * x1, yy0 = y0 * y0, yy1 = y1 * y1;
+  SecAcc a = {0.0, 1.0, 0.0, 0.0};
+  sec_edge(x0, yy0, -y0, xx0 + yy0, r2, own, a);    // bottom, +x
+  sec_edge(y0, xx1, x1, xx1 + yy0, r2, own, a);     // right, +y
+  sec_edge(-x1, yy1, y1, xx1 + yy1, r2, own, a);    // top, -x
+  sec_edge(-y1, xx0, -x0, xx0 + yy1, r2, own, a);   // left, -y
+  const double ang = own ? a.ang : atan2(a.zi, a.zr);
+  return fmin(fmax(a.tri + 0.5 * r2 * ang, 0.0), 1.0);
+}
+
 __device__ __forceinline__ double section_area(double X, double Y, double R,
                                                int i, int j, double z) {
   const double r2 = (R - z) * (R + z);
-  return r2 > 0.0 ? vlb::covered_share(X, Y, sqrt(r2), i, j) : 0.0;
+  return r2 > 0.0 ? unit_square_section((double)i - X, (double)j - Y, r2)
+                  : 0.0;
 }
 
 // one Gauss-Legendre sub-interval [p, q] (nodes g0, g0 + gs, ... of the
-// rule); sp / sq: p / q is a singular end
+// rule; ONE: the node g0 only); sp / sq: p / q is a singular end
+template <bool ONE>
 __device__ __forceinline__ double gl_piece(double X, double Y, double R, int i,
                                            int j, double p, double q, bool sp,
                                            bool sq, int g0, int gs) {
   const double L = q - p;
   double sum = 0.0;
-  for (int g = g0; g < kGL; g += gs) {
+  for (int g = g0; g < (ONE ? g0 + 1 : kGL); g += gs) {
     const double t = gl_x[g];
     double z, dz;
     if (sp && sq) {
@@ -230,86 +299,94 @@ __device__ __forceinline__ double gl_piece(double X, double Y, double R, int i,
 }
 
 // The nodes g0, g0 + gs, ... of every sub-interval's rule (all of them for
-// gs = 1; a group of gs lanes splits them and adds its parts).
+// gs = 1; a group of gs lanes splits them and adds its parts; ONE: gs is
+// the rule's size, one node per lane).  The
+// sub-intervals are walked by one flat loop with a single quadrature call
+// site: a wave whose lane groups hold different cells then spends one
+// evaluation per lane and iteration whatever phase each group is in, and
+// the area code is emitted once.
+template <bool ONE>
 __device__ __forceinline__ double volume_nodes(double X, double Y, double Z,
                                                double R, int i, int j, int k,
                                                int g0, int gs) {
   constexpr double kNone = 1e300;
   const double a0 = (double)i - X, a1 = a0 + 1.0;
   const double b0 = (double)j - Y, b1 = b0 + 1.0;
-  const double lo = fmax((double)k - Z, -R), hi = fmin((double)(k + 1) - Z, R);
+  const double zlo = (double)k - Z, zhi = (double)(k + 1) - Z;
+  const double lo = fmax(zlo, -R), hi = fmin(zhi, R);
   if (!(lo < hi)) return 0.0;
-  // the points where the area is not analytic (absent ones: kNone); the
-  // arrays are fixed-size and fully unrolled, so they stay in registers
+  // the points where the area is not analytic are +-zp[m] (absent ones:
+  // zp = kNone); fixed-size and fully unrolled, so they stay in registers
   const double d2[8] = {a0 * a0, a1 * a1, b0 * b0, b1 * b1,
                         a0 * a0 + b0 * b0, a0 * a0 + b1 * b1,
                         a1 * a1 + b0 * b0, a1 * a1 + b1 * b1};
-  double zs[18];
-  zs[0] = R;
-  zs[1] = -R;
+  double zp[9];
+  zp[0] = R;
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const bool in = d2[m] < R * R;
-    const double zb = in ? sqrt(R * R - d2[m]) : kNone;
-    zs[2 + 2 * m] = zb;
-    zs[3 + 2 * m] = in ? -zb : kNone;
-  }
-  // breakpoints: lo, hi and the z* between them, sorted by a fixed
-  // compare-exchange network (absent ones sort to the end)
-  double bp[20];
-  bp[0] = lo;
-  bp[1] = hi;
+  for (int m = 0; m < 8; ++m)
+    zp[m + 1] = d2[m] < R * R ? sqrt(R * R - d2[m]) : kNone;
+  // the nearest singular point above / below x (kNone / -kNone: none)
+  auto above = [&](double x) {
+    double r = kNone;
 #pragma unroll
-  for (int m = 0; m < 18; ++m)
-    bp[2 + m] = zs[m] > lo && zs[m] < hi ? zs[m] : kNone;
-#pragma unroll
-  for (int a = 0; a < 19; ++a)
-#pragma unroll
-    for (int b = 0; b < 19 - a; ++b) {
-      const double x = bp[b], y = bp[b + 1];
-      bp[b] = fmin(x, y);
-      bp[b + 1] = fmax(x, y);
+    for (int m = 0; m < 9; ++m) {
+      if (zp[m] > x) r = fmin(r, zp[m]);
+      if (-zp[m] > x) r = fmin(r, -zp[m]);
     }
-  double V = 0.0;
-  for (int m = 0; m < 19; ++m) {        // pieces [bp[0], bp[1]], shifting
-    const double u = bp[0], v = bp[1], L = v - u;
+    return r;
+  };
+  auto below = [&](double x) {
+    double r = -kNone;
 #pragma unroll
-    for (int e = 0; e < 19; ++e) bp[e] = bp[e + 1];
-    bp[19] = kNone;
-    if (!(v < kNone)) break;
-    if (!(u < v)) continue;
-    // the nearest z* beyond each end, if closer than half the piece
-    double db = kNone, da = kNone;
-#pragma unroll
-    for (int e = 0; e < 18; ++e) {
-      if (zs[e] < u) db = fmin(db, u - zs[e]);
-      if (zs[e] > v && zs[e] < kNone) da = fmin(da, zs[e] - v);
+    for (int m = 0; m < 9; ++m) {
+      if (zp[m] < x) r = fmax(r, zp[m]);
+      if (-zp[m] < x) r = fmax(r, -zp[m]);
     }
-    // The ends of the piece are singular where they are z* (not a face);
-    // a z* within 1e-9 of the piece's length from an end counts as at it
-    // (the substitution then meets it; grading would take ~30 halvings).
-    bool su = u != (double)k - Z, sv = v != (double)(k + 1) - Z;
-    if (db <= 1e-9 * L) su = true;
-    if (da <= 1e-9 * L) sv = true;
-    double cur = u;
-    bool cur_sing = su;
-    if (db > 1e-9 * L && db < 0.5 * L)      // graded towards u
-      for (double s = db; s < 0.5 * L; s = 2.0 * s + db) {
-        V += gl_piece(X, Y, R, i, j, cur, u + s, cur_sing, false, g0, gs);
-        cur = u + s;
-        cur_sing = false;
-      }
-    if (da > 1e-9 * L && da < 0.5 * L) {    // graded towards v
-      int K = 0;
-      for (double s = da; s < 0.5 * L; s = 2.0 * s + da) ++K;
-      for (int kk = K; kk >= 1; --kk) {
-        const double s = da * (exp2((double)kk) - 1.0);
-        V += gl_piece(X, Y, R, i, j, cur, v - s, cur_sing, false, g0, gs);
-        cur = v - s;
-        cur_sing = false;
-      }
+    return r;
+  };
+  // Pieces [u, v] run between consecutive breakpoints (lo, hi and the
+  // singular points between them).  On a piece: sub-intervals graded
+  // towards u (phase 0), then towards v (phase 1), then the last one
+  // (phase 2); phase 3 starts the next piece.
+  double V = 0.0, u = lo, v = lo, L = 0.0, db = 0.0, da = 0.0, s = 0.0;
+  double cur = lo;
+  bool cur_sing = false, sv = false;
+  int ph = 3, kk = 0;
+  for (;;) {
+    if (ph == 3) {
+      u = v;
+      if (!(u < hi)) break;
+      v = fmin(hi, above(u));
+      L = v - u;
+      db = u - below(u);
+      da = above(v) - v;
+      // The ends of the piece are singular where they are singular points
+      // (not a face); one within 1e-9 of the piece's length from an end
+      // counts as at it (the substitution then meets it; grading would
+      // take ~30 halvings).
+      cur_sing = u != zlo || db <= 1e-9 * L;
+      sv = v != zhi || da <= 1e-9 * L;
+      cur = u;
+      kk = 0;
+      if (da > 1e-9 * L && da < 0.5 * L)
+        for (double t = da; t < 0.5 * L; t = 2.0 * t + da) ++kk;
+      s = db;
+      ph = db > 1e-9 * L && db < 0.5 * L ? 0 : kk > 0 ? 1 : 2;
     }
-    V += gl_piece(X, Y, R, i, j, cur, v, cur_sing, sv, g0, gs);
+    const double q = ph == 0   ? u + s
+                     : ph == 1 ? v - da * (exp2((double)kk) - 1.0)
+                               : v;
+    V += gl_piece<ONE>(X, Y, R, i, j, cur, q, cur_sing, ph == 2 && sv, g0, gs);
+    cur = q;
+    cur_sing = false;
+    if (ph == 0) {
+      s = 2.0 * s + db;
+      if (!(s < 0.5 * L)) ph = kk > 0 ? 1 : 2;
+    } else if (ph == 1) {
+      if (--kk < 1) ph = 2;
+    } else {
+      ph = 3;
+    }
   }
   return V;
 }
@@ -317,7 +394,7 @@ __device__ __forceinline__ double volume_nodes(double X, double Y, double Z,
 __device__ __forceinline__ double sphere_cell_volume(double X, double Y,
                                                      double Z, double R, int i,
                                                      int j, int k) {
-  return fmin(fmax(volume_nodes(X, Y, Z, R, i, j, k, 0, 1), 0.0), 1.0);
+  return fmin(fmax(volume_nodes<false>(X, Y, Z, R, i, j, k, 0, 1), 0.0), 1.0);
 }
 
 // The box of a tile (cells b*256 .. b*256+255), as cell-coordinate
@@ -714,7 +791,7 @@ __global__ __launch_bounds__(kBlock) void k3_geometry_a(
   gid[c] = packed | cnt;
 }
 
-__global__ __launch_bounds__(kBlock) void k3_geometry_b(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k3_geometry_b(
     const Params3 P, const double* __restrict__ S, const double* __restrict__ C,
     const int* __restrict__ gid, double* __restrict__ gw,
     const int* __restrict__ items, const int* __restrict__ nitems) {
@@ -733,7 +810,7 @@ __global__ __launch_bounds__(kBlock) void k3_geometry_b(
     double cp[3];
     for (int a = 0; a < 3; ++a)
       cp[a] = near_copy(S[(fX + a) * P.np + p], node[a], L[a], P.per[a]);
-    double v = volume_nodes(cp[0], cp[1], cp[2], C[cR * P.np + p], i, j, k, r,
+    double v = volume_nodes<true>(cp[0], cp[1], cp[2], C[cR * P.np + p], i, j, k, r,
                             kGroup);
 #pragma unroll
     for (int o = kGroup / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, kGroup);

@@ -153,6 +153,15 @@ static vlb_status validate(const vlb_domain_desc* d, std::string& why) {
 // bytes in flight (16 M-cell channel: 344 -> 288 us).  Below that size, and
 // in the list form (a particle tile would share its block), one tile per
 // block is faster (channel of 0.8 M cells: 17.6 vs 18.1 us).
+//
+// The list form stores the populations past the caches (non-temporal)
+// where one step moves more than 320 MB, 1.25 x the Infinity Cache: the
+// next step cannot find them there anyway, and L2 is left to the rows the
+// scattered tiles pull from their neighbours (dense cavity: FP64 k_step
+// 154.7 -> 150.6 us, FP32 89.0 -> 85.8 us).  Where the step fits the cache
+// such stores cost a third more (0.8 M-cell channel, FP64 37 -> 49 us),
+// and on the 16 M-cell channel (scan form, tiles in order) they gain
+// nothing.
 static void set_stream_groups(Params& P, bool list_form, int prec) {
   int g = list_form ? 1 : (P.nblocks + 7) / 8;
   if (g < 1) g = 1;
@@ -172,6 +181,10 @@ static void set_stream_groups(Params& P, bool list_form, int prec) {
   const bool b16 = prec == VLB_FP16_SHIFT || prec == VLB_BF16_SHIFT;
   const size_t step_bytes = (size_t)P.N * (2 * 9 * 2 + 2 * 4);
   P.pair_tiles = b16 && !list_form && step_bytes > ((size_t)256 << 20);
+  const size_t elem = prec == VLB_FP64 ? 8 : prec == VLB_FP32 ? 4 : 2;
+  const size_t hbytes = prec == VLB_FP64 ? 8 : 4;
+  const size_t moved = (size_t)P.N * (2 * 18 * elem + 2 * hbytes);
+  P.nt_stores = list_form && moved > ((size_t)320 << 20);
 }
 
 static void derive_params(vlb_ctx* c) {

@@ -56,6 +56,9 @@ struct Prec<VLB_FP64> {
   static __device__ __forceinline__ C cv(S v) { return v; }
   static __device__ __forceinline__ C ld(const S* p, size_t i) { return p[i]; }
   static __device__ __forceinline__ void st(S* p, size_t i, C v) { p[i] = v; }
+  static __device__ __forceinline__ void stn(S* p, size_t i, C v) {
+    __builtin_nontemporal_store(v, p + i);
+  }
 };
 
 template <>
@@ -66,6 +69,9 @@ struct Prec<VLB_FP32> {
   static __device__ __forceinline__ C cv(S v) { return v; }
   static __device__ __forceinline__ C ld(const S* p, size_t i) { return p[i]; }
   static __device__ __forceinline__ void st(S* p, size_t i, C v) { p[i] = v; }
+  static __device__ __forceinline__ void stn(S* p, size_t i, C v) {
+    __builtin_nontemporal_store(v, p + i);
+  }
 };
 
 template <>
@@ -79,6 +85,9 @@ struct Prec<VLB_FP16_SHIFT> {
   }
   static __device__ __forceinline__ void st(S* p, size_t i, C v) {
     p[i] = (_Float16)v;
+  }
+  static __device__ __forceinline__ void stn(S* p, size_t i, C v) {
+    __builtin_nontemporal_store((_Float16)v, p + i);
   }
 };
 
@@ -98,6 +107,11 @@ struct Prec<VLB_BF16_SHIFT> {
     uint32_t b = __float_as_uint(v);
     b += 0x7fffu + ((b >> 16) & 1u);
     p[i] = (uint16_t)(b >> 16);
+  }
+  static __device__ __forceinline__ void stn(S* p, size_t i, C v) {
+    uint32_t b = __float_as_uint(v);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    __builtin_nontemporal_store((uint16_t)(b >> 16), p + i);
   }
 };
 
@@ -1395,8 +1409,13 @@ __device__ __forceinline__ void update_cell(
     C o[9];
     inverse(mb, o);
     if (act) {
+      if (P.nt_stores) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) T::st(fout, (size_t)q * plane + cc, o[q]);
+        for (int q = 0; q < 9; ++q) T::stn(fout, (size_t)q * plane + cc, o[q]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) T::st(fout, (size_t)q * plane + cc, o[q]);
+      }
     }
   }
 
@@ -1421,9 +1440,15 @@ __device__ __forceinline__ void update_cell(
     C o[9];
     inverse(nb, o);
     if (act) {
+      if (P.nt_stores) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) T::st(gout, (size_t)q * plane + cc, o[q]);
-      hout[cc] = hnew;
+        for (int q = 0; q < 9; ++q) T::stn(gout, (size_t)q * plane + cc, o[q]);
+        __builtin_nontemporal_store(hnew, hout + cc);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) T::st(gout, (size_t)q * plane + cc, o[q]);
+        hout[cc] = hnew;
+      }
     }
   }
 

@@ -61,6 +61,8 @@ struct Params {
                       // (0: the XCD groups)
   int pair_tiles;     // step kernel, 16-bit forms: two plain tiles per
                       // streaming block (never in the list form)
+  int nt_stores;      // step kernel and probe: populations and carrier
+                      // stored non-temporally
   int ellipses;       // some particle is an ellipse (its kernels carry the
                       // ellipse geometry; no paired tiles)
 };

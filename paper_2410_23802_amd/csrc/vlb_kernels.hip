@@ -599,12 +599,21 @@ __global__ __launch_bounds__(kBlock) void k_stream_probe(
     g[q] = gin[(size_t)q * plane + src[q]];
   }
   const typename Prec<PREC>::H h = hin[c];
+  if (P.nt_stores) {     // as the step kernel stores them
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    fout[(size_t)q * plane + c] = f[q];
-    gout[(size_t)q * plane + c] = g[q];
+    for (int q = 0; q < 9; ++q) {
+      __builtin_nontemporal_store(f[q], fout + (size_t)q * plane + c);
+      __builtin_nontemporal_store(g[q], gout + (size_t)q * plane + c);
+    }
+    __builtin_nontemporal_store(h, hout + c);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      fout[(size_t)q * plane + c] = f[q];
+      gout[(size_t)q * plane + c] = g[q];
+    }
+    hout[c] = h;
   }
-  hout[c] = h;
 }
 
 // Populations of the current state as FP64 (unshifted).

@@ -636,6 +636,7 @@ class Domain3:
         self.shape = (int(d["nz"]), int(d["ny"]), int(d["nx"]))
         desc = make_domain3_desc(d)
         arr = make_spheres(self.spheres)
+        self._destroy = lib().vlb3_destroy    # see Domain.__init__
         h = ctypes.c_void_p()
         _check3(lib().vlb3_create(ctypes.byref(desc), len(self.spheres), arr,
                                   _stream_handle(stream), ctypes.byref(h)),
@@ -643,8 +644,8 @@ class Domain3:
         self.h = h
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().vlb3_destroy(self.h)
+        if getattr(self, "h", None) is not None and self.h.value:
+            self._destroy(self.h)
             self.h = None
 
     __del__ = close
