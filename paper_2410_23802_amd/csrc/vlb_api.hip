@@ -154,14 +154,14 @@ static vlb_status validate(const vlb_domain_desc* d, std::string& why) {
 // in the list form (a particle tile would share its block), one tile per
 // block is faster (channel of 0.8 M cells: 17.6 vs 18.1 us).
 //
-// The list form stores the populations past the caches (non-temporal)
-// where one step moves more than 320 MB, 1.25 x the Infinity Cache: the
-// next step cannot find them there anyway, and L2 is left to the rows the
-// scattered tiles pull from their neighbours (dense cavity: FP64 k_step
-// 154.7 -> 150.6 us, FP32 89.0 -> 85.8 us).  Where the step fits the cache
-// such stores cost a third more (0.8 M-cell channel, FP64 37 -> 49 us),
-// and on the 16 M-cell channel (scan form, tiles in order) they gain
-// nothing.
+// The list form in FP64 and FP32 stores the populations past the caches
+// (non-temporal) where one step moves more than 320 MB, 1.25 x the
+// Infinity Cache: the next step cannot find them there anyway, and L2 is
+// left to the rows the scattered tiles pull from their neighbours (dense
+// cavity: FP64 k_step 154.7 -> 150.6 us, FP32 89.0 -> 85.8 us; its 16-bit
+// forms, 189 MB a step, lost 4 %).  Where the step fits the cache such
+// stores cost a third more (0.8 M-cell channel, FP64 37 -> 49 us), and on
+// the 16 M-cell channel (scan form, tiles in order) they gain nothing.
 static void set_stream_groups(Params& P, bool list_form, int prec) {
   int g = list_form ? 1 : (P.nblocks + 7) / 8;
   if (g < 1) g = 1;
@@ -181,10 +181,10 @@ static void set_stream_groups(Params& P, bool list_form, int prec) {
   const bool b16 = prec == VLB_FP16_SHIFT || prec == VLB_BF16_SHIFT;
   const size_t step_bytes = (size_t)P.N * (2 * 9 * 2 + 2 * 4);
   P.pair_tiles = b16 && !list_form && step_bytes > ((size_t)256 << 20);
-  const size_t elem = prec == VLB_FP64 ? 8 : prec == VLB_FP32 ? 4 : 2;
-  const size_t hbytes = prec == VLB_FP64 ? 8 : 4;
-  const size_t moved = (size_t)P.N * (2 * 18 * elem + 2 * hbytes);
-  P.nt_stores = list_form && moved > ((size_t)320 << 20);
+  const bool wide = prec == VLB_FP64 || prec == VLB_FP32;
+  const size_t elem = prec == VLB_FP64 ? 8 : 4;
+  const size_t moved = (size_t)P.N * (2 * 18 * elem + 2 * elem);
+  P.nt_stores = wide && list_form && moved > ((size_t)320 << 20);
 }
 
 static void derive_params(vlb_ctx* c) {
@@ -419,7 +419,10 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
   for (int k = 0; k < n; ++k)
     if (p[k].radius_minor > 0.0 && p[k].radius_minor < p[k].radius)
       c->P.ellipses = 1;
-  if (c->P.ellipses) c->P.pair_tiles = 0;
+  if (c->P.ellipses) {
+    c->P.pair_tiles = 0;
+    c->P.nt_stores = 0;
+  }
   const size_t part_slots =
       c->P.scan ? (size_t)n * c->P.nblocks : (size_t)n * c->maxb;
   c->initialized = false;

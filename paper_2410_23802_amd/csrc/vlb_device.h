@@ -1267,7 +1267,7 @@ __device__ __forceinline__ void load_cell(
 // equal the literal forms to rounding; in the 32- and 16-bit forms they
 // keep the per-step rounding from acting as a small systematic force or
 // heat source.
-template <int PREC, bool OUT, class PartFn>
+template <int PREC, bool OUT, bool NT, class PartFn>
 __device__ __forceinline__ void update_cell(
     const Params& P, const Hot<typename Prec<PREC>::C>& H,
     const CellLoad<PREC>& L, typename Prec<PREC>::S* __restrict__ fout,
@@ -1409,7 +1409,7 @@ __device__ __forceinline__ void update_cell(
     C o[9];
     inverse(mb, o);
     if (act) {
-      if (P.nt_stores) {
+      if constexpr (NT) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) T::stn(fout, (size_t)q * plane + cc, o[q]);
       } else {
@@ -1440,7 +1440,7 @@ __device__ __forceinline__ void update_cell(
     C o[9];
     inverse(nb, o);
     if (act) {
-      if (P.nt_stores) {
+      if constexpr (NT) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) T::stn(gout, (size_t)q * plane + cc, o[q]);
         __builtin_nontemporal_store(hnew, hout + cc);
@@ -1468,7 +1468,8 @@ __device__ __forceinline__ void update_cell(
 // that its work overlaps them; a true result, which must be uniform over
 // the wave, abandons the tile: the return value is then false), and part()
 // as update_cell describes.
-template <int PREC, bool OUT, class PreFn, class GatherFn, class PartFn>
+template <int PREC, bool OUT, bool NT, class PreFn, class GatherFn,
+          class PartFn>
 __device__ __forceinline__ bool lattice_tile(
     const Params& P, const Hot<typename Prec<PREC>::C>& H,
     const typename Prec<PREC>::S* __restrict__ fin,
@@ -1483,8 +1484,8 @@ __device__ __forceinline__ bool lattice_tile(
   pre();
   load_cell<PREC>(P, fin, gin, hin, plane, tile, L);
   if (gather()) return false;
-  update_cell<PREC, OUT>(P, H, L, fout, gout, hout, plane, macro, flags,
-                         part);
+  update_cell<PREC, OUT, NT>(P, H, L, fout, gout, hout, plane, macro, flags,
+                             part);
   return true;
 }
 
@@ -1616,7 +1617,7 @@ __device__ __forceinline__ unsigned long long wave_particle_mask(
 // (a batch) they test them, one particle per lane.  List form: each tile
 // in the role its block count gives.
 template <int PREC, bool OUT, bool SCAN, bool COUNTED = false,
-          bool ELL = false>
+          bool ELL = false, bool NT = false>
 __device__ __forceinline__ void step_task(
     const Params& P, const Hot<typename Prec<PREC>::C>& H, const StepBufs& B,
     int have, int tile, bool ptile, TileShared<typename Prec<PREC>::C>& sh,
@@ -1844,8 +1845,9 @@ __device__ __forceinline__ void step_task(
       sh.M[0][t] = drho; sh.M[1][t] = jxs; sh.M[2][t] = jys;
     }
   };
-  if (!lattice_tile<PREC, OUT>(P, H, fin, fout, gin, gout, hin, hout, plane,
-                               tile, macro, flags, pre, gather, part))
+  if (!lattice_tile<PREC, OUT, NT>(P, H, fin, fout, gin, gout, hin, hout,
+                                   plane, tile, macro, flags, pre, gather,
+                                   part))
     return;
   if (!ptile) return;
 
@@ -2000,11 +2002,11 @@ __device__ __forceinline__ void pair_task(
   }
   auto none = [](bool, int, int, C, C, C, PSums<C>&) {};
   if (!skipA)
-    update_cell<PREC, OUT>(P, H, a, fout, gout, hout, plane, macro, flags,
-                           none);
+    update_cell<PREC, OUT, false>(P, H, a, fout, gout, hout, plane, macro,
+                                  flags, none);
   if (!skipB)
-    update_cell<PREC, OUT>(P, H, b, fout, gout, hout, plane, macro, flags,
-                           none);
+    update_cell<PREC, OUT, false>(P, H, b, fout, gout, hout, plane, macro,
+                                  flags, none);
 }
 
 static inline unsigned blocks_for(long n, int per) {

@@ -14,7 +14,9 @@ namespace vlb {
 // (and the LDS of a particle tile caps a CU at 7 blocks).  PAIR (16-bit
 // forms, where the host sets pair_tiles): the streaming blocks take two
 // tiles each; a kernel of its own, so that the one-tile path keeps its code.
-template <int PREC, bool OUT, bool SCAN, bool PAIR, bool ELL>
+// NT: the populations and the carrier are stored non-temporally (list form,
+// where the host sets nt_stores).
+template <int PREC, bool OUT, bool SCAN, bool PAIR, bool ELL, bool NT>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 5))) void k_step(
     const Params P, const Hot<typename Prec<PREC>::C> H, const StepBufs B,
@@ -53,7 +55,7 @@ __attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 5))) void k_step(
     lcnt = B.L.cnt[tile];                                // uniform
     ptile = lcnt != 0;
   }
-  step_task<PREC, OUT, SCAN, SCAN && counted_tiles(PREC, PAIR), ELL>(
+  step_task<PREC, OUT, SCAN, SCAN && counted_tiles(PREC, PAIR), ELL, NT>(
       P, H, B, have, tile, ptile, sh, lcnt, lent);
 }
 
@@ -644,7 +646,7 @@ hipError_t launch_particles(const Params& P, PState cur, PState next,
   return hipGetLastError();
 }
 
-template <int PREC, bool OUT, bool SCAN, bool PAIR, bool ELL>
+template <int PREC, bool OUT, bool SCAN, bool PAIR, bool ELL, bool NT>
 static hipError_t step_t(const StepLaunch& a, hipStream_t s) {
   const Params& P = *a.P;
   // the host keeps the tile counts exactly where this kernel reads them
@@ -653,19 +655,28 @@ static hipError_t step_t(const StepLaunch& a, hipStream_t s) {
     return hipErrorInvalidValue;
   const Hot<typename Prec<PREC>::C> H = make_hot<typename Prec<PREC>::C>(P);
   const unsigned grid = (unsigned)(P.nfirst + stream_grid(P, PAIR));
-  hipExtLaunchKernelGGL((k_step<PREC, OUT, SCAN, PAIR, ELL>), dim3(grid),
+  hipExtLaunchKernelGGL((k_step<PREC, OUT, SCAN, PAIR, ELL, NT>), dim3(grid),
                         dim3(kBlock), 0, s, a.ev_start, a.ev_stop, 0, P, H,
                         a.B, a.have);
   return hipGetLastError();
 }
 
+// the list form's non-temporal stores: FP64 and FP32 disk domains only
+template <int PREC>
+constexpr bool kNtStores = PREC == VLB_FP64 || PREC == VLB_FP32;
+
 template <int PREC, bool PAIR, bool ELL>
 static hipError_t step_q(const StepLaunch& a, hipStream_t s) {
   if (a.P->scan)
-    return a.out ? step_t<PREC, true, true, PAIR, ELL>(a, s)
-                 : step_t<PREC, false, true, PAIR, ELL>(a, s);
-  return a.out ? step_t<PREC, true, false, PAIR, ELL>(a, s)
-               : step_t<PREC, false, false, PAIR, ELL>(a, s);
+    return a.out ? step_t<PREC, true, true, PAIR, ELL, false>(a, s)
+                 : step_t<PREC, false, true, PAIR, ELL, false>(a, s);
+  if constexpr (kNtStores<PREC> && !PAIR && !ELL)
+    if (a.P->nt_stores)
+      return a.out ? step_t<PREC, true, false, false, false, true>(a, s)
+                   : step_t<PREC, false, false, false, false, true>(a, s);
+  if (a.P->nt_stores) return hipErrorInvalidValue;
+  return a.out ? step_t<PREC, true, false, PAIR, ELL, false>(a, s)
+               : step_t<PREC, false, false, PAIR, ELL, false>(a, s);
 }
 
 // A domain holding ellipses runs the step kernel built with their geometry
