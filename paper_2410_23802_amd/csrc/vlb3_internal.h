@@ -37,6 +37,7 @@ struct Params3 {
   double body[3], grav[3], beta, T_ref;
   double zeta, k_pp, k_pw;
   double init_u[3], init_T;
+  int nt_stores;              // the step stores past the caches
 };
 
 // Per (sphere, tile) partial sums of sum f_s,p (f^eq - f*) e (3) and of its
