@@ -215,8 +215,9 @@ vlb_status vlb3_create(const vlb3_domain_desc* desc, int32_t nspheres,
          hipMalloc((void**)&c->tmask, (size_t)P.nblocks *
                                           sizeof(unsigned long long)) ==
              hipSuccess &&
-         hipMalloc((void**)&c->items, N * kMaxK * sizeof(int)) == hipSuccess &&
-         hipMalloc((void**)&c->nitems, sizeof(int)) == hipSuccess;
+         hipMalloc((void**)&c->items, kSegs * seg_items(P) * sizeof(int)) ==
+             hipSuccess &&
+         hipMalloc((void**)&c->nitems, kSegs * sizeof(int)) == hipSuccess;
   if (ok && hipMalloc((void**)&c->flags, sizeof(int)) != hipSuccess) ok = false;
   if (!ok) return give_up(VLB_ENOMEM, "device allocation failed");
   // sphere constants and the initial state
@@ -280,8 +281,7 @@ vlb_status vlb3_step(vlb3_ctx* c, int64_t nsteps) {
                              c->partial, c->tmask, c->have, 1, c->stream));
     if (P.np > 0) c->scur ^= 1;
     HIP3(c, launch_geometry(P, c->S[c->scur], c->C, c->gid, c->gw, c->tmask,
-                            c->items, c->nitems, P.N * kMaxK, c->flags,
-                            c->stream));
+                            c->items, c->nitems, c->flags, c->stream));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
       HIP3(c, hipEventCreate(&e0));

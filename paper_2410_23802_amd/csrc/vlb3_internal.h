@@ -56,12 +56,17 @@ hipError_t launch_particles(const Params3& P, double* cur, double* nxt,
                             int update, hipStream_t s);
 // the spheres' shares of the cells of the tiles they may reach (gid: count
 // and ids packed, gw: kMaxK shares per cell) and each tile's candidate mask
-// (items, nitems: the list of partly covered cell slots, room for
-// max_items = N * kMaxK)
+// (items, nitems: the lists of partly covered cell slots, kSegs of them,
+// segment k at items + k * seg_items(P) for the tiles b with b mod kSegs =
+// k, its length in nitems[k])
+constexpr int kSegs = 8;
+__host__ __device__ inline size_t seg_items(const Params3& P) {
+  return (size_t)((P.nblocks + kSegs - 1) / kSegs) * kBlock * kMaxK;
+}
 hipError_t launch_geometry(const Params3& P, const double* S,
                            const double* C, int* gid, double* gw,
                            unsigned long long* tmask, int* items, int* nitems,
-                           int max_items, int* flags, hipStream_t s);
+                           int* flags, hipStream_t s);
 hipError_t launch_step(const Params3& P, bool out, const double* fin,
                        double* fout, const double* gin, double* gout,
                        const double* hin, double* hout, const double* S,

@@ -599,19 +599,59 @@ __global__ __launch_bounds__(kBlock) void k3_particles(
     const double* __restrict__ C, const double* __restrict__ partial,
     const unsigned long long* __restrict__ tmask, int have, int update) {
   __shared__ double red[kBlock / 64][kPartial];
+  __shared__ double sp[4][kMaxSpheres];   // positions and radii, step n
   const int p = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int np = P.np;
+  if (t < np) {
+    for (int a = 0; a < 3; ++a) sp[a][t] = cur[(fX + a) * np + t];
+    sp[3][t] = C[cR * np + t];
+  }
   double acc[kPartial] = {0, 0, 0, 0, 0, 0};
-  if (have)   // the tiles whose candidates included the sphere
-    for (int b = t; b < P.nblocks; b += kBlock)
-      if ((tmask[b] >> p) & 1ull)
-        for (int v = 0; v < kPartial; ++v)
-          acc[v] += partial[((size_t)p * P.nblocks + b) * kPartial + v];
+  if (have) {   // the tiles whose candidates included the sphere
+    // the masks of kBatch tiles are loaded together, then the partials of
+    // the hits (one dependent round trip per batch, not per tile)
+    constexpr int kBatch = 8;
+    for (int b0 = t; b0 < P.nblocks; b0 += kBatch * kBlock) {
+      unsigned long long m[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int b = b0 + u * kBlock;
+        m[u] = b < P.nblocks ? tmask[b] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u)
+        if ((m[u] >> p) & 1ull) {
+          const int b = b0 + u * kBlock;
+          for (int v = 0; v < kPartial; ++v)
+            acc[v] += partial[((size_t)p * P.nblocks + b) * kPartial + v];
+        }
+    }
+  }
   for (int v = 0; v < kPartial; ++v) {
     const double s = wave_sum(acc[v]);
     if (lane == 0) red[wv][v] = s;
   }
   __syncthreads();
+  if (wv != 0) return;
+  // repulsion (positions at n) from the other spheres, one per lane
+  double Fr[3] = {0.0, 0.0, 0.0};
+  if (update && P.zeta > 0.0) {
+    const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+    const double Xp[3] = {sp[0][p], sp[1][p], sp[2][p]};
+    if (lane < np && lane != p) {
+      double r[3], d2 = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        r[a] = Xp[a] - near_copy(sp[a][lane], Xp[a], L[a], P.per[a]);
+        d2 += r[a] * r[a];
+      }
+      const double d = sqrt(d2), reach = sp[3][p] + sp[3][lane] + P.zeta;
+      if (d < reach && d > 0.0) {
+        const double w = (reach - d) / P.zeta, mag = P.k_pp * w * w;
+        for (int a = 0; a < 3; ++a) Fr[a] = mag * r[a] / d;
+      }
+    }
+    for (int a = 0; a < 3; ++a) Fr[a] = wave_sum(Fr[a]);
+  }
   if (t != 0) return;
   for (int v = 0; v < kPartial; ++v)
     acc[v] = ((red[0][v] + red[1][v]) + red[2][v]) + red[3][v];
@@ -635,22 +675,8 @@ __global__ __launch_bounds__(kBlock) void k3_particles(
     Up[a] = cur[(fUp + a) * np + p];
     Op[a] = cur[(fOxp + a) * np + p];
   }
-  // repulsion (positions at n): the other spheres, then the walls
-  double Fr[3] = {0.0, 0.0, 0.0};
+  // repulsion of the walls (the spheres' is in Fr already)
   if (P.zeta > 0.0) {
-    for (int q = 0; q < np; ++q) {
-      if (q == p) continue;
-      double r[3], d2 = 0.0;
-      for (int a = 0; a < 3; ++a) {
-        r[a] = X[a] - near_copy(cur[(fX + a) * np + q], X[a], L[a], P.per[a]);
-        d2 += r[a] * r[a];
-      }
-      const double d = sqrt(d2), reach = R + C[cR * np + q] + P.zeta;
-      if (d < reach && d > 0.0) {
-        const double w = (reach - d) / P.zeta, mag = P.k_pp * w * w;
-        for (int a = 0; a < 3; ++a) Fr[a] += mag * r[a] / d;
-      }
-    }
     for (int face = 0; face < 6; ++face) {
       const int a = face / 2;
       if (P.per[a]) continue;
@@ -708,8 +734,9 @@ __global__ __launch_bounds__(kBlock) void k3_geometry_a(
     const Params3 P, const double* __restrict__ S, const double* __restrict__ C,
     int* __restrict__ gid, double* __restrict__ gw,
     unsigned long long* __restrict__ tmask, int* __restrict__ items,
-    int* __restrict__ nitems, int max_items, int* flags) {
+    int* __restrict__ nitems, int* flags) {
   __shared__ double sp[4][kMaxSpheres];   // X, Y, Z, R of every sphere
+  __shared__ int woff[kBlock / 64 + 1];   // the waves' item offsets
   const unsigned long long mask = tile_candidates(P, S, C, blockIdx.x);
   if (threadIdx.x == 0) tmask[blockIdx.x] = mask;     // for the step and
   if (!mask) return;                                  // the sphere pass
@@ -783,8 +810,10 @@ __global__ __launch_bounds__(kBlock) void k3_geometry_a(
     }
     ++cnt;
   }
-  // the wave's items: an exclusive prefix sum of the per-lane counts and
-  // one atomic per wave (one per item would queue at a single address)
+  // the block's items: prefix sums of the per-lane counts over the wave and
+  // the block, and one atomic per block on the counter of the block's
+  // segment (kSegs of them: one counter for every block queued at a single
+  // address and took longer than the rest of the pass)
   const int mine = __popc(part);
   int pre = mine;
 #pragma unroll
@@ -792,17 +821,25 @@ __global__ __launch_bounds__(kBlock) void k3_geometry_a(
     const int v = __shfl_up(pre, o, 64);
     if (lane >= o) pre += v;
   }
-  const int total = __shfl(pre, 63, 64);
-  int base = 0;
-  if (lane == 0 && total > 0) base = atomicAdd(nitems, total);
-  base = __shfl(base, 0, 64);
-  int at = base + pre - mine;
-  for (int s2 = 0; s2 < kMaxK; ++s2)
-    if ((part >> s2) & 1) {
-      if (at < max_items) items[at] = c * kMaxK + s2;
-      else atomicOr(flags, kFlagOverlap);    // cannot happen: room for all
-      ++at;
+  const int wv = t >> 6;
+  if (lane == 63) woff[wv] = pre;
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int w2 = 0; w2 < kBlock / 64; ++w2) {
+      const int n2 = woff[w2];
+      woff[w2] = acc;
+      acc += n2;
     }
+    woff[kBlock / 64] =
+        acc > 0 ? atomicAdd(&nitems[blockIdx.x % kSegs], acc) : 0;
+  }
+  __syncthreads();
+  // room for every slot of the segment's tiles
+  int* seg = items + (size_t)(blockIdx.x % kSegs) * seg_items(P);
+  int at = woff[kBlock / 64] + woff[wv] + pre - mine;
+  for (int s2 = 0; s2 < kMaxK; ++s2)
+    if ((part >> s2) & 1) seg[at++] = c * kMaxK + s2;
   if (!act) return;
 #pragma unroll
   for (int s2 = 0; s2 < kMaxK; ++s2) gw[(size_t)c * kMaxK + s2] = w[s2];
@@ -815,11 +852,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     const int* __restrict__ items, const int* __restrict__ nitems) {
   const int r = threadIdx.x % kGroup;
   const int groups = gridDim.x * (kBlock / kGroup);
-  const int n = *nitems;
+  int first[kSegs + 1];                 // the segments, concatenated
+  first[0] = 0;
+#pragma unroll
+  for (int k = 0; k < kSegs; ++k) first[k + 1] = first[k] + nitems[k];
+  const int n = first[kSegs];
+  const size_t seg = seg_items(P);
   const int nxy = P.nx * P.ny;
   for (int it = blockIdx.x * (kBlock / kGroup) + threadIdx.x / kGroup; it < n;
        it += groups) {                                 // uniform in a group
-    const int item = items[it];
+    int sg = 0;
+#pragma unroll
+    for (int k2 = 1; k2 < kSegs; ++k2) sg += it >= first[k2];
+    int base = first[0];
+#pragma unroll
+    for (int k2 = 1; k2 < kSegs; ++k2) base = sg == k2 ? first[k2] : base;
+    const int item = items[(size_t)sg * seg + (it - base)];
     const int c = item / kMaxK, slot = item - c * kMaxK;
     const int p = (gid[c] >> (8 * slot + 8)) & 255;
     const int k = c / nxy, j = (c - k * nxy) / P.nx, i = c - k * nxy - j * P.nx;
@@ -1176,12 +1224,12 @@ hipError_t launch_particles(const Params3& P, double* cur, double* nxt,
 hipError_t launch_geometry(const Params3& P, const double* S,
                            const double* C, int* gid, double* gw,
                            unsigned long long* tmask, int* items, int* nitems,
-                           int max_items, int* flags, hipStream_t s) {
+                           int* flags, hipStream_t s) {
   if (P.np == 0) return hipSuccess;
-  hipError_t e = hipMemsetAsync(nitems, 0, sizeof(int), s);
+  hipError_t e = hipMemsetAsync(nitems, 0, kSegs * sizeof(int), s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k3_geometry_a, dim3(nblocks_of(P)), dim3(kBlock), 0, s,
-                     P, S, C, gid, gw, tmask, items, nitems, max_items, flags);
+                     P, S, C, gid, gw, tmask, items, nitems, flags);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k3_geometry_b, dim3(2048), dim3(kBlock), 0, s, P, S, C,
