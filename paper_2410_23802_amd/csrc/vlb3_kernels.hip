@@ -217,31 +217,26 @@ __constant__ double gl_x[kGL], gl_w[kGL];
 // sector of angle arg(conj(u) v) enters as the complex factor u.v + i u x v
 // (rescaled by a power of two, exactly); with the centre outside the closed
 // square the net angle lies in (-pi, pi) and one atan2 of the product
-// gives it, otherwise (the square's column of cells) every sector takes
-// its own.
-struct SecAcc {
-  double tri, zr, zi, ang;
-};
-
-__device__ __forceinline__ void sec_factor(double cr, double ci, bool own,
-                                           SecAcc& a) {
+// gives it, otherwise (the square's column of cells) each edge's product
+// takes its own (an edge's sectors subtend less than pi from a centre
+// inside the square).  One atan2 call site serves both, so the code is
+// emitted once.
+__device__ __forceinline__ void cmul_scaled(double cr, double ci, double& zr,
+                                            double& zi) {
   if (cr == 0.0 && ci == 0.0) return;
-  if (own) {
-    a.ang += atan2(ci, cr);
-    return;
-  }
-  const double r = a.zr * cr - a.zi * ci, im = a.zr * ci + a.zi * cr;
+  const double r = zr * cr - zi * ci, im = zr * ci + zi * cr;
   int e;
   (void)frexp(fmax(fabs(r), fabs(im)), &e);
-  a.zr = ldexp(r, -e);
-  a.zi = ldexp(im, -e);
+  zr = ldexp(r, -e);
+  zi = ldexp(im, -e);
 }
 
 // edge from p (|p|^2 = pp) along the unit axis d: b = p.d, hh = h^2 =
-// |p|^2 - b^2, cr = p x d
+// |p|^2 - b^2, cr = p x d; adds its triangle part to tri and its sectors'
+// factors to (zr, zi)
 __device__ __forceinline__ void sec_edge(double b, double hh, double cr,
-                                         double pp, double r2, bool own,
-                                         SecAcc& a) {
+                                         double pp, double r2, double& tri,
+                                         double& zr, double& zi) {
   const double disc = r2 - hh;
   double s1 = 1.0, s2 = 0.0;
   if (disc > 0.0) {
@@ -250,12 +245,12 @@ __device__ __forceinline__ void sec_edge(double b, double hh, double cr,
     s2 = fmin(fmax(-b + w, 0.0), 1.0);
   }
   if (!(s1 < s2)) {              // the whole edge outside: p -> p + d
-    sec_factor(pp + b, cr, own, a);
+    cmul_scaled(pp + b, cr, zr, zi);
     return;
   }
-  a.tri += 0.5 * (s2 - s1) * cr;
-  if (s1 > 0.0) sec_factor(pp + s1 * b, s1 * cr, own, a);
-  if (s2 < 1.0) sec_factor(pp + (1.0 + s2) * b + s2, (1.0 - s2) * cr, own, a);
+  tri += 0.5 * (s2 - s1) * cr;
+  if (s1 > 0.0) cmul_scaled(pp + s1 * b, s1 * cr, zr, zi);
+  if (s2 < 1.0) cmul_scaled(pp + (1.0 + s2) * b + s2, (1.0 - s2) * cr, zr, zi);
 }
 
 __device__ __forceinline__ double unit_square_section(double x0, double y0,
@@ -263,27 +258,45 @@ __device__ __forceinline__ double unit_square_section(double x0, double y0,
   const double x1 = x0 + 1.0, y1 = y0 + 1.0;
   const bool own = x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0;
   const double xx0 = x0 * x0, xx1 = x1 * x1, yy0 = y0 * y0, yy1 = y1 * y1;
-  SecAcc a = {0.0, 1.0, 0.0, 0.0};
-  sec_edge(x0, yy0, -y0, xx0 + yy0, r2, own, a);    // bottom, +x
-  sec_edge(y0, xx1, x1, xx1 + yy0, r2, own, a);     // right, +y
-  sec_edge(-x1, yy1, y1, xx1 + yy1, r2, own, a);    // top, -x
-  sec_edge(-y1, xx0, -x0, xx0 + yy1, r2, own, a);   // left, -y
-  const double ang = own ? a.ang : atan2(a.zi, a.zr);
-  return fmin(fmax(a.tri + 0.5 * r2 * ang, 0.0), 1.0);
+  double tri = 0.0;
+  // per edge products (own) or the running product in slot 0
+  double ar = 1.0, ai = 0.0, br = 1.0, bi = 0.0, cr = 1.0, ci = 0.0;
+  double dr = 1.0, di = 0.0;
+  double xr, xi;
+  sec_edge(x0, yy0, -y0, xx0 + yy0, r2, tri, ar, ai);      // bottom, +x
+  xr = own ? 1.0 : ar; xi = own ? 0.0 : ai;
+  sec_edge(y0, xx1, x1, xx1 + yy0, r2, tri, xr, xi);      // right, +y
+  if (own) { br = xr; bi = xi; } else { ar = xr; ai = xi; }
+  xr = own ? 1.0 : ar; xi = own ? 0.0 : ai;
+  sec_edge(-x1, yy1, y1, xx1 + yy1, r2, tri, xr, xi);     // top, -x
+  if (own) { cr = xr; ci = xi; } else { ar = xr; ai = xi; }
+  xr = own ? 1.0 : ar; xi = own ? 0.0 : ai;
+  sec_edge(-y1, xx0, -x0, xx0 + yy1, r2, tri, xr, xi);    // left, -y
+  if (own) { dr = xr; di = xi; } else { ar = xr; ai = xi; }
+  double ang = 0.0;
+  const int nang = own ? 4 : 1;
+#pragma unroll 1
+  for (int e = 0; e < nang; ++e) {
+    ang += atan2(ai, ar);
+    ar = br; ai = bi;
+    br = cr; bi = ci;
+    cr = dr; ci = di;
+  }
+  return fmin(fmax(tri + 0.5 * r2 * ang, 0.0), 1.0);
 }
 
-__device__ __forceinline__ double section_area(double X, double Y, double R,
-                                               int i, int j, double z) {
+// (x0, y0: the cell's lower corner relative to the centre)
+__device__ __forceinline__ double section_area(double x0, double y0, double R,
+                                               double z) {
   const double r2 = (R - z) * (R + z);
-  return r2 > 0.0 ? unit_square_section((double)i - X, (double)j - Y, r2)
-                  : 0.0;
+  return r2 > 0.0 ? unit_square_section(x0, y0, r2) : 0.0;
 }
 
 // one Gauss-Legendre sub-interval [p, q] (nodes g0, g0 + gs, ... of the
 // rule; ONE: the node g0 only); sp / sq: p / q is a singular end
 template <bool ONE>
-__device__ __forceinline__ double gl_piece(double X, double Y, double R, int i,
-                                           int j, double p, double q, bool sp,
+__device__ __forceinline__ double gl_piece(double x0, double y0, double R,
+                                           double p, double q, bool sp,
                                            bool sq, int g0, int gs) {
   const double L = q - p;
   double sum = 0.0;
@@ -304,28 +317,25 @@ __device__ __forceinline__ double gl_piece(double X, double Y, double R, int i,
       z = p + L * t;
       dz = L;
     }
-    sum += gl_w[g] * section_area(X, Y, R, i, j, z) * dz;
+    sum += gl_w[g] * section_area(x0, y0, R, z) * dz;
   }
   return sum;
 }
 
-// The nodes g0, g0 + gs, ... of every sub-interval's rule (all of them for
-// gs = 1; a group of gs lanes splits them and adds its parts; ONE: gs is
-// the rule's size, one node per lane).  The
-// sub-intervals are walked by one flat loop with a single quadrature call
-// site: a wave whose lane groups hold different cells then spends one
-// evaluation per lane and iteration whatever phase each group is in, and
-// the area code is emitted once.
-template <bool ONE>
-__device__ __forceinline__ double volume_nodes(double X, double Y, double Z,
-                                               double R, int i, int j, int k,
-                                               int g0, int gs) {
+// The sub-intervals of the volume of the sphere (centre X, Y, Z, radius R)
+// in cell (i, j, k), in order: emit(p, q, sp, sq) for each (z relative to
+// the centre; sp / sq: p / q is a singular end), until it returns false.
+// One flat loop with a single emit site.
+template <class Emit>
+__device__ __forceinline__ void walk_subintervals(double X, double Y,
+                                                  double Z, double R, int i,
+                                                  int j, int k, Emit emit) {
   constexpr double kNone = 1e300;
   const double a0 = (double)i - X, a1 = a0 + 1.0;
   const double b0 = (double)j - Y, b1 = b0 + 1.0;
   const double zlo = (double)k - Z, zhi = (double)(k + 1) - Z;
   const double lo = fmax(zlo, -R), hi = fmin(zhi, R);
-  if (!(lo < hi)) return 0.0;
+  if (!(lo < hi)) return;
   // the points where the area is not analytic are +-zp[m] (absent ones:
   // zp = kNone); fixed-size and fully unrolled, so they stay in registers
   const double d2[8] = {a0 * a0, a1 * a1, b0 * b0, b1 * b1,
@@ -360,7 +370,7 @@ __device__ __forceinline__ double volume_nodes(double X, double Y, double Z,
   // towards u (phase 0), then towards v (phase 1), then the last one
   // (phase 2); phase 3 starts the next piece.
   constexpr double kGrade = 0.6;
-  double V = 0.0, u = lo, v = lo, L = 0.0, db = 0.0, da = 0.0, s = 0.0;
+  double u = lo, v = lo, L = 0.0, db = 0.0, da = 0.0, s = 0.0;
   double sk = 0.0;
   double cur = lo;
   bool cur_sing = false, sv = false;
@@ -393,7 +403,7 @@ __device__ __forceinline__ double volume_nodes(double X, double Y, double Z,
       ph = db > 1e-9 * L && s < kGrade * L ? 0 : kk > 0 ? 1 : 2;
     }
     const double q = ph == 0 ? u + s : ph == 1 ? v - sk : v;
-    V += gl_piece<ONE>(X, Y, R, i, j, cur, q, cur_sing, ph == 2 && sv, g0, gs);
+    if (!emit(cur, q, cur_sing, ph == 2 && sv)) return;
     cur = q;
     cur_sing = false;
     if (ph == 0) {
@@ -406,13 +416,26 @@ __device__ __forceinline__ double volume_nodes(double X, double Y, double Z,
       ph = 3;
     }
   }
+}
+
+// The whole volume on one lane (all nodes of every sub-interval).
+__device__ __forceinline__ double volume_all_nodes(double X, double Y,
+                                                   double Z, double R, int i,
+                                                   int j, int k) {
+  const double x0 = (double)i - X, y0 = (double)j - Y;
+  double V = 0.0;
+  walk_subintervals(X, Y, Z, R, i, j, k,
+                    [&](double p, double q, bool sp, bool sq) {
+                      V += gl_piece<false>(x0, y0, R, p, q, sp, sq, 0, 1);
+                      return true;
+                    });
   return V;
 }
 
 __device__ __forceinline__ double sphere_cell_volume(double X, double Y,
                                                      double Z, double R, int i,
                                                      int j, int k) {
-  return fmin(fmax(volume_nodes<false>(X, Y, Z, R, i, j, k, 0, 1), 0.0), 1.0);
+  return fmin(fmax(volume_all_nodes(X, Y, Z, R, i, j, k), 0.0), 1.0);
 }
 
 // The box of a tile (cells b*256 .. b*256+255), as cell-coordinate
@@ -846,12 +869,34 @@ __global__ __launch_bounds__(kBlock) void k3_geometry_a(
   gid[c] = packed | cnt;
 }
 
+// The exact volumes of the partly covered cell slots listed by the first
+// pass, four slots per wave at a time, in passes: each 16-lane group walks
+// its slot's sub-intervals into LDS (up to kCap a pass), then the wave
+// evaluates the four lists together, sixteen lanes (one node each) per
+// sub-interval, so that a wave takes the mean of its slots' sub-interval
+// counts rather than the largest; each group adds its sub-intervals' sums
+// in order (the volume does not depend on the other slots of the wave).
+// Past kCap sub-intervals a slot takes further passes, its walk skipping
+// those already done.
+constexpr int kCap = 48;
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k3_geometry_b(
     const Params3 P, const double* __restrict__ S, const double* __restrict__ C,
     const int* __restrict__ gid, double* __restrict__ gw,
     const int* __restrict__ items, const int* __restrict__ nitems) {
-  const int r = threadIdx.x % kGroup;
-  const int groups = gridDim.x * (kBlock / kGroup);
+  constexpr int kW = kBlock / 64, kG = 64 / kGroup;   // waves, groups
+  __shared__ double sp_[kW][kG][kCap], sq_[kW][kG][kCap], sv_[kW][kG][kCap];
+  __shared__ unsigned char sf_[kW][kG][kCap];
+  __shared__ double cell_[kW][kG][3];                 // x0, y0, R
+  __shared__ int sn_[kW][kG];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int grp = lane / kGroup, r = lane % kGroup;
   int first[kSegs + 1];                 // the segments, concatenated
   first[0] = 0;
 #pragma unroll
@@ -859,28 +904,96 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   const int n = first[kSegs];
   const size_t seg = seg_items(P);
   const int nxy = P.nx * P.ny;
-  for (int it = blockIdx.x * (kBlock / kGroup) + threadIdx.x / kGroup; it < n;
-       it += groups) {                                 // uniform in a group
-    int sg = 0;
+  const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+  const int nwaves = gridDim.x * kW;
+  for (int it0 = (blockIdx.x * kW + wv) * kG; it0 < n; it0 += nwaves * kG) {
+    const int it = it0 + grp;                            // uniform in a group
+    const bool has = it < n;
+    int c = 0, slot = 0, i = 0, j = 0, k = 0;
+    double cp[3] = {0.0, 0.0, 0.0}, R = 0.0;
+    if (has) {
+      int sg = 0;
 #pragma unroll
-    for (int k2 = 1; k2 < kSegs; ++k2) sg += it >= first[k2];
-    int base = first[0];
+      for (int k2 = 1; k2 < kSegs; ++k2) sg += it >= first[k2];
+      int base = first[0];
 #pragma unroll
-    for (int k2 = 1; k2 < kSegs; ++k2) base = sg == k2 ? first[k2] : base;
-    const int item = items[(size_t)sg * seg + (it - base)];
-    const int c = item / kMaxK, slot = item - c * kMaxK;
-    const int p = (gid[c] >> (8 * slot + 8)) & 255;
-    const int k = c / nxy, j = (c - k * nxy) / P.nx, i = c - k * nxy - j * P.nx;
-    const double node[3] = {i + 0.5, j + 0.5, k + 0.5};
-    const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
-    double cp[3];
-    for (int a = 0; a < 3; ++a)
-      cp[a] = near_copy(S[(fX + a) * P.np + p], node[a], L[a], P.per[a]);
-    double v = volume_nodes<true>(cp[0], cp[1], cp[2], C[cR * P.np + p], i, j, k, r,
-                            kGroup);
+      for (int k2 = 1; k2 < kSegs; ++k2) base = sg == k2 ? first[k2] : base;
+      const int item = items[(size_t)sg * seg + (it - base)];
+      c = item / kMaxK;
+      slot = item - c * kMaxK;
+      const int p = (gid[c] >> (8 * slot + 8)) & 255;
+      k = c / nxy;
+      j = (c - k * nxy) / P.nx;
+      i = c - k * nxy - j * P.nx;
+      const double node[3] = {i + 0.5, j + 0.5, k + 0.5};
+      for (int a = 0; a < 3; ++a)
+        cp[a] = near_copy(S[(fX + a) * P.np + p], node[a], L[a], P.per[a]);
+      R = C[cR * P.np + p];
+      if (r == 0) {
+        cell_[wv][grp][0] = (double)i - cp[0];
+        cell_[wv][grp][1] = (double)j - cp[1];
+        cell_[wv][grp][2] = R;
+      }
+    }
+    double V = 0.0;
+    for (int skip = 0;; skip += kCap) {
+      // walk: this pass's sub-intervals of the group's slot into LDS
+      int cnt = 0, idx = 0;
+      bool more = false;
+      if (has)
+        walk_subintervals(cp[0], cp[1], cp[2], R, i, j, k,
+                          [&](double p, double q, bool sp, bool sq) {
+                            if (idx++ < skip) return true;
+                            if (cnt == kCap) {
+                              more = true;
+                              return false;
+                            }
+                            if (r == 0) {
+                              sp_[wv][grp][cnt] = p;
+                              sq_[wv][grp][cnt] = q;
+                              sf_[wv][grp][cnt] =
+                                  (unsigned char)((sp ? 1 : 0) | (sq ? 2 : 0));
+                            }
+                            ++cnt;
+                            return true;
+                          });
+      if (r == 0) sn_[wv][grp] = cnt;
+      wave_lds_sync();
+      // evaluate the four lists together: entry e of the concatenation by
+      // group e mod kG in round e / kG
+      int nn[kG], tot = 0;
 #pragma unroll
-    for (int o = kGroup / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, kGroup);
-    if (r == 0) gw[(size_t)c * kMaxK + slot] = fmin(fmax(v, 0.0), 1.0);
+      for (int g = 0; g < kG; ++g) {
+        nn[g] = sn_[wv][g];
+        tot += nn[g];
+      }
+      for (int e0 = 0; e0 < tot; e0 += kG) {            // uniform in the wave
+        const int e = e0 + grp;
+        double val = 0.0;
+        int g = 0, l = e;
+        if (e < tot) {
+#pragma unroll
+          for (int g2 = 0; g2 < kG - 1; ++g2)
+            if (g == g2 && l >= nn[g2]) {
+              l -= nn[g2];
+              g = g2 + 1;
+            }
+          const unsigned f = sf_[wv][g][l];
+          val = gl_piece<true>(cell_[wv][g][0], cell_[wv][g][1],
+                               cell_[wv][g][2], sp_[wv][g][l], sq_[wv][g][l],
+                               f & 1u, (f & 2u) != 0u, r, kGroup);
+        }
+#pragma unroll
+        for (int o = kGroup / 2; o >= 1; o >>= 1) val += __shfl_xor(val, o, kGroup);
+        if (e < tot && r == 0) sv_[wv][g][l] = val;
+      }
+      wave_lds_sync();
+      for (int l = 0; l < cnt; ++l) V += sv_[wv][grp][l];   // in order
+      const bool again = __ballot(more) != 0ull;
+      wave_lds_sync();   // the lists are read before the next pass writes
+      if (!again) break;
+    }
+    if (has && r == 0) gw[(size_t)c * kMaxK + slot] = fmin(fmax(V, 0.0), 1.0);
   }
 }
 
