@@ -214,21 +214,23 @@ __constant__ double gl_x[kGL], gl_w[kGL];
 // from p along a unit axis d, so the circle meets it at
 // s = -p.d +- sqrt(r2 - h^2) (h the edge line's distance from the centre)
 // with no division, and the sectors' vectors follow from p, d and s.  Each
-// sector of angle arg(conj(u) v) enters as the complex factor u.v + i u x v
-// (rescaled by a power of two, exactly); with the centre outside the closed
+// sector of angle arg(conj(u) v) enters as the complex factor u.v + i u x v;
+// with the centre outside the closed
 // square the net angle lies in (-pi, pi) and one atan2 of the product
 // gives it, otherwise (the square's column of cells) each edge's product
 // takes its own (an edge's sectors subtend less than pi from a centre
 // inside the square).  One atan2 call site serves both, so the code is
 // emitted once.
-__device__ __forceinline__ void cmul_scaled(double cr, double ci, double& zr,
-                                            double& zi) {
+// (No rescaling is needed: a factor's modulus is |u| |v| <= (R + 2)^2 and
+// an edge contributes at most two, so eight factors stay far from
+// overflow; a vanishing factor, a corner at the centre, is left out.  A
+// form with selects instead of branches measured 5 % slower.)
+__device__ __forceinline__ void cmul(double cr, double ci, double& zr,
+                                     double& zi) {
   if (cr == 0.0 && ci == 0.0) return;
   const double r = zr * cr - zi * ci, im = zr * ci + zi * cr;
-  int e;
-  (void)frexp(fmax(fabs(r), fabs(im)), &e);
-  zr = ldexp(r, -e);
-  zi = ldexp(im, -e);
+  zr = r;
+  zi = im;
 }
 
 // edge from p (|p|^2 = pp) along the unit axis d: b = p.d, hh = h^2 =
@@ -245,12 +247,12 @@ __device__ __forceinline__ void sec_edge(double b, double hh, double cr,
     s2 = fmin(fmax(-b + w, 0.0), 1.0);
   }
   if (!(s1 < s2)) {              // the whole edge outside: p -> p + d
-    cmul_scaled(pp + b, cr, zr, zi);
+    cmul(pp + b, cr, zr, zi);
     return;
   }
   tri += 0.5 * (s2 - s1) * cr;
-  if (s1 > 0.0) cmul_scaled(pp + s1 * b, s1 * cr, zr, zi);
-  if (s2 < 1.0) cmul_scaled(pp + (1.0 + s2) * b + s2, (1.0 - s2) * cr, zr, zi);
+  if (s1 > 0.0) cmul(pp + s1 * b, s1 * cr, zr, zi);
+  if (s2 < 1.0) cmul(pp + (1.0 + s2) * b + s2, (1.0 - s2) * cr, zr, zi);
 }
 
 __device__ __forceinline__ double unit_square_section(double x0, double y0,
