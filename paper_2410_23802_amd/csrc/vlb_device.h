@@ -258,30 +258,64 @@ __device__ __forceinline__ double quad_disk_area(const double* u,
   return tri + 0.5 * R * R * atan2(zi, zr);
 }
 
-// Exact share of cell (i, j) covered by the disk (centre X, Y, radius R),
-// by Green's theorem over the four edges of the square taken
-// counter-clockwise: triangles from the centre to the parts of the edges
-// inside the circle, circular sectors for the parts outside.  When the
-// centre lies outside the closed cell the cell subtends less than pi from
-// it, so the sectors' net angle is in (-pi, pi) and one atan2 of the
-// product of their complex factors gives it; otherwise (a disk narrower
-// than the cell's diagonal) each sector is evaluated on its own.
-__device__ double covered_share(double X, double Y, double R, int i, int j) {
-  const double x0 = (double)i - X, x1 = (double)(i + 1) - X;
-  const double y0 = (double)j - Y, y1 = (double)(j + 1) - Y;
-  double A;
-  if (x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0) {
-    A = tri_disk_area(x0, y0, x1, y0, R) + tri_disk_area(x1, y0, x1, y1, R) +
-        tri_disk_area(x1, y1, x0, y1, R) + tri_disk_area(x0, y1, x0, y0, R);
-  } else {
-    double tri = 0.0, zr = 1.0, zi = 0.0;
-    tri_disk_parts(x0, y0, x1, y0, R, tri, zr, zi);
-    tri_disk_parts(x1, y0, x1, y1, R, tri, zr, zi);
-    tri_disk_parts(x1, y1, x0, y1, R, tri, zr, zi);
-    tri_disk_parts(x0, y1, x0, y0, R, tri, zr, zi);
-    A = tri + 0.5 * R * R * atan2(zi, zr);
+// The area of the disk of radius^2 r2 centred at the origin inside the
+// unit square [x0, x0 + 1] x [y0, y0 + 1] (coordinates relative to the
+// centre), by Green's theorem over the square's edges counter-clockwise.
+// An edge runs from p along a unit axis d (b = p.d, hh = h^2 = |p|^2 -
+// b^2, cr = p x d, pp = |p|^2), so the circle meets it at
+// s = -b +- sqrt(r2 - hh), with no division.  A sector of angle
+// arg(conj(u) v) enters as the complex factor u.v + i u x v, multiplied
+// into one product whose atan2 gives the net angle when the centre lies
+// outside the closed square (it is then in (-pi, pi)); in the square that
+// holds the centre each sector takes its own atan2.
+struct SqAcc {
+  double tri, zr, zi, ang;
+};
+
+__device__ __forceinline__ void sq_sector(double cr, double ci, bool own,
+                                          SqAcc& a) {
+  if (cr == 0.0 && ci == 0.0) return;
+  if (own) {
+    a.ang += atan2(ci, cr);
+    return;
   }
-  return fmin(fmax(A, 0.0), 1.0);
+  const double r = a.zr * cr - a.zi * ci, im = a.zr * ci + a.zi * cr;
+  a.zr = r;
+  a.zi = im;
+}
+
+__device__ __forceinline__ void sq_edge(double b, double hh, double cr,
+                                        double pp, double r2, bool own,
+                                        SqAcc& a) {
+  const double disc = r2 - hh;
+  double s1 = 1.0, s2 = 0.0;
+  if (disc > 0.0) {
+    const double w = sqrt(disc);
+    s1 = fmin(fmax(-b - w, 0.0), 1.0);
+    s2 = fmin(fmax(-b + w, 0.0), 1.0);
+  }
+  if (!(s1 < s2)) {              // the whole edge outside: p -> p + d
+    sq_sector(pp + b, cr, own, a);
+    return;
+  }
+  a.tri += 0.5 * (s2 - s1) * cr;
+  if (s1 > 0.0) sq_sector(pp + s1 * b, s1 * cr, own, a);
+  if (s2 < 1.0) sq_sector(pp + (1.0 + s2) * b + s2, (1.0 - s2) * cr, own, a);
+}
+
+// Exact share of cell (i, j) covered by the disk (centre X, Y, radius R).
+__device__ double covered_share(double X, double Y, double R, int i, int j) {
+  const double x0 = (double)i - X, y0 = (double)j - Y;
+  const double x1 = x0 + 1.0, y1 = y0 + 1.0, r2 = R * R;
+  const bool own = x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0;
+  const double xx0 = x0 * x0, xx1 = x1 * x1, yy0 = y0 * y0, yy1 = y1 * y1;
+  SqAcc a = {0.0, 1.0, 0.0, 0.0};
+  sq_edge(x0, yy0, -y0, xx0 + yy0, r2, own, a);     // bottom, +x
+  sq_edge(y0, xx1, x1, xx1 + yy0, r2, own, a);      // right, +y
+  sq_edge(-x1, yy1, y1, xx1 + yy1, r2, own, a);     // top, -x
+  sq_edge(-y1, xx0, -x0, xx0 + yy1, r2, own, a);    // left, -y
+  const double ang = own ? a.ang : atan2(a.zi, a.zr);
+  return fmin(fmax(a.tri + 0.5 * r2 * ang, 0.0), 1.0);
 }
 
 // Exact share of cell (i, j) covered by the ellipse of semi-axes a (the
