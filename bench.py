@@ -11,8 +11,9 @@ cell counts).  The same line reports the FP32 / FP16-shifted /
 BF16-shifted forms, the step kernel's achieved HBM bandwidth against the
 8 TB/s peak, the bandwidth of a plain device copy, the 200 x 4000
 single-disk channel (its working set fits the 256 MB Infinity Cache), the
-channel's physics on 16 M cells, the 256-domain batch, and the FP64 CPU
-oracle timed on a bounded sample of the headline workload on the host
+channel's physics on 16 M cells, the 256-domain batch, the two
+three-dimensional workloads (FP64 and the FP32 storage form), and the FP64
+CPU oracle timed on a bounded sample of the headline workload on the host
 cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -228,7 +229,10 @@ def run_batch(vlb, steps, warmup):
 # Algorithmic bytes per cell and step in three dimensions (FP64): the 19
 # flow and 7 energy populations read once and written once, and the
 # [df_s/dt] carrier read and written once.
-BYTES_PER_CELL3 = 2 * (19 + 7) * 8 + 2 * 8
+# (19 + 7) populations and the carrier, read and written: FP64 and the FP32
+# storage form (whose arithmetic is FP64 too)
+BYTES_PER_CELL3 = {"fp64": 2 * (19 + 7) * 8 + 2 * 8,
+                   "fp32": 2 * (19 + 7) * 4 + 2 * 4}
 WORKLOADS3 = {
     "c6_sphere_channel3": "80 x 80 x 320 channel, one cold sphere of D = 16 "
                           "settling (D3Q19 flow, D3Q7 energy, FP64)",
@@ -238,8 +242,9 @@ WORKLOADS3 = {
 
 
 def run_3d(vlb, steps, warmup):
-    """The three-dimensional path on both workloads: whole-step MLUPS and
-    the lattice step kernel's event-timed duration against its algorithmic
+    """The three-dimensional path on both workloads, FP64 (the top-level
+    keys) and the FP32 storage form ("fp32"): whole-step MLUPS and the
+    lattice step kernel's event-timed duration against its algorithmic
     bytes."""
     import torch
     import workloads as W
@@ -247,34 +252,38 @@ def run_3d(vlb, steps, warmup):
     for name, what in WORKLOADS3.items():
         d, ps = getattr(W, name)()
         cells = d["nx"] * d["ny"] * d["nz"]
-        dom = vlb.Domain3(d, ps).init()
-        dom.step(warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        dom.step(steps)
-        wall = time.perf_counter() - t0
-        dom.timing(True)
-        dom.timing_read()
-        dom.step(steps)
-        ms, n = dom.timing_read()
-        dom.timing(False)
-        dom.close()
-        k_ms = ms / max(n, 1)
-        gbs = BYTES_PER_CELL3 * cells / (k_ms * 1e-3) / 1e9
+        res = {}
+        for prec in ("fp64", "fp32"):
+            dom = vlb.Domain3(d, ps, precision=prec).init()
+            dom.step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dom.step(steps)
+            wall = time.perf_counter() - t0
+            dom.timing(True)
+            dom.timing_read()
+            dom.step(steps)
+            ms, n = dom.timing_read()
+            dom.timing(False)
+            dom.close()
+            k_ms = ms / max(n, 1)
+            bpc = BYTES_PER_CELL3[prec]
+            gbs = bpc * cells / (k_ms * 1e-3) / 1e9
+            res[prec] = {"mlups": round(cells * steps / wall / 1e6, 1),
+                         "ms_per_step": round(wall * 1e3 / steps, 4),
+                         "k3_step_us": round(k_ms * 1e3, 2),
+                         # the sphere pass and the geometry passes (exact
+                         # sphere-cell volumes, FP64-bound)
+                         "rest_of_step_us": round(
+                             wall * 1e6 / steps - k_ms * 1e3, 2),
+                         "achieved_GBs": round(gbs, 1),
+                         "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                         "bytes_per_cell": bpc}
+            print(f"# 3-D {name} {prec}: {res[prec]['mlups']} MLUPS, k3_step "
+                  f"{k_ms * 1e3:.1f} us -> {gbs:.0f} GB/s", file=sys.stderr,
+                  flush=True)
         out[name] = {"workload": what, "cells": cells, "spheres": len(ps),
-                     "mlups": round(cells * steps / wall / 1e6, 1),
-                     "ms_per_step": round(wall * 1e3 / steps, 4),
-                     "k3_step_us": round(k_ms * 1e3, 2),
-                     # the sphere pass and the geometry passes (exact
-                     # sphere-cell volumes, FP64-bound)
-                     "rest_of_step_us": round(wall * 1e6 / steps - k_ms * 1e3,
-                                              2),
-                     "achieved_GBs": round(gbs, 1),
-                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
-                     "bytes_per_cell": BYTES_PER_CELL3}
-        print(f"# 3-D {name}: {out[name]['mlups']} MLUPS, k3_step "
-              f"{k_ms * 1e3:.1f} us -> {gbs:.0f} GB/s", file=sys.stderr,
-              flush=True)
+                     **res["fp64"], "fp32": res["fp32"]}
     return out
 
 

@@ -80,7 +80,10 @@ typedef struct {
   double  coll_stiff_pw;     /* sphere-wall force at contact                 */
   double  init_rho, init_u[3], init_T;   /* initial fluid state              */
   int32_t kmax;              /* max spheres touching one cell, 1..4          */
-  int32_t precision;         /* VLB_FP64 (the only form in three dimensions) */
+  int32_t precision;         /* storage of the populations and the carrier:
+                                VLB_FP64, or VLB_FP32 (deviations from the
+                                equilibria of the initial state at rest);
+                                the arithmetic is FP64 in both            */
 } vlb3_domain_desc;
 
 /* A sphere.  fixed = 1: velocity and spin prescribed (not integrated). */
@@ -128,7 +131,8 @@ vlb_status vlb3_read_field(vlb3_ctx* ctx, int32_t field, double* dst,
                            int32_t dst_is_device);
 
 /* Copy the post-collision populations: which = 0 the 19 flow planes,
- * 1 the 7 energy planes ([q][k][j][i], host memory). */
+ * 1 the 7 energy planes ([q][k][j][i], host memory, FP64; the FP32 storage
+ * form's values with its reference added back). */
 vlb_status vlb3_read_populations(vlb3_ctx* ctx, int32_t which, double* dst);
 
 /* The first n spheres' states (n <= the count; host memory). */

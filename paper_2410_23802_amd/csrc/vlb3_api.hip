@@ -25,8 +25,10 @@ struct vlb3_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int device = 0;
-  double *f[2] = {nullptr, nullptr}, *g[2] = {nullptr, nullptr};
-  double *h[2] = {nullptr, nullptr};
+  // populations and carrier in the storage type (8 or 4 bytes, esz)
+  void *f[2] = {nullptr, nullptr}, *g[2] = {nullptr, nullptr};
+  void *h[2] = {nullptr, nullptr};
+  size_t esz = sizeof(double);
   double *S[2] = {nullptr, nullptr};   // sphere states
   double* C = nullptr;                 // sphere constants
   double* partial = nullptr;
@@ -64,6 +66,15 @@ static vlb_status fail3(vlb3_ctx* c, vlb_status s, const std::string& m) {
       return fail3((ctx), VLB_EHIP,                                      \
                    std::string(#expr) + ": " + hipGetErrorString(e_));   \
   } while (0)
+
+static bool dalloc3b(vlb3_ctx* c, void** p, size_t bytes) {
+  if (hipMalloc(p, bytes ? bytes : 8) != hipSuccess) {
+    *p = nullptr;
+    return false;
+  }
+  c->dev_bytes += bytes ? bytes : 8;
+  return true;
+}
 
 static bool dalloc3(vlb3_ctx* c, double** p, size_t n) {
   if (hipMalloc((void**)p, (n ? n : 1) * sizeof(double)) != hipSuccess) {
@@ -109,8 +120,8 @@ static std::string check_desc(const vlb3_domain_desc* d) {
     return "rho_f, cv_f, lambda_f, R_lambda, R_cv must be > 0";
   if (d->sigma_rule != 0 && d->sigma_rule != 1) return "sigma_rule must be 0 or 1";
   if (d->kmax < 1 || d->kmax > kMaxK) return "kmax must be in 1..4";
-  if (d->precision != VLB_FP64)
-    return "three-dimensional domains compute in FP64 only";
+  if (d->precision != VLB_FP64 && d->precision != VLB_FP32)
+    return "precision must be VLB_FP64 or VLB_FP32 (storage; FP64 arithmetic)";
   if (d->coll_range < 0.0) return "coll_range must be >= 0";
   if (!(d->init_rho > 0.0)) return "init_rho must be > 0";
   return "";
@@ -195,17 +206,38 @@ vlb_status vlb3_create(const vlb3_domain_desc* desc, int32_t nspheres,
   P.k_pp = desc->coll_stiff_pp;
   P.k_pw = desc->coll_stiff_pw;
   P.init_T = desc->init_T;
-  // One step moves 432 B a cell.  Above 320 MB (1.25 x the Infinity
-  // Cache) the next step cannot find the populations in the cache, and
-  // non-temporal stores leave it to the loads (80 x 80 x 320 channel:
-  // 254 -> 245 us a step; the 382 MB of the 96^3 box: unchanged).
-  P.nt_stores = (size_t)P.N * 432 > ((size_t)320 << 20);
+  // Storage: FP64, or FP32 deviations from the equilibria of the initial
+  // state at rest (w_q rho_0 for f; w_q c_ref T_0 for g, the rest
+  // population's c_v,f T_0 - (1 - w_0) c_ref T_0), so that FP32 holds the
+  // small departures rather than values of order one.
+  P.f32 = desc->precision == VLB_FP32;
+  c->esz = P.f32 ? sizeof(float) : sizeof(double);
+  {
+    const double w19[kQ] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+                            1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0,
+                            1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                            1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                            1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+    for (int q = 0; q < kQ; ++q) P.fshift[q] = P.f32 ? w19[q] * P.rho0 : 0.0;
+    const double cT0 = P.cref * P.init_T;
+    P.gshift[0] = P.f32 ? P.cv_f * P.init_T - (1.0 - 0.25) * cT0 : 0.0;
+    for (int q = 1; q < kQG; ++q) P.gshift[q] = P.f32 ? 0.125 * cT0 : 0.0;
+  }
+  // One step moves 432 B a cell in FP64, 216 B in FP32.  Above 320 MB
+  // (1.25 x the Infinity Cache) the next step cannot find the populations
+  // in the cache, and non-temporal stores leave it to the loads (80 x 80 x
+  // 320 channel, FP64: 254 -> 245 us a step; the 382 MB of the 96^3 box:
+  // unchanged).
+  const size_t moved = (size_t)P.N * (2 * (kQ + kQG + 1) * c->esz);
+  P.nt_stores = moved > ((size_t)320 << 20);
 
   const size_t N = (size_t)P.N, np = (size_t)(nspheres > 0 ? nspheres : 1);
   bool ok = true;
   for (int b = 0; b < 2 && ok; ++b)
-    ok = dalloc3(c, &c->f[b], N * kQ) && dalloc3(c, &c->g[b], N * kQG) &&
-         dalloc3(c, &c->h[b], N) && dalloc3(c, &c->S[b], np * kFields);
+    ok = dalloc3b(c, &c->f[b], N * kQ * c->esz) &&
+         dalloc3b(c, &c->g[b], N * kQG * c->esz) &&
+         dalloc3b(c, &c->h[b], N * c->esz) &&
+         dalloc3(c, &c->S[b], np * kFields);
   ok = ok && dalloc3(c, &c->C, np * kConsts) && dalloc3(c, &c->macro, N * kMacro) &&
        dalloc3(c, &c->partial, np * (size_t)P.nblocks * kPartial) &&
        dalloc3(c, &c->sums, np * 5);
@@ -331,10 +363,23 @@ vlb_status vlb3_read_field(vlb3_ctx* c, int32_t field, double* dst,
 vlb_status vlb3_read_populations(vlb3_ctx* c, int32_t which, double* dst) {
   if (!c || !dst || (which != 0 && which != 1)) return VLB_EINVAL;
   if (!c->initialized) return fail3(c, VLB_ESTATE, "no state to read");
-  const size_t n = (size_t)c->P.N * (which ? kQG : kQ);
-  HIP3(c, hipMemcpyAsync(dst, which ? c->g[c->cur] : c->f[c->cur],
-                         n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  const size_t N = (size_t)c->P.N, nq = which ? kQG : kQ, n = N * nq;
+  const void* src = which ? c->g[c->cur] : c->f[c->cur];
+  if (!c->P.f32) {
+    HIP3(c, hipMemcpyAsync(dst, src, n * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP3(c, hipStreamSynchronize(c->stream));
+    return VLB_OK;
+  }
+  // FP32 storage: the deviations, plus the reference, as FP64
+  std::vector<float> tmp(n);
+  HIP3(c, hipMemcpyAsync(tmp.data(), src, n * sizeof(float),
+                         hipMemcpyDeviceToHost, c->stream));
   HIP3(c, hipStreamSynchronize(c->stream));
+  const double* shift = which ? c->P.gshift : c->P.fshift;
+  for (size_t q = 0; q < nq; ++q)
+    for (size_t i = 0; i < N; ++i)
+      dst[q * N + i] = (double)tmp[q * N + i] + shift[q];
   return VLB_OK;
 }
 

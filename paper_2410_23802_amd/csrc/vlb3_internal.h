@@ -38,13 +38,19 @@ struct Params3 {
   double zeta, k_pp, k_pw;
   double init_u[3], init_T;
   int nt_stores;              // the step stores past the caches
+  // storage: FP64, or FP32 populations and carrier (f32 = 1) kept as the
+  // deviations f_q - fshift[q], g_q - gshift[q] (the arithmetic stays FP64)
+  int f32;
+  double fshift[kQ], gshift[kQG];
 };
 
 // Per (sphere, tile) partial sums of sum f_s,p (f^eq - f*) e (3) and of its
 // moment about the centre (3).
 constexpr int kPartial = 6;
 
-hipError_t launch_init(const Params3& P, double* f, double* g, double* h,
+// f, g, h: populations and carrier in the storage type (FP64, or FP32
+// where P.f32)
+hipError_t launch_init(const Params3& P, void* f, void* g, void* h,
                        double* macro, const double* S, const double* C,
                        int* flags, hipStream_t s);
 // the momentum-exchange sums over the tiles whose candidate masks (tmask,
@@ -67,9 +73,9 @@ hipError_t launch_geometry(const Params3& P, const double* S,
                            const double* C, int* gid, double* gw,
                            unsigned long long* tmask, int* items, int* nitems,
                            int* flags, hipStream_t s);
-hipError_t launch_step(const Params3& P, bool out, const double* fin,
-                       double* fout, const double* gin, double* gout,
-                       const double* hin, double* hout, const double* S,
+hipError_t launch_step(const Params3& P, bool out, const void* fin,
+                       void* fout, const void* gin, void* gout,
+                       const void* hin, void* hout, const double* S,
                        const double* C, const int* gid, const double* gw,
                        const unsigned long long* tmask, double* partial,
                        double* macro, int* flags, hipStream_t s);

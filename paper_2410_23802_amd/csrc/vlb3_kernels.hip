@@ -129,19 +129,28 @@ __device__ __forceinline__ void relax_moments(const double (&a)[kQ],
 // f'_Q = (base of Q) + (M^T dm)_Q, stored as each is formed (no array of
 // 19 results held)
 // (NT: stored non-temporally)
-template <bool NT>
-__device__ __forceinline__ void put(double* p, double v) {
+template <bool NT, class T>
+__device__ __forceinline__ void put(T* p, double v) {
   if constexpr (NT)
-    __builtin_nontemporal_store(v, p);
+    __builtin_nontemporal_store((T)v, p);
   else
-    *p = v;
+    *p = (T)v;
 }
 
-template <bool NT, class Base, size_t... Q>
+// a population in the storage form: FP64 as it is, FP32 less its shift
+template <bool NT, class T>
+__device__ __forceinline__ void put_pop(T* p, double v, double shift) {
+  if constexpr (sizeof(T) < sizeof(double)) v -= shift;
+  put<NT>(p, v);
+}
+
+// (stored minus shift[Q]: the storage form's reference)
+template <bool NT, class T, class Base, size_t... Q>
 __device__ __forceinline__ void back_transform_store(
-    const double (&dm)[kQ], Base base, double* __restrict__ out, size_t N,
-    size_t c, std::index_sequence<Q...>) {
-  (put<NT>(out + Q * N + c, base((int)Q) + col_dot<(int)Q>(dm)), ...);
+    const double (&dm)[kQ], Base base, T* __restrict__ out, size_t N,
+    size_t c, const double* shift, std::index_sequence<Q...>) {
+  (put_pop<NT>(out + Q * N + c, base((int)Q) + col_dot<(int)Q>(dm), shift[Q]),
+   ...);
 }
 
 // ---------------------------------------------------------------------------
@@ -577,9 +586,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 // Initial state
 
+// T: the storage type of the populations and the carrier
+template <class T>
 __global__ __launch_bounds__(kBlock) void k3_init(
-    const Params3 P, double* __restrict__ f, double* __restrict__ g,
-    double* __restrict__ h, double* __restrict__ macro,
+    const Params3 P, T* __restrict__ f, T* __restrict__ g,
+    T* __restrict__ h, double* __restrict__ macro,
     const double* __restrict__ S, const double* __restrict__ C, int* flags) {
   const unsigned long long mask = tile_candidates(P, S, C, blockIdx.x);
   const int c = blockIdx.x * kBlock + threadIdx.x;
@@ -599,16 +610,18 @@ __global__ __launch_bounds__(kBlock) void k3_init(
     for (int a = 0; a < 3; ++a) u[a] += geo.w[n] * us[a];
     eps += geo.w[n] * P.cv_s * C[cTinit * P.np + geo.id[n]];
   }
-  const double cv = (1.0 - fs) * P.cv_f + fs * P.cv_s, T = eps / cv;
+  const double cv = (1.0 - fs) * P.cv_f + fs * P.cv_s, Tc = eps / cv;
   const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
   for (int q = 0; q < kQ; ++q)
-    f[(size_t)q * P.N + c] = feq_q(q, P.rho0, u[0], u[1], u[2], u2);
-  g[c] = eps - (1.0 - kW0G) * P.cref * T;
+    put_pop<false>(f + (size_t)q * P.N + c,
+                   feq_q(q, P.rho0, u[0], u[1], u[2], u2), P.fshift[q]);
+  put_pop<false>(g + c, eps - (1.0 - kW0G) * P.cref * Tc, P.gshift[0]);
 #pragma unroll
-  for (int q = 1; q < kQG; ++q) g[(size_t)q * P.N + c] = kW1G * P.cref * T;
-  h[c] = 2.0 * fs;
-  const double mv[kMacro] = {P.rho0, u[0], u[1], u[2], T, fs, 0.0};
+  for (int q = 1; q < kQG; ++q)
+    put_pop<false>(g + (size_t)q * P.N + c, kW1G * P.cref * Tc, P.gshift[q]);
+  put<false>(h + c, 2.0 * fs);
+  const double mv[kMacro] = {P.rho0, u[0], u[1], u[2], Tc, fs, 0.0};
 #pragma unroll
   for (int m = 0; m < kMacro; ++m) macro[(size_t)m * P.N + c] = mv[m];
 }
@@ -1003,12 +1016,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 // The lattice step
 
 // NT (the host's nt_stores): populations and carrier stored
-// non-temporally
-template <bool OUT, bool NT>
+// non-temporally; St: their storage type (double, or float holding the
+// deviations from P.fshift and P.gshift, the arithmetic in FP64 either way)
+template <bool OUT, bool NT, class St>
 __global__ __launch_bounds__(kBlock) void k3_step(
-    const Params3 P, const double* __restrict__ fin, double* __restrict__ fout,
-    const double* __restrict__ gin, double* __restrict__ gout,
-    const double* __restrict__ hin, double* __restrict__ hout,
+    const Params3 P, const St* __restrict__ fin, St* __restrict__ fout,
+    const St* __restrict__ gin, St* __restrict__ gout,
+    const St* __restrict__ hin, St* __restrict__ hout,
     const double* __restrict__ S, const double* __restrict__ C,
     const int* __restrict__ gid, const double* __restrict__ gw,
     const unsigned long long* __restrict__ tmask, double* __restrict__ partial,
@@ -1049,10 +1063,19 @@ __global__ __launch_bounds__(kBlock) void k3_step(
     const bool wall = wx_[q] || wy_[q] || wz_[q];
     const size_t at = wall ? (size_t)opp(q) * P.N + cc
                            : (size_t)q * P.N + (size_t)(cc + off);
-    fst[q] = fin[at];
-    if (q < kQG) g[q] = gin[at];
+    fst[q] = (double)fin[at];
+    if (q < kQG) g[q] = (double)gin[at];
   }
-  const double hold = hin[cc];
+  const double hold = (double)hin[cc];
+  // the storage form's reference (zero in FP64; w_q is w_opp(q), so a
+  // bounced population takes its own direction's shift)
+  if constexpr (sizeof(St) < sizeof(double)) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      fst[q] += P.fshift[q];
+      if (q < kQG) g[q] += P.gshift[q];
+    }
+  }
   if (bxl || bxh || byl || byh || bzl || bzh) {
 #pragma unroll
     for (int q = 1; q < kQ; ++q) {
@@ -1203,11 +1226,13 @@ __global__ __launch_bounds__(kBlock) void k3_step(
   // source on the rest population
   {
     const double geq0 = eps - (1.0 - kW0G) * P.cref * T, geqi = kW1G * P.cref * T;
-    put<NT>(gout + c, g[0] - se * (g[0] - geq0) + (1.0 - 0.5 * se) * qc);
+    put_pop<NT>(gout + c, g[0] - se * (g[0] - geq0) + (1.0 - 0.5 * se) * qc,
+                P.gshift[0]);
 #pragma unroll
     for (int q = 1; q < kQG; ++q) {
       const double ev = 0.5 * (g[q] + g[opp(q)]), od = 0.5 * (g[q] - g[opp(q)]);
-      put<NT>(gout + (size_t)q * P.N + c, g[q] - se * (ev - geqi) - sj * od);
+      put_pop<NT>(gout + (size_t)q * P.N + c,
+                  g[q] - se * (ev - geqi) - sj * od, P.gshift[q]);
     }
   }
   // flow MRT collision (eq. lbe.rho.col),
@@ -1233,7 +1258,7 @@ __global__ __launch_bounds__(kBlock) void k3_step(
       return a[q] + feq_q(q, rho, u[0], u[1], u[2], u2) + 0.5 * guo(q);
     };
     back_transform_store<NT>(dm, base, fout, (size_t)P.N, (size_t)c,
-                         std::make_index_sequence<kQ>{});
+                             P.fshift, std::make_index_sequence<kQ>{});
   }
   put<NT>(hout + c, 2.0 * fs + dfs);
   if (OUT) {
@@ -1318,11 +1343,17 @@ __global__ __launch_bounds__(kBlock) void k3_sphere_sums(
 
 static unsigned nblocks_of(const Params3& P) { return (unsigned)P.nblocks; }
 
-hipError_t launch_init(const Params3& P, double* f, double* g, double* h,
+hipError_t launch_init(const Params3& P, void* f, void* g, void* h,
                        double* macro, const double* S, const double* C,
                        int* flags, hipStream_t s) {
-  hipLaunchKernelGGL(k3_init, dim3(nblocks_of(P)), dim3(kBlock), 0, s, P, f,
-                     g, h, macro, S, C, flags);
+  if (P.f32)
+    hipLaunchKernelGGL(k3_init<float>, dim3(nblocks_of(P)), dim3(kBlock), 0,
+                       s, P, (float*)f, (float*)g, (float*)h, macro, S, C,
+                       flags);
+  else
+    hipLaunchKernelGGL(k3_init<double>, dim3(nblocks_of(P)), dim3(kBlock), 0,
+                       s, P, (double*)f, (double*)g, (double*)h, macro, S, C,
+                       flags);
   return hipGetLastError();
 }
 
@@ -1352,21 +1383,29 @@ hipError_t launch_geometry(const Params3& P, const double* S,
   return hipGetLastError();
 }
 
-hipError_t launch_step(const Params3& P, bool out, const double* fin,
-                       double* fout, const double* gin, double* gout,
-                       const double* hin, double* hout, const double* S,
+hipError_t launch_step(const Params3& P, bool out, const void* fin,
+                       void* fout, const void* gin, void* gout,
+                       const void* hin, void* hout, const double* S,
                        const double* C, const int* gid, const double* gw,
                        const unsigned long long* tmask, double* partial,
                        double* macro, int* flags, hipStream_t s) {
-#define VLB3_STEP(O, N)                                                    \
-  hipLaunchKernelGGL((k3_step<O, N>), dim3(nblocks_of(P)), dim3(kBlock), 0, \
-                     s, P, fin, fout, gin, gout, hin, hout, S, C, gid, gw,   \
-                     tmask, partial, macro, flags)
-  if (P.nt_stores) {
-    if (out) VLB3_STEP(true, true); else VLB3_STEP(false, true);
-  } else {
-    if (out) VLB3_STEP(true, false); else VLB3_STEP(false, false);
+#define VLB3_STEP(O, N, T)                                                   \
+  hipLaunchKernelGGL((k3_step<O, N, T>), dim3(nblocks_of(P)), dim3(kBlock),  \
+                     0, s, P, (const T*)fin, (T*)fout, (const T*)gin,        \
+                     (T*)gout, (const T*)hin, (T*)hout, S, C, gid, gw, tmask, \
+                     partial, macro, flags)
+#define VLB3_STEP_T(T)                                                       \
+  if (P.nt_stores) {                                                         \
+    if (out) VLB3_STEP(true, true, T); else VLB3_STEP(false, true, T);       \
+  } else {                                                                   \
+    if (out) VLB3_STEP(true, false, T); else VLB3_STEP(false, false, T);     \
   }
+  if (P.f32) {
+    VLB3_STEP_T(float)
+  } else {
+    VLB3_STEP_T(double)
+  }
+#undef VLB3_STEP_T
 #undef VLB3_STEP
   return hipGetLastError();
 }

@@ -587,7 +587,7 @@ class Batch:
 # ---------------------------------------------------------------------------
 # Three dimensions (include/vlb3.h)
 
-def make_domain3_desc(d: dict) -> vlb3_domain_desc:
+def make_domain3_desc(d: dict, precision="fp64") -> vlb3_domain_desc:
     s = vlb3_domain_desc()
     s.nx, s.ny, s.nz = int(d["nx"]), int(d["ny"]), int(d["nz"])
     for k in range(6):
@@ -606,7 +606,8 @@ def make_domain3_desc(d: dict) -> vlb3_domain_desc:
         s.init_u[a] = float(d["init_u"][a])
     s.sigma_rule = int(d["sigma_rule"])
     s.kmax = int(d["kmax"])
-    s.precision = 0
+    s.precision = (PRECISIONS[precision] if isinstance(precision, str)
+                   else int(precision))
     return s
 
 
@@ -627,14 +628,16 @@ def _check3(status: int, where: str, handle=None):
 
 
 class Domain3:
-    """One three-dimensional domain on the GPU (FP64), through the vlb3_*
-    C ABI.  Fields are numpy arrays shaped (nz, ny, nx)."""
+    """One three-dimensional domain on the GPU, through the vlb3_* C ABI:
+    populations stored in FP64 or FP32 ("fp64", "fp32"), the arithmetic in
+    FP64.  Fields are numpy arrays shaped (nz, ny, nx)."""
 
-    def __init__(self, d: dict, spheres=(), stream=None):
+    def __init__(self, d: dict, spheres=(), stream=None, precision="fp64"):
         self.d = dict(d)
         self.spheres = list(spheres)
         self.shape = (int(d["nz"]), int(d["ny"]), int(d["nx"]))
-        desc = make_domain3_desc(d)
+        self.precision = precision
+        desc = make_domain3_desc(d, precision)
         arr = make_spheres(self.spheres)
         self._destroy = lib().vlb3_destroy    # see Domain.__init__
         h = ctypes.c_void_p()
