@@ -243,3 +243,27 @@ def test_c5_batch_autotuned_sample_matches_oracle(vlb, oracle_mod):
         e = check_case(oracle_mod, o, f, p, d, ps, n, "fp32")
         say(f"  vs oracle: {e}")
     b.close()
+
+
+def test_c5_sample_long_horizon_fp64(vlb, oracle_mod):
+    """Four seeded C5 domains batched in FP64 over 1000 steps against the
+    FP64 oracle at the single-domain bar (1e-12 of each scale, or 4x the
+    spread of the oracle's FMA twin): the batch keeps parity over a run a
+    hundred times longer than the ten steps above."""
+    cases = W.c5_batch()
+    rng = np.random.default_rng(11)
+    pick = sorted(int(i) for i in rng.choice(len(cases), size=4,
+                                              replace=False))
+    sub = [cases[i] for i in pick]
+    b = vlb.Batch(sub, "fp64")
+    say(f"C5 sample {pick}: {b.cells} cells, FP64, 1000 steps")
+    b.init()
+    n = 1000
+    b.step(n)
+    for k, (d, ps) in enumerate(sub):
+        f, p = batch_state(b, k, ps)
+        o = oracle_mod.Oracle(d, ps).init().step(n)
+        e = check_case(oracle_mod, o, f, p, d, ps, n, "fp64")
+        say(f"  domain {pick[k]} ({d['nx']} x {d['ny']}): "
+            f"worst {max(e.values()):.1e}")
+    b.close()
