@@ -138,6 +138,17 @@ vlb_status vlb3_read_populations(vlb3_ctx* ctx, int32_t which, double* dst);
 /* The first n spheres' states (n <= the count; host memory). */
 vlb_status vlb3_read_spheres(vlb3_ctx* ctx, int32_t n, vlb3_sphere_state* dst);
 
+/* Checkpoint, as vlb_save / vlb_load: vlb3_save writes the complete state
+ * (populations and carrier in the storage form, macroscopic fields, the
+ * spheres' state, the last step's momentum-exchange partial sums and tile
+ * candidate masks, the step counter) into buf; with buf == NULL it only
+ * stores the needed size in *inout_len.  vlb3_load restores a buffer written
+ * by vlb3_save for a context created with the same descriptor and spheres;
+ * stepping after a load continues bit for bit.  VLB_EINVAL for a buffer
+ * that is too short or does not match the context. */
+vlb_status vlb3_save(vlb3_ctx* ctx, void* buf, size_t* inout_len);
+vlb_status vlb3_load(vlb3_ctx* ctx, const void* buf, size_t len);
+
 /* Kernel timing, as vlb_timing_enable / vlb_timing_read: while enabled,
  * every launch of the step kernel is bracketed by HIP events on the context
  * stream; read returns the summed duration (ms) and the count, and resets

@@ -415,6 +415,102 @@ vlb_status vlb3_read_spheres(vlb3_ctx* c, int32_t n, vlb3_sphere_state* dst) {
   return VLB_OK;
 }
 
+// Checkpoint layout: the header, then f, g, h of the current step (in the
+// storage type), the macroscopic fields, and with spheres their current
+// state, the last step's partial sums and tile candidate masks.
+struct Save3Header {
+  char magic[8];
+  int32_t nx, ny, nz, f32, np, have;
+  int64_t step;
+};
+
+static size_t save3_size(const vlb3_ctx* c) {
+  const size_t N = (size_t)c->P.N, np = (size_t)c->P.np;
+  size_t n = sizeof(Save3Header) + N * (kQ + kQG + 1) * c->esz +
+             N * kMacro * sizeof(double);
+  if (np > 0)
+    n += np * kFields * sizeof(double) +
+         np * (size_t)c->P.nblocks * kPartial * sizeof(double) +
+         (size_t)c->P.nblocks * sizeof(unsigned long long);
+  return n;
+}
+
+vlb_status vlb3_save(vlb3_ctx* c, void* buf, size_t* inout_len) {
+  if (!c || !inout_len) return VLB_EINVAL;
+  const size_t need = save3_size(c);
+  if (!buf) {
+    *inout_len = need;
+    return VLB_OK;
+  }
+  if (*inout_len < need) return fail3(c, VLB_EINVAL, "checkpoint buffer too small");
+  if (!c->initialized) return fail3(c, VLB_ESTATE, "no valid state to save");
+  Save3Header hd;
+  memset(&hd, 0, sizeof hd);
+  memcpy(hd.magic, "VLB3CKP1", 8);
+  hd.nx = c->P.nx; hd.ny = c->P.ny; hd.nz = c->P.nz; hd.f32 = c->P.f32;
+  hd.np = c->P.np; hd.have = c->have; hd.step = c->step;
+  char* o = (char*)buf;
+  memcpy(o, &hd, sizeof hd);
+  o += sizeof hd;
+  const size_t N = (size_t)c->P.N, np = (size_t)c->P.np;
+  const hipMemcpyKind D2H = hipMemcpyDeviceToHost;
+  const size_t fb = N * kQ * c->esz, gb = N * kQG * c->esz, hb = N * c->esz;
+  HIP3(c, hipMemcpyAsync(o, c->f[c->cur], fb, D2H, c->stream)); o += fb;
+  HIP3(c, hipMemcpyAsync(o, c->g[c->cur], gb, D2H, c->stream)); o += gb;
+  HIP3(c, hipMemcpyAsync(o, c->h[c->cur], hb, D2H, c->stream)); o += hb;
+  HIP3(c, hipMemcpyAsync(o, c->macro, N * kMacro * 8, D2H, c->stream));
+  o += N * kMacro * 8;
+  if (np > 0) {
+    const size_t sb = np * kFields * 8;
+    const size_t pb = np * (size_t)c->P.nblocks * kPartial * 8;
+    const size_t tb = (size_t)c->P.nblocks * 8;
+    HIP3(c, hipMemcpyAsync(o, c->S[c->scur], sb, D2H, c->stream)); o += sb;
+    HIP3(c, hipMemcpyAsync(o, c->partial, pb, D2H, c->stream)); o += pb;
+    HIP3(c, hipMemcpyAsync(o, c->tmask, tb, D2H, c->stream));
+  }
+  HIP3(c, hipStreamSynchronize(c->stream));
+  *inout_len = need;
+  return VLB_OK;
+}
+
+vlb_status vlb3_load(vlb3_ctx* c, const void* buf, size_t len) {
+  if (!c || !buf) return VLB_EINVAL;
+  if (len < sizeof(Save3Header) || len < save3_size(c))
+    return fail3(c, VLB_EINVAL, "checkpoint too short");
+  Save3Header hd;
+  memcpy(&hd, buf, sizeof hd);
+  if (memcmp(hd.magic, "VLB3CKP1", 8) != 0 || hd.nx != c->P.nx ||
+      hd.ny != c->P.ny || hd.nz != c->P.nz || hd.f32 != c->P.f32 ||
+      hd.np != c->P.np)
+    return fail3(c, VLB_EINVAL, "checkpoint does not match this context");
+  const char* o = (const char*)buf + sizeof hd;
+  const size_t N = (size_t)c->P.N, np = (size_t)c->P.np;
+  const hipMemcpyKind H2D = hipMemcpyHostToDevice;
+  const size_t fb = N * kQ * c->esz, gb = N * kQG * c->esz, hb = N * c->esz;
+  c->cur = 0;
+  c->scur = 0;
+  HIP3(c, hipMemcpyAsync(c->f[0], o, fb, H2D, c->stream)); o += fb;
+  HIP3(c, hipMemcpyAsync(c->g[0], o, gb, H2D, c->stream)); o += gb;
+  HIP3(c, hipMemcpyAsync(c->h[0], o, hb, H2D, c->stream)); o += hb;
+  HIP3(c, hipMemcpyAsync(c->macro, o, N * kMacro * 8, H2D, c->stream));
+  o += N * kMacro * 8;
+  if (np > 0) {
+    const size_t sb = np * kFields * 8;
+    const size_t pb = np * (size_t)c->P.nblocks * kPartial * 8;
+    const size_t tb = (size_t)c->P.nblocks * 8;
+    HIP3(c, hipMemcpyAsync(c->S[0], o, sb, H2D, c->stream)); o += sb;
+    HIP3(c, hipMemcpyAsync(c->partial, o, pb, H2D, c->stream)); o += pb;
+    HIP3(c, hipMemcpyAsync(c->tmask, o, tb, H2D, c->stream));
+  }
+  HIP3(c, hipMemsetAsync(c->flags, 0, sizeof(int), c->stream));
+  // the copies read the caller's buffer: finish before returning
+  HIP3(c, hipStreamSynchronize(c->stream));
+  c->have = hd.have;
+  c->step = hd.step;
+  c->initialized = true;
+  return VLB_OK;
+}
+
 vlb_status vlb3_timing_enable(vlb3_ctx* c, int32_t on) {
   if (!c) return VLB_EINVAL;
   c->timing = on != 0;

@@ -210,6 +210,8 @@ def lib():
         "vlb3_read_populations": ([vp, i32, vp], ctypes.c_int),
         "vlb3_read_spheres": ([vp, i32, ctypes.POINTER(vlb3_sphere_state)],
                               ctypes.c_int),
+        "vlb3_save": ([vp, vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "vlb3_load": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
         "vlb3_timing_enable": ([vp, i32], ctypes.c_int),
         "vlb3_timing_read": ([vp, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(i64)], ctypes.c_int),
@@ -686,6 +688,20 @@ class Domain3:
             for k in names:
                 out[i][k] = getattr(arr[i], k)
         return out
+
+    def save(self) -> bytes:
+        n = ctypes.c_size_t(0)
+        _check3(lib().vlb3_save(self.h, None, ctypes.byref(n)), "vlb3_save",
+                self.h)
+        buf = ctypes.create_string_buffer(n.value)
+        _check3(lib().vlb3_save(self.h, buf, ctypes.byref(n)), "vlb3_save",
+                self.h)
+        return buf.raw[:n.value]
+
+    def load(self, data: bytes):
+        buf = ctypes.create_string_buffer(bytes(data), len(data))
+        _check3(lib().vlb3_load(self.h, buf, len(data)), "vlb3_load", self.h)
+        return self
 
     def timing(self, on: bool):
         _check3(lib().vlb3_timing_enable(self.h, int(bool(on))),

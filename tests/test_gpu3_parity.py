@@ -291,3 +291,33 @@ def test_gpu3_fp32_storage_rest_state(vlb):
         g.close()
     for a, b in zip(out["fp64"], out["fp32"]):
         assert np.abs(a - b).max() <= 1e-15 * max(1.0, np.abs(a).max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gpu3_checkpoint_continues_bit_for_bit(vlb, prec):
+    """Save after three steps of the walled two-sphere case, step four more;
+    load the checkpoint into a fresh context and step the same four: every
+    population, field and sphere state agrees bit for bit, and so does the
+    step count.  A checkpoint of another shape is refused."""
+    d, ps = wall_case()
+    a = vlb.Domain3(d, ps, precision=prec).init()
+    a.step(3)
+    ck = a.save()
+    a.step(4)
+    b = vlb.Domain3(d, ps, precision=prec).init()
+    b.load(ck)
+    b.step(4)
+    for n in ("f", "g"):
+        assert np.array_equal(a.populations(n), b.populations(n)), n
+    for n in FIELDS:
+        assert np.array_equal(a.field(n), b.field(n)), n
+    pa, pb = a.particles(), b.particles()
+    for key in pa.dtype.names:
+        assert np.array_equal(pa[key], pb[key]), key
+    assert (vlb.lib().vlb3_step_count(a.h) == vlb.lib().vlb3_step_count(b.h)
+            == 7)
+    c = vlb.Domain3(W.domain3(9, 9, 9), [], precision=prec).init()
+    with pytest.raises(Exception):
+        c.load(ck)
+    for dom in (a, b, c):
+        dom.close()
