@@ -131,9 +131,11 @@ __device__ __forceinline__ double near_copy(double Xp, double node, double L,
 
 // Integer ownership: the point of cell (i, j) nearest to the centre lies
 // strictly inside the circle.  Evaluated without fused multiply-adds so the
-// decision is the same on every IEEE machine.
-__device__ __noinline__ bool owns_cell(double X, double Y, double R, int i,
-                                       int j) {
+// decision is the same on every IEEE machine.  The _in forms are inlined
+// (the step kernel of one domain, list form); the out-of-line ones keep the
+// register count of the other callers down.  Both do the same operations.
+__device__ __forceinline__ bool owns_cell_in(double X, double Y, double R,
+                                             int i, int j) {
 #pragma clang fp contract(off)
   double lo = (double)i, hi = (double)(i + 1);
   double nx_ = X < lo ? lo : (X > hi ? hi : X);
@@ -148,14 +150,24 @@ __device__ __noinline__ bool owns_cell(double X, double Y, double R, int i,
 }
 
 // The cell lies in the closed disk: its corner farthest from the centre does.
-__device__ __noinline__ bool cell_within(double X, double Y, double R, int i,
-                                         int j) {
+__device__ __forceinline__ bool cell_within_in(double X, double Y, double R,
+                                               int i, int j) {
 #pragma clang fp contract(off)
   double ex = (X < (double)i + 0.5) ? (double)(i + 1) - X : X - (double)i;
   double ey = (Y < (double)j + 0.5) ? (double)(j + 1) - Y : Y - (double)j;
   double q = ex * ex;
   q = q + ey * ey;
   return q <= R * R;
+}
+
+__device__ __noinline__ bool owns_cell(double X, double Y, double R, int i,
+                                       int j) {
+  return owns_cell_in(X, Y, R, i, j);
+}
+
+__device__ __noinline__ bool cell_within(double X, double Y, double R, int i,
+                                         int j) {
+  return cell_within_in(X, Y, R, i, j);
 }
 
 // Signed area of (disk of radius R at the origin) intersected with the
@@ -397,6 +409,21 @@ __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_partner<0x140>(v);   // row_mirror
   return (lane_value(v, 0) + lane_value(v, 16)) +
          (lane_value(v, 32) + lane_value(v, 48));
+}
+
+// The same sum, complete in lane 63 only (the other lanes hold partial
+// sums): after the row sums, row_bcast:15 adds row r - 1's into rows 1 and
+// 3, then row_bcast:31 adds row 1's into row 3, so lane 63 holds
+// (r3 + r2) + (r1 + r0) -- wave_sum's bits, as a + b and b + a are the
+// same -- with two DPP steps in place of eight lane reads.
+__device__ __forceinline__ double wave_sum_last(double v) {
+  v += dpp_partner<0xB1>(v);
+  v += dpp_partner<0x4E>(v);
+  v += dpp_partner<0x141>(v);
+  v += dpp_partner<0x140>(v);
+  v += __builtin_amdgcn_update_dpp(0.0, v, 0x142, 0xA, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0.0, v, 0x143, 0xC, 0xF, false);
+  return v;
 }
 
 __device__ __forceinline__ double wave_min(double v) {
@@ -1651,7 +1678,7 @@ __device__ __forceinline__ unsigned long long wave_particle_mask(
 // (a batch) they test them, one particle per lane.  List form: each tile
 // in the role its block count gives.
 template <int PREC, bool OUT, bool SCAN, bool COUNTED = false,
-          bool ELL = false, bool NT = false>
+          bool ELL = false, bool NT = false, bool INL = false>
 __device__ __forceinline__ void step_task(
     const Params& P, const Hot<typename Prec<PREC>::C>& H, const StepBufs& B,
     int have, int tile, bool ptile, TileShared<typename Prec<PREC>::C>& sh,
@@ -1710,10 +1737,12 @@ __device__ __forceinline__ void step_task(
       const double X = near_copy(sh.bp.X[k], xn, (double)P.nx, P.perx);
       const double Y = near_copy(sh.bp.Y[k], yn, (double)P.ny, P.pery);
       const double R = sh.bp.R[k];
-      if (!owns_cell(X, Y, R, cx, cy)) continue;
+      if (!(INL ? owns_cell_in(X, Y, R, cx, cy) : owns_cell(X, Y, R, cx, cy)))
+        continue;
       if (nin < kShareCache) {
         sh.slot[nin][t] = (unsigned char)k;
-        if (cell_within(X, Y, sh.bp.Rb[k], cx, cy))
+        if (INL ? cell_within_in(X, Y, sh.bp.Rb[k], cx, cy)
+                : cell_within(X, Y, sh.bp.Rb[k], cx, cy))
           sh.share[nin][t] = (C)1;
         else
           cut |= 1u << nin;
@@ -1949,11 +1978,11 @@ __device__ __forceinline__ void step_task(
         ctz = -(rx * dpy - ry * dpx) * kk;
       }
       if (__ballot(add) != 0ull) {   // uniform in the wave
-        cfx = wave_sum(cfx);
-        cfy = wave_sum(cfy);
-        ctz = wave_sum(ctz);
+        cfx = wave_sum_last(cfx);
+        cfy = wave_sum_last(cfy);
+        ctz = wave_sum_last(ctz);
       }
-      if (lane == 0) {
+      if (lane == 63) {
         sh.red[k][wv][0] = cfx;
         sh.red[k][wv][1] = cfy;
         sh.red[k][wv][2] = ctz;

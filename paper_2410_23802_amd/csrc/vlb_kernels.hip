@@ -11,7 +11,9 @@ namespace vlb {
 // per SIMD, the occupancy of the plain update).  The 32-bit forms are held to 5
 // waves (96 VGPRs, no added spill): 4-7 % faster on the channel than the
 // unconstrained 4 waves; at 6 the particle role spills and loses it again
-// (and the LDS of a particle tile caps a CU at 7 blocks).  PAIR (16-bit
+// (and the LDS of a particle tile caps a CU at 7 blocks; on the dense
+// cavity the 16-bit forms gain 3 % from 6 waves, but their spills add a
+// quarter to the kernel's HBM writes).  PAIR (16-bit
 // forms, where the host sets pair_tiles): the streaming blocks take two
 // tiles each; a kernel of its own, so that the one-tile path keeps its code.
 // NT: the populations and the carrier are stored non-temporally (list form,
@@ -55,8 +57,8 @@ __attribute__((amdgpu_waves_per_eu(PREC == VLB_FP64 ? 4 : 5))) void k_step(
     lcnt = B.L.cnt[tile];                                // uniform
     ptile = lcnt != 0;
   }
-  step_task<PREC, OUT, SCAN, SCAN && counted_tiles(PREC, PAIR), ELL, NT>(
-      P, H, B, have, tile, ptile, sh, lcnt, lent);
+  step_task<PREC, OUT, SCAN, SCAN && counted_tiles(PREC, PAIR), ELL, NT,
+            !SCAN && !ELL>(P, H, B, have, tile, ptile, sh, lcnt, lent);
 }
 
 // -------------------------------------------------------------------------
