@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -88,6 +89,9 @@ static hipError_t clear_lists(vlb_ctx* c) {
                                   c->P.nblocks * sizeof(int), c->stream);
     if (e == hipSuccess)
       e = hipMemsetAsync(c->tcount[k], 0, c->P.nblocks * sizeof(int),
+                         c->stream);
+    if (e == hipSuccess)
+      e = hipMemsetAsync(c->bin_cnt[k], 0, c->P.nblocks * sizeof(int),
                          c->stream);
     if (e != hipSuccess) return e;
   }
@@ -266,6 +270,8 @@ static Lists lists(vlb_ctx* c) {
   L.clr = nullptr;
   L.ocnt = nullptr;
   L.oent = nullptr;
+  L.bcnt = L.bent = L.bclr = nullptr;
+  L.obcnt = L.obent = nullptr;
   return L;
 }
 
@@ -281,6 +287,13 @@ static Lists bin_lists(vlb_ctx* c) {
   L.clr = c->blk_cnt[stale];
   L.ocnt = c->blk_cnt[c->lpar];
   L.oent = c->blk_ent[c->lpar];
+  // the centre bins turn with them (list form only)
+  const bool bins = c->np > 0 && !c->P.scan;
+  L.bcnt = bins ? c->bin_cnt[nxt] : nullptr;
+  L.bent = bins ? c->bin_ent[nxt] : nullptr;
+  L.bclr = bins ? c->bin_cnt[stale] : nullptr;
+  L.obcnt = bins ? c->bin_cnt[c->lpar] : nullptr;
+  L.obent = bins ? c->bin_ent[c->lpar] : nullptr;
   c->lpar = nxt;
   return L;
 }
@@ -357,6 +370,10 @@ vlb_status vlb_create(const vlb_domain_desc* desc, void* hip_stream,
     ok = ok && dalloc(c, (void**)&c->blk_cnt[k], c->P.nblocks * sizeof(int));
     ok = ok && dalloc(c, (void**)&c->blk_ent[k],
                       (size_t)c->P.nblocks * kListCap * sizeof(int2));
+    // centre bins: never more than nblocks (bins at least 16 cells wide)
+    ok = ok && dalloc(c, (void**)&c->bin_cnt[k], c->P.nblocks * sizeof(int));
+    ok = ok && dalloc(c, (void**)&c->bin_ent[k],
+                      (size_t)c->P.nblocks * kBinCap * sizeof(int));
   }
   ok = ok && dalloc(c, (void**)&c->flags, 4 * sizeof(int));
   if (ok && hipHostMalloc((void**)&c->flags_host, 4 * sizeof(int),
@@ -404,6 +421,23 @@ vlb_status vlb_set_particles(vlb_ctx* c, int32_t n,
   // band rows of a particle <= 2R + 4; each row touches <= 4 blocks
   c->maxb = 4 * (2 * (int)ceil(rmax) + 5);
   c->P.rmax = rmax;
+  // centre bins of the repulsion's search: at least 2 rmax + zeta + 2 cells
+  // wide (two particles within reach then lie in neighbouring bins) and at
+  // least 16, and no more bins than lattice blocks (their buffers' size);
+  // equal widths that tile each axis
+  {
+    const double wmin = fmax(2.0 * rmax + fmax(c->P.coll_range, 0.0) + 2.0, 16.0);
+    c->P.nbx = std::max(1, (int)floor(c->d.nx / wmin));
+    c->P.nby = std::max(1, (int)floor(c->d.ny / wmin));
+    // a thin domain (one side under 16 cells) could still hold more
+    while ((int64_t)c->P.nbx * c->P.nby > c->P.nblocks) {
+      if (c->P.nbx >= c->P.nby) --c->P.nbx;
+      else --c->P.nby;
+    }
+    c->P.nbins = c->P.nbx * c->P.nby;
+    c->P.binw_x = (double)c->d.nx / c->P.nbx;
+    c->P.binw_y = (double)c->d.ny / c->P.nby;
+  }
   c->P.np = n;
   c->P.maxb = c->maxb;
   // scan form for few particles: partials [particle][tile] must stay small
@@ -937,6 +971,8 @@ void vlb_destroy(vlb_ctx* c) {
     if (c->tcount[k]) (void)hipFree(c->tcount[k]);
     if (c->blk_cnt[k]) (void)hipFree(c->blk_cnt[k]);
     if (c->blk_ent[k]) (void)hipFree(c->blk_ent[k]);
+    if (c->bin_cnt[k]) (void)hipFree(c->bin_cnt[k]);
+    if (c->bin_ent[k]) (void)hipFree(c->bin_ent[k]);
   }
   if (c->flags) (void)hipFree(c->flags);
   if (c->flags_host) (void)hipHostFree(c->flags_host);

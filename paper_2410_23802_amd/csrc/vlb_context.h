@@ -23,6 +23,10 @@ struct vlb_ctx {
   // fills, and the stale ones it clears
   int* blk_cnt[3] = {nullptr, nullptr, nullptr};
   int2* blk_ent[3] = {nullptr, nullptr, nullptr};
+  // list form: centre bins of the particles (the repulsion's search), in
+  // the same turn as the block lists
+  int* bin_cnt[3] = {nullptr, nullptr, nullptr};
+  int* bin_ent[3] = {nullptr, nullptr, nullptr};
   int lpar = 0;                          // [lpar]: the current lists
   // scan form: particles reaching each tile, three in turn (the next
   // step's, the one after, a stale one being cleared)

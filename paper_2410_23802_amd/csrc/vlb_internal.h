@@ -11,6 +11,7 @@ namespace vlb {
 
 constexpr int kBlock = 256;       // cells per lattice block (one per thread)
 constexpr int kListCap = 32;      // particle entries per block list
+constexpr int kBinCap = 8;        // particle entries per centre bin
 constexpr int kMaxRadius = 28;    // band rows of one particle fit one wave
 constexpr int kRedVals = 3;       // Fx, Fy, Tz per partial slot
 constexpr int kScanMax = 64;      // scan form up to this many particles
@@ -48,6 +49,11 @@ struct Params {
   double rho_f, grav_x, grav_y;
   double rmax;        // largest particle radius
   double coll_range, coll_pp, coll_pw;
+  // list form: the grid of centre bins the repulsion searches (bins at
+  // least 2 rmax + coll_range + 2 wide, so that two particles within reach
+  // lie in neighbouring bins; never more bins than lattice blocks)
+  int nbx, nby, nbins;
+  double binw_x, binw_y;
   int wall_face[4];   // 1 where the face is a wall (collisions)
   int np, maxb;
   int scan;           // 1: scan form (few particles, one launch per step)
@@ -134,7 +140,25 @@ struct Lists {
   // positions' band boxes), for the neighbour search of the repulsion
   const int* ocnt;
   const int2* oent;
+  // list form, a binning pass: the centre bins of the positions it writes
+  // (filled), the stale ones (cleared) and those of the positions it starts
+  // from (read by the repulsion), or null
+  int* bcnt;     // [nbins]
+  int* bent;     // [nbins][kBinCap] particle ids
+  int* bclr;     // [nbins]
+  const int* obcnt;
+  const int* obent;
 };
+
+// The centre bin of a particle at (X, Y): the same arithmetic where the bins
+// are filled and where they are searched.
+__host__ __device__ inline void centre_bin(const Params& P, double X,
+                                           double Y, int& bx, int& by) {
+  // clamped to the grid (a NaN goes to bin 0)
+  const double fx = floor(X / P.binw_x), fy = floor(Y / P.binw_y);
+  bx = fx > 0.0 ? (fx < (double)P.nbx ? (int)fx : P.nbx - 1) : 0;
+  by = fy > 0.0 ? (fy < (double)P.nby ? (int)fy : P.nby - 1) : 0;
+}
 
 // The buffers one lattice step of one domain reads and writes (device
 // pointers; the population and carrier pointers are in the storage type of

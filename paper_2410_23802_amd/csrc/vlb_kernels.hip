@@ -215,6 +215,11 @@ __global__ __launch_bounds__(256) void k_particles(
          k += gridDim.x * blockDim.x)
       L.clr[k] = 0;
   }
+  if (L.bclr) {  // and the previous step's centre-bin counts
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < P.nbins;
+         k += gridDim.x * blockDim.x)
+      L.bclr[k] = 0;
+  }
   const int lane = threadIdx.x & 63;
   const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
   const bool mine = p < P.np;          // uniform in the wave
@@ -242,15 +247,18 @@ __global__ __launch_bounds__(256) void k_particles(
   }
 
   // Repulsion of the update.  The candidates of particle p are the
-  // particles listed in the tiles of the box of half-width R_p + rmax +
-  // zeta around its centre, in the lists of the positions the pass starts
-  // from: a particle within reach (d < R_p + R_q + zeta) has its centre
-  // cell in that box, and a particle's band box holds its centre cell.  The
-  // wave marks them in a bitmap, gathers their positions into LDS, and
-  // each lane then visits its own (q = lane, lane + 64, ...) in ascending
-  // order, as a loop over all particles q = lane, lane + 64, ... would --
-  // the others are out of reach and add nothing, so the sums are those of
-  // that all-pairs loop.
+  // particles whose centres lie in the 3 x 3 centre bins around p's, as the
+  // previous pass filled them at the positions this pass starts from (a bin
+  // is at least 2 rmax + zeta + 2 cells wide, so a particle within reach,
+  // d < R_p + R_q + zeta, lies there); where one of those bins overflowed,
+  // the particles listed in the tiles of the box of half-width R_p + rmax +
+  // zeta around its centre (a particle within reach has its centre cell in
+  // that box, and a particle's band box holds its centre cell).  The wave
+  // marks them in a bitmap, gathers their positions into LDS, and each lane
+  // then visits its own (q = lane, lane + 64, ...) in ascending order, as a
+  // loop over all particles q = lane, lane + 64, ... would -- the others
+  // are out of reach and add nothing, so the sums are those of that
+  // all-pairs loop.
   // Without those lists (or with more particles than the bitmap holds)
   // the block stages all particles in LDS, kStage at a time.
   double cx = 0.0, cy = 0.0;
@@ -267,7 +275,37 @@ __global__ __launch_bounds__(256) void k_particles(
       const int w = threadIdx.x >> 6, nwords = (P.np + 63) >> 6;
       for (int k = lane; k < nwords; k += 64) marks[w][k] = 0ull;
       __syncthreads();
-      if (mine) {
+      // the candidates: the particles whose centres lie in the 3 x 3 centre
+      // bins around p's (a bin is wider than any reach, so a particle within
+      // reach lies there), one bin per lane; where a bin overflowed, those
+      // listed in the tiles of the box below
+      bool binned = false;
+      if (mine && L.obcnt) {
+        int bx, by, b = -1, n = 0, q[kBinCap];
+        centre_bin(P, Xp, Yp, bx, by);
+        if (lane < 9) {
+          int ix = bx + lane % 3 - 1, iy = by + lane / 3 - 1;
+          if (P.perx) ix = (ix + P.nbx) % P.nbx;
+          if (P.pery) iy = (iy + P.nby) % P.nby;
+          if (ix >= 0 && ix < P.nbx && iy >= 0 && iy < P.nby)
+            b = iy * P.nbx + ix;
+        }
+        if (b >= 0) {
+          // the count and every entry issued together (entries past the
+          // count are stale and left out below)
+          n = L.obcnt[b];
+#pragma unroll
+          for (int e = 0; e < kBinCap; ++e)
+            q[e] = L.obent[(size_t)b * kBinCap + e];
+        }
+        binned = __ballot(n > kBinCap) == 0ull;   // uniform in the wave
+        if (binned) {
+#pragma unroll
+          for (int e = 0; e < kBinCap; ++e)
+            if (e < n) atomicOr(&marks[w][q[e] >> 6], 1ull << (q[e] & 63));
+        }
+      }
+      if (mine && !binned) {
         int i0, i1, j0, j1;
         band_box(P, Xp, Yp, Rp + P.rmax + P.coll_range, i0, i1, j0, j1);
         ColSegs cs;
@@ -414,6 +452,14 @@ __global__ __launch_bounds__(256) void k_particles(
   const double R = own.R;
   const bool ok = centre_ok(P, nX, nY);
   if (!ok && lane == 0) atomicOr(flags, kFlagUnstable);
+  // ---- the centre bin of the new position (list form)
+  if (L.bcnt && ok && lane == 0) {
+    int bx, by;
+    centre_bin(P, nX, nY, bx, by);
+    const int b = by * P.nbx + bx;
+    const int pos = atomicAdd(&L.bcnt[b], 1);
+    if (pos < kBinCap) L.bent[(size_t)b * kBinCap + pos] = p;
+  }
   int i0 = 0, i1 = -1, j0 = 0, j1 = -1;
   if (ok) band_box(P, nX, nY, R, i0, i1, j0, j1);
   const int rows = j1 - j0 + 1;

@@ -246,6 +246,38 @@ def test_particle_pass_neighbour_search_2100_particles_fp64(vlb, oracle_mod):
     check(e, 6, twin=twin_errors(oracle_mod, d, ps, 6, o, pkeys=keys))
 
 
+def test_particle_pass_centre_bins_overflow_fp64(vlb, oracle_mod):
+    """620 disks of radius 1.5 packed into the lower half of 64 x 600
+    cells: the repulsion's centre bins (16 x 16.2 cells here) hold up to 11
+    centres, more than a bin keeps (8), so the particles next to a full bin
+    take their candidates from the tile lists and the others from the bins;
+    against the oracle."""
+    nx, ny, R = 64, 600, 1.5
+    rng = np.random.default_rng(21)
+    d = W.walls(W.domain(nx, ny, tau_f=0.7, lambda_f=0.05, R_lambda=3.0,
+                         R_cv=1.5, gravity=(0.0, -4e-5), beta=0.1,
+                         init_T=1.0, coll_range=2.0, coll_stiff_pp=2e-3,
+                         coll_stiff_pw=4e-3), thermal="adiabatic")
+    pts = W.rsa_disks(620, R, (0.0, 0.0, float(nx), 300.0), 1.0, seed=21)
+    assert max(len(v) for v in _tile_lists(pts, R, nx, ny).values()) <= 32
+    # the bin grid the library derives: width max(2 R + zeta + 2, 16)
+    nbx, nby = nx // 16, ny // 16
+    occ = {}
+    for x, y in pts:
+        k = (int(x // (nx / nbx)), int(y // (ny / nby)))
+        occ[k] = occ.get(k, 0) + 1
+    assert max(occ.values()) > 8 and min(occ.values()) <= 8
+    ps = [W.particle(x, y, R, rho_s=rng.uniform(1.2, 2.0), T_init=0.3,
+                     ux=rng.uniform(-0.01, 0.01), uy=rng.uniform(-0.01, 0.01))
+          for x, y in pts]
+    say("case: 620 particles in full centre bins, list form fp64 6 steps")
+    g, o = run_pair(vlb, oracle_mod, d, ps, 6)
+    e = field_errors(g, o)
+    keys = ("x", "y", "ux", "uy", "omega", "Fx", "Fy", "Tz")
+    e.update(particle_errors(g, o, keys))
+    check(e, 6, twin=twin_errors(oracle_mod, d, ps, 6, o, pkeys=keys))
+
+
 def _box_tiles(x, y, h, nx, ny):
     """The 256-cell tiles that the box of half-width h around (x, y) meets,
     on walled axes: cells floor(x - h) - 1 .. floor(x + h) + 1 clipped to
