@@ -278,6 +278,45 @@ def test_particle_pass_centre_bins_overflow_fp64(vlb, oracle_mod):
     check(e, 6, twin=twin_errors(oracle_mod, d, ps, 6, o, pkeys=keys))
 
 
+@pytest.mark.parametrize("nx,ny,n,rmin,rmax", [(160, 128, 90, 3.0, 5.0),
+                                               (40, 300, 200, 2.0, 2.0)])
+def test_particle_pass_periodic_seam_list_form_fp64(vlb, oracle_mod, nx, ny,
+                                                     n, rmin, rmax):
+    """More disks than the scan form takes in a box periodic in x, walls in
+    y, laid out so that disks touch across the seam: the repulsion's
+    candidates across the periodic axis (its centre bins wrap; on 40 cells
+    there are only two bins across, so the wrap meets one bin twice);
+    against the oracle."""
+    rng = np.random.default_rng(31)
+    d = W.walls(W.domain(nx, ny, tau_f=0.65, lambda_f=0.05, R_lambda=4.0,
+                         R_cv=1.5, gravity=(0.0, -4e-5), beta=0.2,
+                         init_T=1.0, coll_range=2.0, coll_stiff_pp=2e-3,
+                         coll_stiff_pw=4e-3), which=(W.YLO, W.YHI),
+                thermal="adiabatic")
+    pts = W.rsa_disks(n, rmax, (0.0, 0.0, float(nx), float(ny)), 1.0,
+                      seed=31)
+    # shift by half the width: pairs that were neighbours in the middle now
+    # meet across the seam (gaps are unchanged, so nothing overlaps)
+    pts = [((x + nx / 2) % nx, y) for x, y in pts]
+    # pairs within reach (R_p + R_q + zeta <= 2 rmax + 2) across the seam
+    P = np.array(pts)
+    ddx = np.abs(P[:, None, 0] - P[None, :, 0])
+    near = np.hypot(np.minimum(ddx, nx - ddx), P[:, None, 1] - P[None, :, 1])
+    np.fill_diagonal(near, np.inf)
+    assert ((near < 2 * rmax + 2) & (ddx > nx / 2)).any()
+    ps = [W.particle(x, y, rng.uniform(rmin, rmax),
+                     rho_s=rng.uniform(1.2, 2.0), T_init=0.2,
+                     ux=rng.uniform(-0.01, 0.01), uy=rng.uniform(-0.01, 0.01))
+          for x, y in pts]
+    say(f"case: {n} particles across a periodic seam ({nx} x {ny}), list "
+        f"form fp64 60 steps")
+    g, o = run_pair(vlb, oracle_mod, d, ps, 60)
+    e = field_errors(g, o)
+    keys = ("x", "y", "ux", "uy", "omega", "Fx", "Fy", "Tz")
+    e.update(particle_errors(g, o, keys))
+    check(e, 60, twin=twin_errors(oracle_mod, d, ps, 60, o, pkeys=keys))
+
+
 def _box_tiles(x, y, h, nx, ny):
     """The 256-cell tiles that the box of half-width h around (x, y) meets,
     on walled axes: cells floor(x - h) - 1 .. floor(x + h) + 1 clipped to
