@@ -147,7 +147,6 @@ constexpr int kStage = 1024;
 union PassShared {
   struct {
     unsigned long long marks[4][kWords];
-    int wbase[4][kWords];
     int cq[4][kCand];
     double X[4][kCand], Y[4][kCand], R[4][kCand];
   } nb;
@@ -267,7 +266,6 @@ __global__ __launch_bounds__(256) void k_particles(
     const double Xp = own.X, Yp = own.Y, Rp = own.R;
     if (L.ocnt && P.np <= 64 * kWords) {
       auto& marks = psh.nb.marks;
-      auto& wbase = psh.nb.wbase;
       auto& cq = psh.nb.cq;
       auto& cX = psh.nb.X;
       auto& cY = psh.nb.Y;
@@ -332,35 +330,34 @@ __global__ __launch_bounds__(256) void k_particles(
       __syncthreads();
       if (mine) {
         // the marked particles but p, ascending: the m of them are
-        // gathered kCand at a time; word k's come after wbase[k] others.
-        // Lane l's own (q mod 64 = l) are bit l of the words, the words
-        // holding one listed in col0 (0..63) and col1 (64..127).
-        if (lane == 0) marks[w][p >> 6] &= ~(1ull << (p & 63));
-        wave_lds_sync();
+        // gathered kCand at a time.  Word k of the bitmap (k < nwords <=
+        // 128) is held by lane k mod 64 (wd[k / 64]), with the count of
+        // marked particles in the words before it (wb); lane l's own
+        // particles (q mod 64 = l) are bit l of the words, visited over the
+        // nonzero words in ascending order.
+        unsigned long long wd[2];
+        int wb[2];
         int m = 0;
-        for (int k0 = 0; k0 < nwords; k0 += 64) {
-          const int k = k0 + lane;
-          const unsigned long long bits = k < nwords ? marks[w][k] : 0ull;
-          const int c = __popcll(bits);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k = lane + 64 * h;
+          unsigned long long bits = k < nwords ? marks[w][k] : 0ull;
+          if (k == (p >> 6)) bits &= ~(1ull << (p & 63));
+          wd[h] = bits;
           int ctotal;
-          const int b = m + wave_excl_scan<7>(c, lane, ctotal);
-          if (k < nwords) wbase[w][k] = b;
+          wb[h] = m + wave_excl_scan<7>(__popcll(bits), lane, ctotal);
           m += ctotal;
         }
-        unsigned long long col0 = 0ull, col1 = 0ull;
-        for (int k = 0; k < nwords; ++k) {
-          if ((marks[w][k] >> lane) & 1ull) {
-            if (k < 64) col0 |= 1ull << k;
-            else col1 |= 1ull << (k - 64);
-          }
-        }
-        wave_lds_sync();
+        const unsigned long long nz[2] = {__ballot(wd[0] != 0ull),
+                                          __ballot(wd[1] != 0ull)};
         const unsigned long long below = (1ull << lane) - 1ull;
         for (int c0 = 0; c0 < m; c0 += kCand) {
           const int mc = min(kCand, m - c0);
-          for (int k = lane; k < nwords; k += 64) {
-            unsigned long long bits = marks[w][k];
-            for (int pos = wbase[w][k]; bits && pos < c0 + kCand;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int k = lane + 64 * h;
+            unsigned long long bits = wd[h];
+            for (int pos = wb[h]; bits && pos < c0 + kCand;
                  bits &= bits - 1ull, ++pos)
               if (pos >= c0)
                 cq[w][pos - c0] = k * 64 + __ffsll((long long)bits) - 1;
@@ -373,15 +370,26 @@ __global__ __launch_bounds__(256) void k_particles(
             cR[w][i] = pc.R[q];
           }
           wave_lds_sync();
-          while (col0 | col1) {
-            const int k = col0 ? __ffsll((long long)col0) - 1
-                               : 64 + __ffsll((long long)col1) - 1;
-            const int i = wbase[w][k] + __popcll(marks[w][k] & below) - c0;
-            if (i >= kCand) break;                 // a later chunk's
-            repulsion_pair(P, Xp, Yp, Rp, cX[w][i], cY[w][i], cR[w][i], cx,
-                           cy);
-            if (col0) col0 &= col0 - 1ull;
-            else col1 &= col1 - 1ull;
+          // this chunk's candidates of lane l, ascending: q = 64 k + l over
+          // the words k holding bit l
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            for (unsigned long long z = nz[h]; z; z &= z - 1ull) {
+              const int kl = __ffsll((long long)z) - 1;   // uniform
+              const unsigned lo = (unsigned)__builtin_amdgcn_readlane(
+                  (int)(unsigned)wd[h], kl);
+              const unsigned hi = (unsigned)__builtin_amdgcn_readlane(
+                  (int)(unsigned)(wd[h] >> 32), kl);
+              const unsigned long long wk =
+                  ((unsigned long long)hi << 32) | lo;
+              const int bk = __builtin_amdgcn_readlane(wb[h], kl);
+              if ((wk >> lane) & 1ull) {
+                const int i = bk + __popcll(wk & below) - c0;
+                if (i >= 0 && i < kCand)
+                  repulsion_pair(P, Xp, Yp, Rp, cX[w][i], cY[w][i],
+                                 cR[w][i], cx, cy);
+              }
+            }
           }
           wave_lds_sync();
         }
