@@ -271,8 +271,10 @@ __global__ __launch_bounds__(256) void k_particles(
       auto& cY = psh.nb.Y;
       auto& cR = psh.nb.R;
       const int w = threadIdx.x >> 6, nwords = (P.np + 63) >> 6;
+      // each wave works on its own slice of the LDS (its bitmap and
+      // candidates), so wave-level ordering is enough: no block barrier
       for (int k = lane; k < nwords; k += 64) marks[w][k] = 0ull;
-      __syncthreads();
+      wave_lds_sync();
       // the candidates: the particles whose centres lie in the 3 x 3 centre
       // bins around p's (a bin is wider than any reach, so a particle within
       // reach lies there), one bin per lane; where a bin overflowed, those
@@ -327,7 +329,7 @@ __global__ __launch_bounds__(256) void k_particles(
           mark_listed(L, f0, n0, f1, n1, marks[w]);
         }
       }
-      __syncthreads();
+      wave_lds_sync();
       if (mine) {
         // the marked particles but p, ascending: the m of them are
         // gathered kCand at a time.  Word k of the bitmap (k < nwords <=
