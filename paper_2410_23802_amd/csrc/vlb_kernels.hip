@@ -462,13 +462,15 @@ __global__ __launch_bounds__(256) void k_particles(
   const double R = own.R;
   const bool ok = centre_ok(P, nX, nY);
   if (!ok && lane == 0) atomicOr(flags, kFlagUnstable);
-  // ---- the centre bin of the new position (list form)
+  // ---- the centre bin of the new position (list form): its place is taken
+  // now and its entry written after the block lists' adds are issued, so
+  // that the two round trips overlap
+  int bpos = kBinCap, bidx = 0;
   if (L.bcnt && ok && lane == 0) {
     int bx, by;
     centre_bin(P, nX, nY, bx, by);
-    const int b = by * P.nbx + bx;
-    const int pos = atomicAdd(&L.bcnt[b], 1);
-    if (pos < kBinCap) L.bent[(size_t)b * kBinCap + pos] = p;
+    bidx = by * P.nbx + bx;
+    bpos = atomicAdd(&L.bcnt[bidx], 1);
   }
   int i0 = 0, i1 = -1, j0 = 0, j1 = -1;
   if (ok) band_box(P, nX, nY, R, i0, i1, j0, j1);
@@ -506,6 +508,7 @@ __global__ __launch_bounds__(256) void k_particles(
   if (lane == 0) {
     PState& dst = (mode == kModeBinOnly) ? cur : next;
     dst.nslot[p] = total;
+    if (bpos < kBinCap) L.bent[(size_t)bidx * kBinCap + bpos] = p;
   }
 }
 
