@@ -51,8 +51,9 @@ wall (1000, 2000: x* = 2.91 and 2.74, other methods 2.76-2.91 and
 with a large amplitude (4500: 1.27).  Here: 100, 564, 1000, 2000 and 2500
 give the first four regimes (x* = 2.84 and 2.85 near the wall), but at
 4500 the oscillation dies out (half-range 0.016), a failing replay kept as
-a strict expected failure; the large-amplitude regime appears at Gr = 6000
-instead (half-range 1.12 over the last 40 % of the run).  Other readings of
+a strict expected failure; the large-amplitude regime sets in between Gr =
+4500 and 5000 instead (half-range 1.30 at 5000 and 1.32 at 5500; at 4500 a
+run to t* = 400 stays on the centre line).  Other readings of
 the unstated rules were run on the GPU (Gr = 1000 / 2000 / 4500 / 6000):
 every touched cell held fully gives x* = 2.78 / 2.80 and half-range 0.015 /
 1.37; the cells whose node lies inside held fully, 2.78 / 2.87 and 0.024 /
