@@ -381,7 +381,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is not part of this build",
+              "the library steps one domain per GPU and has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 
