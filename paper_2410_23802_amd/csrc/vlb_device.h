@@ -102,16 +102,16 @@ struct Prec<VLB_BF16_SHIFT> {
   static __device__ __forceinline__ C ld(const S* p, size_t i) {
     return cv(p[i]);
   }
+  // round to nearest even on the upper 16 bits (gfx950 converts in one
+  // instruction, the same bits for every finite value)
+  static __device__ __forceinline__ S rne(C v) {
+    return __builtin_bit_cast(uint16_t, (__bf16)v);
+  }
   static __device__ __forceinline__ void st(S* p, size_t i, C v) {
-    // round to nearest even on the upper 16 bits
-    uint32_t b = __float_as_uint(v);
-    b += 0x7fffu + ((b >> 16) & 1u);
-    p[i] = (uint16_t)(b >> 16);
+    p[i] = rne(v);
   }
   static __device__ __forceinline__ void stn(S* p, size_t i, C v) {
-    uint32_t b = __float_as_uint(v);
-    b += 0x7fffu + ((b >> 16) & 1u);
-    __builtin_nontemporal_store((uint16_t)(b >> 16), p + i);
+    __builtin_nontemporal_store(rne(v), p + i);
   }
 };
 
